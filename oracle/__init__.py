@@ -46,6 +46,8 @@ ALPHA_MIN = 1.0 / 255.0
 ALPHA_MAX = 0.99
 T_MIN = 1e-4
 DET_MIN = 1e-12          # Sec. 5.2: V1 determinant below 1e-12 -> unsolvable
+ISO_MIN = 1e-4           # near-singular V1 (Sec. 4.3.5), scale-invariant reading:
+                         # covered pixels (nearly) on one line
 WSUM_MIN = 1e-3          # Sec. 5.2: accumulated alpha below 1e-3 -> unsolvable
 PIX_MIN = 2              # Sec. 5.2: fewer than 2 pixels -> unsolvable
 VIEWS_MIN = 2            # Sec. 5.2: visible in fewer than 2 views
@@ -223,6 +225,17 @@ def solve_views(mom, mu_c, cov, rendered):
     flags |= np.where(mom[..., S_N] < PIX_MIN, VF_FEW_PIX, 0).astype(np.uint8)
     flags |= np.where(mom[..., S_W] < WSUM_MIN, VF_LOW_ALPHA, 0).astype(np.uint8)
     flags |= np.where(~(det >= DET_MIN), VF_SINGULAR, 0).astype(np.uint8)
+    # weighted covariance C of the pixel offsets u; near-singular when
+    # 4 det(C) / tr(C)^2 < ISO_MIN (its eigenvalues differ by ~1/ISO_MIN)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sw = mom[..., S_W]
+        mx, my = mom[..., S_UX] / sw, mom[..., S_UY] / sw
+        ca = mom[..., S_UXUX] / sw - mx * mx
+        cb = mom[..., S_UXUY] / sw - mx * my
+        cc = mom[..., S_UYUY] / sw - my * my
+        tr = ca + cc
+        iso_ok = (tr > 0) & (4.0 * (ca * cc - cb * cb) >= ISO_MIN * tr * tr)
+    flags |= np.where(~iso_ok, VF_SINGULAR, 0).astype(np.uint8)
     ok = flags == 0
     flags[ok] = VF_OK
     theta = np.zeros((V, N, 3, 2))

@@ -464,6 +464,25 @@ def test_thresholds_of_sec_5_2():
     assert out["flags"][0, 1] & oracle.VF_FEW_PIX
     assert out["flags"][0, 2] & oracle.VF_SINGULAR
     assert out["flags"][0, 3] == oracle.VF_OK
+    # near-singular V1 independently of scale: pixels on one line (a single
+    # column) make V1 exactly singular, however many pixels there are
+    xs = np.zeros(9)
+    ys = np.arange(9.0) - 4.0
+    w = np.linspace(0.2, 0.6, 9)
+    rec = np.zeros((1, 1, 16))
+    rec[0, 0, oracle.S_W] = w.sum()
+    rec[0, 0, oracle.S_UX], rec[0, 0, oracle.S_UY] = (w * xs).sum(), (w * ys).sum()
+    rec[0, 0, oracle.S_UXUX], rec[0, 0, oracle.S_UXUY] = (w * xs * xs).sum(), (w * xs * ys).sum()
+    rec[0, 0, oracle.S_UYUY] = (w * ys * ys).sum()
+    rec[0, 0, oracle.S_N] = 9
+    line = rec.copy()
+    line[0, 0, oracle.S_UXUX] += 1e-7 * line[0, 0, oracle.S_UYUY]   # FP32-sized residue
+    out = oracle.solve_views(line, np.zeros((1, 1, 2)), np.zeros((1, 1, 3)), np.ones((1, 1), np.uint8))
+    assert out["flags"][0, 0] & oracle.VF_SINGULAR
+    strip = rec.copy()
+    strip[0, 0, oracle.S_UXUX] = 0.25 * strip[0, 0, oracle.S_W]       # two columns +-0.5 px
+    out = oracle.solve_views(strip, np.zeros((1, 1, 2)), np.zeros((1, 1, 3)), np.ones((1, 1), np.uint8))
+    assert out["flags"][0, 0] == oracle.VF_OK
 
 
 # ----------------------------------------------------------------- P10: exact recovery end to end
