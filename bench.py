@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark: Gaussians/s motion-transferred on one MI355X.
+
+One step = one cold frame of the whole hot path on one batch of synthetic
+input already resident in HBM:
+    tg_preprocess -> tg_bin_sort -> (zero accumulators) -> tg_splat_accumulate
+    -> tg_solve_views -> tg_triangulate
+for 1M Gaussians x 20 views x 1920x1080 (the paper-shaped "large" workload:
+large motions, 5% uniform outlier tracks, Bernoulli(0.9) track visibility).
+
+Prints ONE JSON line (rank 0).  Besides the contract fields it carries
+`roofline` (the dominant kernel, tg_splat_accumulate, against the VALU peak,
+timed with HIP events on the stream it runs on) and `cpu_baseline` (the CPU
+oracle on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gaussians/s motion-transferred (1M G, 20 views, 1080p); frames/s + p99 latency"
+# MI355X: 256 CUs x 64 FP32 lanes x 2.4 GHz (non-packed VALU lane-ops/s)
+VALU_PEAK = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12
+# algorithmic VALU lane-ops: per evaluated (pixel, Gaussian) pair -- offset (2),
+# quadratic form (5), exp (4, quarter rate), opacity and clamp (2), the two
+# threshold tests (2), transmittance test (1) -- and per contributing pair --
+# weight (2), transmittance update (2), 13 moment multiply-adds, 2 static
+# counters, count (5 more products) -- see the design notes
+OPS_PER_EVAL = 16
+OPS_PER_CONTRIB = 24
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, sample_views=2):
+    """The oracle on a bounded sample: `sample_views` of the views, all
+    pixels, all Gaussians, through solve and triangulation; extrapolated
+    linearly in the number of views."""
+    import numpy as np
+
+    import oracle
+    import synth
+    V = len(wl.cams)
+    cams = wl.cams[:sample_views]
+    sub = synth.Workload(name=wl.name, scene=wl.scene, cams=cams, motion=wl.motion,
+                         disp=wl.disp[:sample_views], vis=wl.vis[:sample_views])
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    r = oracle.motion_transfer(sub.scene, sub.cams, sub.disp, sub.vis)
+    t = time.perf_counter() - t0
+    t_frame = t * V / sample_views
+    n = wl.scene.n
+    return dict(value=n / t_frame, unit="Gaussians/s", cores=min(sample_views, threads), kind="oracle",
+                sample=f"{sample_views} of {V} views at full resolution with all {n} Gaussians "
+                       f"(geometry, depth-ordered tile lists, FP64 compositing, per-view solve, "
+                       f"triangulation) in {t:.1f} s, extrapolated x{V / sample_views:g} to the full frame; "
+                       f"compositing parallel over views", seconds=t)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm", action="store_true", help="also time warm frames (resident splats and bins)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU frame parallelism is described in the design "
+              "notes but not launched (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2604_02586_amd import api
+
+    dev = torch.device("cuda:0")
+    log(f"generating workload '{args.workload}'")
+    t0 = time.perf_counter()
+    wl = synth.make_workload(args.workload)
+    N, V, W, H = wl.scene.n, len(wl.cams), wl.cams[0].W, wl.cams[0].H
+    log(f"  {N} Gaussians x {V} views x {W}x{H} in {time.perf_counter() - t0:.1f} s")
+
+    g = api.GaussianTensors.from_scene(wl.scene, dev)
+    disp = torch.as_tensor(wl.disp).to(dev).contiguous()
+    vis = torch.as_tensor(wl.vis).to(dev).contiguous()
+    g_out = api.GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.quats), torch.empty_like(g.scales),
+                                g.opacity)
+    mt = api.MotionTransfer(wl.cams, N, dev)
+    # size the pair capacity once (host sync allowed outside the timed region)
+    mt.preprocess(g)
+    mt.bin_sort(check_overflow=True)
+    n_pairs = int(mt.bins.n_pairs.item())
+    log(f"  coarse pairs {n_pairs} (capacity {mt.bins.capacity})")
+    # one untimed launch with pair counters
+    mt.accumulate(disp, vis, stats=True)
+    torch.cuda.synchronize()
+    e_eval, e_contrib = (int(x) for x in mt.stats.cpu())
+    log(f"  pairs evaluated {e_eval}, contributing {e_contrib}")
+
+    stream = torch.cuda.current_stream()
+    names = ["preprocess", "bin_sort", "zero_acc", "accumulate", "solve", "triangulate"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record(stream)
+        mark(0)
+        mt.preprocess(g)
+        mark(1)
+        mt.bin_sort(check_overflow=False)
+        mark(2)
+        mt.acc.zero_()
+        mark(3)
+        api.splat_accumulate(mt.splats, mt.bins, N, mt.cams_host, disp, vis, mt.params, mt.acc)
+        mark(4)
+        mt.solve()
+        mark(5)
+        mt.triangulate(g, g_out)
+        mark(6)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert int(mt.bins.overflow.item()) == 0, "pair capacity overflow during timing"
+    ms = (t1 - t0) * 1e3 / args.steps
+    stage = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(6)] for k in range(args.steps)])
+    stage_ms = {n: float(np.mean(stage[:, i])) for i, n in enumerate(names)}
+    frame_ms = stage.sum(1)
+    acc_ms = stage_ms["accumulate"]
+    log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+    st = mt.status.cpu().numpy().view(np.uint32)
+
+    warm = None
+    if args.warm:
+        for _ in range(args.warmup):
+            mt.run_warm(g, disp, vis, g_out)
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        for _ in range(args.steps):
+            mt.run_warm(g, disp, vis, g_out)
+        torch.cuda.synchronize()
+        warm = (time.perf_counter() - tw) * 1e3 / args.steps
+
+    alg_ops = OPS_PER_EVAL * e_eval + OPS_PER_CONTRIB * e_contrib
+    achieved = alg_ops / (acc_ms * 1e-3)
+    # algorithmic bytes per frame: parameters in and out, tracks, accumulators
+    # written once and read once (13 used slots)
+    b_alg = N * 44 * 2 + V * W * H * 9 + 2 * N * V * 52
+    out = {
+        "metric": METRIC,
+        "value": N / (ms * 1e-3),
+        "unit": "Gaussians/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 solves)",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N} Gaussians x {V} views x {W}x{H}, "
+                               "tracks with 5% outliers and 0.9 visibility",
+                   "gaussians": N, "views": V, "width": W, "height": H, "parallelism": "single GPU"},
+        "frames_per_s": 1e3 / ms,
+        "latency_ms": {"p50": float(np.percentile(frame_ms, 50)), "p99": float(np.percentile(frame_ms, 99))},
+        "stages_ms": stage_ms,
+        "hbm_fraction_of_frame": b_alg / (ms * 1e-3) / HBM_PEAK,
+        "pairs": {"coarse": n_pairs, "evaluated": e_eval, "contributing": e_contrib},
+        "status": {"position_updated": float(((st & 1) > 0).mean()),
+                   "covariance_updated": float(((st & 2) > 0).mean())},
+        "roofline": {"kernel": "tg_splat_accumulate", "bound": "alu", "achieved": achieved / 1e12,
+                     "peak": VALU_PEAK / 1e12, "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK,
+                     "traffic": None, "algorithmic_ops": alg_ops, "avg_ms": acc_ms},
+    }
+    if warm is not None:
+        out["warm_ms_per_frame"] = warm
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(wl)
+        log(f"  cpu baseline {out['cpu_baseline']['value']:.3g} Gaussians/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

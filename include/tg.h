@@ -1,0 +1,279 @@
+/*
+ * tg.h -- C ABI of libtg, the MI355X (gfx950) library for TrackerSplat's
+ * tracking-to-Gaussian motion transfer and its differentiable rasteriser.
+ *
+ * Paper: "TrackerSplat: Exploiting Point Tracking for Fast and Robust Dynamic
+ * 3D Gaussians Reconstruction", SIGGRAPH Asia 2025.
+ *
+ * One frame of motion transfer is the call sequence
+ *     tg_preprocess -> tg_bin_sort -> tg_splat_accumulate
+ *                   -> tg_solve_views -> tg_triangulate
+ * and the post-relocation refinement uses
+ *     tg_preprocess -> tg_bin_sort -> tg_raster_fwd / tg_raster_bwd
+ *                   -> tg_l1_loss_grad -> tg_adam_step.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns tg_status.  Argument errors (null pointers,
+ *    negative sizes, misaligned records, too many views) are detected on the
+ *    host before anything is launched and leave all buffers untouched.
+ *  - Every call is asynchronous on the caller's HIP stream (`stream`, a
+ *    hipStream_t; NULL means the default stream).  No call synchronises the
+ *    device.  Conditions only the device can see (pair-list overflow) are
+ *    written to caller-visible device words that the caller reads after it
+ *    synchronises.
+ *  - The caller owns every buffer.  Pointers marked "device" must be device
+ *    memory (e.g. torch tensors); pointers marked "host" are read during the
+ *    call only.  The library keeps no pointer after it returns and allocates
+ *    no device memory: scratch space comes from a caller workspace whose size
+ *    is returned by a query call (ws == NULL).
+ *  - Arrays are C-contiguous, float32 unless stated; "[V,N,k]" means view
+ *    major, then Gaussian, then component.  Record arrays (rec, acc) must be
+ *    16-byte aligned.
+ *  - Calls on different streams with disjoint output buffers may run
+ *    concurrently.  No exception crosses the ABI.
+ */
+#ifndef TG_H
+#define TG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TG_ABI_VERSION 1
+#define TG_TILE 16          /* pixels per tile side (16x16 = 256 pixels)      */
+#define TG_MAX_VIEWS 32     /* views per launch; more views are chunked       */
+#define TG_ACC_STRIDE 16    /* floats per accumulator record                  */
+#define TG_REC_STRIDE 8     /* floats per splat record                        */
+
+typedef enum tg_status {
+    TG_OK = 0,
+    TG_ERR_INVALID_ARG = 1,  /* null pointer, bad size or mode               */
+    TG_ERR_ALIGNMENT = 2,    /* record array not 16-byte aligned              */
+    TG_ERR_WORKSPACE = 3,    /* workspace missing or smaller than required    */
+    TG_ERR_OVERFLOW = 4,     /* host-detected capacity problem                */
+    TG_ERR_DEVICE = 5,       /* a HIP runtime call failed                     */
+    TG_ERR_BUDGET = 6,       /* serving: request does not fit the budget      */
+    TG_ERR_UNSUPPORTED = 7   /* size outside what this build supports         */
+} tg_status;
+
+/* Pinhole camera (80 bytes).  p_cam = R x + t with R row-major world->camera;
+ * pixel = (fx p_x/p_z + cx, fy p_y/p_z + cy); pixel (row r, column c) is
+ * sampled at (c, r).  x right, y down, z forward. */
+typedef struct tg_camera {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float pad[2];
+} tg_camera;
+
+/* Method constants.  tg_default_params() fills the values used throughout:
+ * renderer constants (alpha clamp 0.99, alpha_min 1/255, T_min 1e-4,
+ * dilation 0.3 px^2, 3-sigma extent, near plane 0.2, Jacobian clamp 1.3x the
+ * half field of view) and the unsolvable thresholds of Sec. 5.2 (determinant
+ * of V1 below 1e-12, accumulated alpha below 1e-3, fewer than 2 pixels per
+ * view; fewer than 2 views, total alpha below 1e-3, fewer than 3 pixels
+ * across views).  iso_min (1e-4) makes "near-singular V1" (Sec. 4.3.5)
+ * scale-invariant: the covered pixels must not lie (nearly) on one line. */
+typedef struct tg_params {
+    float near_z;
+    float dilation;
+    float extent;
+    float j_clamp;
+    float alpha_min;
+    float alpha_max;
+    float t_min;
+    float static_px;        /* |x' - x| below this counts as static (Sec. 4.5.2) */
+    double det_min;
+    double iso_min;         /* near-singular V1: 4 det(C)/tr(C)^2 below this,
+                               C the weighted covariance of the pixel offsets  */
+    double wsum_min;
+    double wsum_total_min;
+    int32_t pix_min;
+    int32_t views_min;
+    int32_t pix_total_min;
+    int32_t coarse_shift;   /* log2 of tiles per coarse-bin side (default 3)  */
+} tg_params;
+
+/* 3D Gaussians (Sec. 3.1): mean, rotation, scale, opacity, optional SH
+ * colour.  All device pointers. */
+typedef struct tg_gaussians {
+    float* means;        /* [N,3]                                             */
+    float* quats;        /* [N,4] (w,x,y,z); need not be normalised           */
+    float* scales;       /* [N,3] linear (scale_mode 0) or log (scale_mode 1) */
+    float* opacity;      /* [N]   in (0,1) (opacity_mode 0) or logit (mode 1) */
+    float* sh;           /* [N,(d+1)^2,3] SH coefficients or NULL             */
+    int32_t sh_degree;   /* 0..3                                              */
+    int32_t scale_mode;
+    int32_t opacity_mode;
+    int32_t pad;
+} tg_gaussians;
+
+/* Per-(view, Gaussian) splats written by tg_preprocess.  All device. */
+typedef struct tg_splats {
+    float* rec;          /* [V,N,8]: mu_x, mu_y, conic a, b, c, opacity,
+                            depth, 0.  mu is the splat centre; conic is the
+                            inverse of the dilated 2D covariance.  16B aligned */
+    float* cov2d;        /* [V,N,3]: undilated Sigma_2D (a, b, c) of Eq. 1    */
+    uint16_t* rect;      /* [V,N,4]: tile rectangle tx0, ty0, tx1, ty1
+                            (half-open; all zero when culled)                 */
+    uint32_t* key;       /* [V,N]: FP32 bits of the camera-space depth, or
+                            0xFFFFFFFF when culled                            */
+    float* colors;       /* [V,N,3] view-dependent RGB or NULL                */
+    uint8_t* clamped;    /* [V,N,3] 1 where the colour was clamped at 0, or NULL */
+} tg_splats;
+
+/* Depth-ordered coarse-bin lists written by tg_bin_sort.  All device. */
+typedef struct tg_bins {
+    uint32_t* order;       /* [V,N]: Gaussian ids by (depth key, id)          */
+    uint32_t* cell_ids;    /* [capacity]: per coarse bin, the ids of the
+                              Gaussians whose tile rectangle meets the bin,
+                              in depth order                                  */
+    uint32_t* cell_ranges; /* [n_cells,2]: [start, end) into cell_ids         */
+    int64_t* n_pairs;      /* [1]: number of (bin, Gaussian) pairs            */
+    int32_t* overflow;     /* [1]: set to 1 when n_pairs > capacity           */
+    int64_t capacity;
+} tg_bins;
+
+/* ---------------------------------------------------------------------- */
+int tg_abi_version(void);
+const char* tg_status_string(tg_status s);
+void tg_default_params(tg_params* p);
+
+/* Number of coarse bins over V views for N Gaussians (host arithmetic
+ * only; the coarse size grows past p->coarse_shift when bin and rank bits
+ * would exceed 32).  -1 on invalid arguments. */
+int64_t tg_num_cells(const tg_camera* cams, int32_t V, int64_t N, const tg_params* p);
+/* Number of 16x16 tiles over V views. */
+int64_t tg_num_tiles(const tg_camera* cams, int32_t V);
+
+/*
+ * tg_preprocess -- EWA projection of every Gaussian into every view
+ * (Sec. 3.1, Eq. 1).
+ *
+ * For view v and Gaussian i: p = R_v mu + t_v; culled if p_z <= near_z;
+ * Sigma_3D = R S S^T R^T; Sigma_2D = J W Sigma_3D W^T J^T (W = R_v, J the
+ * Jacobian of the perspective map at p, its x/y ratios clamped to j_clamp
+ * times the half field of view); the dilated Sigma_2D + dilation*I gives the
+ * conic and a 3-sigma radius; the tile rectangle covers the centre +- radius.
+ * The integer-deciding quantities (centre, radius, rectangle, depth key) use
+ * FP32 in a fixed operation order; Sigma_2D and the conic are formed in FP64
+ * and rounded.  With g->sh != NULL and out->colors != NULL, colours are the
+ * degree-d SH evaluated in the viewing direction, +0.5, clamped at 0.
+ *
+ * cams: host [V] (any V >= 1; launched in chunks of TG_MAX_VIEWS).
+ * Errors: TG_ERR_INVALID_ARG for null buffers, N < 0, V < 1, bad modes;
+ *         TG_ERR_ALIGNMENT if out->rec is not 16-byte aligned.
+ */
+tg_status tg_preprocess(const tg_gaussians* g, int64_t N, const tg_camera* cams, int32_t V,
+                        const tg_params* p, tg_splats* out, void* stream);
+
+/*
+ * tg_bin_sort -- depth ordering and coarse binning of the splats
+ * (Sec. 3.1: blending follows depth order).
+ *
+ * Step 1: per view, a device LSD radix sort of the N depth keys (ties by
+ * Gaussian id) gives bins->order.  Step 2: every non-culled Gaussian emits a
+ * key (coarse bin | depth rank) for each coarse bin (2^coarse_shift tiles a
+ * side) its tile rectangle meets; a device radix sort of those keys gives,
+ * per bin, the Gaussians in depth order.  The renderer reads a tile's list as
+ * the entries of its bin whose rectangle contains the tile, which is exactly
+ * the depth-ordered per-tile list.
+ *
+ * ws/ws_bytes: workspace.  With ws == NULL the required size is written to
+ * *ws_bytes and nothing runs.  bins->capacity bounds the pair count; if the
+ * device count exceeds it, *bins->overflow is set, no list is written and the
+ * later stages of the frame do nothing (the caller re-sizes and re-runs).
+ * Errors: TG_ERR_WORKSPACE if *ws_bytes is smaller than required;
+ *         TG_ERR_UNSUPPORTED if bin and rank bits exceed 32 at every
+ *         coarse size.
+ */
+tg_status tg_bin_sort(const tg_splats* s, int64_t N, const tg_camera* cams, int32_t V,
+                      const tg_params* p, tg_bins* bins, void* ws, size_t* ws_bytes,
+                      void* stream);
+
+/*
+ * tg_splat_accumulate -- PWI-LS statistics (Sec. 4.3.3, 4.3.4 Eq. 4,
+ * Sec. 4.3.5; static-pixel counters of Sec. 4.5.2).
+ *
+ * For every pixel x of every view, in depth order: alpha = min(alpha_max,
+ * o exp(-1/2 d^T conic d)); skip when alpha < alpha_min; stop when
+ * T (1 - alpha) < t_min (that Gaussian excluded); w = alpha T.  When the
+ * pixel's track is visible, add to acc[v,i] the record
+ *   [w, w ux, w uy, w ux ux, w ux uy, w uy uy, w dx, w dy,
+ *    w ux dx, w ux dy, w uy dx, w uy dy, 1, s, s alpha, (pad)]
+ * with u = x - mu (centre of the splat), d = disp = x' - x and s = 1 when
+ * |d| < static_px.  These are the centred entries of V1 = sum w P_i and
+ * V2 = sum w Q_i (the paper's raw-coordinate V1, V2 follow by an exact
+ * change of origin).  Then T <- T (1 - alpha).
+ *
+ * disp: device [V,H,W,2] float32 (x' - x in pixels).  vis: device [V,H,W]
+ * uint8 or NULL (all visible).  All views must share one resolution.
+ * acc: device [V,N,16] float32, zeroed by the caller (results are added).
+ * t_final: device [V,H,W] or NULL: final transmittance per pixel.
+ * stats: device int64 [2] or NULL: adds (pairs evaluated, pairs
+ * contributing) over the launch.
+ */
+tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins, int64_t N,
+                              const tg_camera* cams, int32_t V, const float* disp,
+                              const uint8_t* vis, const tg_params* p, float* acc,
+                              float* t_final, int64_t* stats, void* stream);
+
+/*
+ * tg_solve_views -- per (view, Gaussian) 2D affine motion (Sec. 4.3.4 Eq. 4,
+ * Sec. 4.2 Eq. 2) in FP64.
+ *
+ * From the centred record: V1 = [[Suu, Su],[Su^T, Sw]], V2 = [[Sud],[Sd^T]],
+ * Theta = V1^{-1} V2 = [G^T; c^T]; A = I + G; mu' = mu + c (the paper's
+ * A mu + b); Sigma' = A Sigma A^T with the undilated Sigma_2D.  Flags per
+ * (view, Gaussian): 1 solved, 2 culled, 4 fewer than pix_min pixels,
+ * 8 accumulated alpha below wsum_min, 16 near-singular V1: det V1 below
+ * det_min, or 4 det(C)/tr(C)^2 below iso_min with C = Suu/Sw - (Su/Sw)(Su/Sw)^T
+ * the weighted covariance of the pixel offsets (bits 2-16 may combine).  Unsolved entries get zero mu'/Sigma'.
+ * mu2d_new [V,N,2], cov2d_new [V,N,3] float32, vflags [V,N] uint8: device.
+ */
+tg_status tg_solve_views(const float* acc, const tg_splats* s, int64_t N, int32_t V,
+                         const tg_params* p, float* mu2d_new, float* cov2d_new,
+                         uint8_t* vflags, void* stream);
+
+/*
+ * tg_triangulate -- multi-view update of each Gaussian (Sec. 4.4) in FP64.
+ *
+ * Needs at least views_min solved views, total alpha >= wsum_total_min and
+ * total pixels >= pix_total_min (Sec. 5.2).  Mean: homogeneous DLT over the
+ * solved views' mu' in K^{-1}-normalised coordinates, smallest eigenvector
+ * of the 4x4 normal matrix (Jacobi), rejected when |h_w| < 1e-12 or behind
+ * a used camera.  Covariance: the 3 equations per view of
+ * Sigma_2D' = J W Sigma_3D' W^T J^T (J at the new mean) in 6 unknowns,
+ * unweighted normal equations, Cholesky.  Decomposition: Jacobi eigen;
+ * rejected when an eigenvalue is <= 0; eigenpairs re-ordered so the scale
+ * ranks match the input Gaussian's, columns sign-aligned to the old rotation,
+ * det +1, quaternion with w >= 0, scales = sqrt(eigenvalues).
+ * Status bits: 1 mean updated, 2 rotation/scale updated, 4 few views,
+ * 8 low total alpha, 16 few total pixels, 32 non-positive eigenvalue or
+ * singular covariance system, 64 degenerate DLT, 128 behind a camera.
+ * Everything not updated is copied from g_in.  g_out may alias g_in (in-place
+ * update).  cams: host [V]; V <= TG_MAX_VIEWS.
+ */
+tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_new, const uint8_t* vflags,
+                         const float* acc, const tg_splats* s, const tg_gaussians* g_in,
+                         int64_t N, const tg_camera* cams, int32_t V, const tg_params* p,
+                         tg_gaussians* g_out, uint32_t* status, void* stream);
+
+/* Linear index of tiles and coarse bins, for tests and tools: expands the
+ * coarse lists into the per-tile depth-ordered lists.  tile_ranges [T,2]
+ * start/end into tile_ids (capacity entries).  Runs two passes (count, fill)
+ * using the workspace; query with ws == NULL. */
+tg_status tg_bin_expand(const tg_splats* s, const tg_bins* bins, int64_t N,
+                        const tg_camera* cams, int32_t V, const tg_params* p,
+                        uint32_t* tile_ids, uint32_t* tile_ranges, int64_t capacity,
+                        int64_t* n_out, void* ws, size_t* ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TG_H */

@@ -1,0 +1,278 @@
+"""Python API over libtg.  Torch provides device memory and streams only;
+every step of the method runs in the HIP kernels behind the C ABI.
+
+The thin wrappers (`preprocess`, `bin_sort`, `splat_accumulate`,
+`solve_views`, `triangulate`, `bin_expand`) mirror the C entry points of
+include/tg.h one to one.  `MotionTransfer` owns the buffers of one scene
+shape (N Gaussians, V views of one resolution) and runs a frame.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+__all__ = ["GaussianTensors", "SplatTensors", "BinTensors", "MotionTransfer", "preprocess", "bin_sort",
+           "splat_accumulate", "solve_views", "triangulate", "bin_expand", "stream_ptr", "default_params"]
+
+default_params = _lib.default_params
+
+
+def stream_ptr(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libtg takes device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("libtg takes contiguous tensors only")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class GaussianTensors:
+    means: torch.Tensor          # [N,3] f32
+    quats: torch.Tensor          # [N,4] f32 (w,x,y,z)
+    scales: torch.Tensor         # [N,3] f32 (linear or log)
+    opacity: torch.Tensor        # [N] f32 (activated or logit)
+    sh: torch.Tensor | None = None   # [N,K,3] f32
+    sh_degree: int = 0
+    scale_mode: int = 0
+    opacity_mode: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    def c(self) -> _lib.Gaussians:
+        return _lib.Gaussians(_ptr(self.means), _ptr(self.quats), _ptr(self.scales), _ptr(self.opacity),
+                              _ptr(self.sh), int(self.sh_degree), int(self.scale_mode), int(self.opacity_mode), 0)
+
+    @staticmethod
+    def from_scene(scene, device="cuda", sh=False):
+        t = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        g = GaussianTensors(t(scene.means), t(scene.quats), t(scene.scales), t(scene.opacity))
+        if sh and scene.sh is not None:
+            k = scene.sh.shape[1] // 3
+            g.sh = t(scene.sh).reshape(-1, k, 3).contiguous()
+            g.sh_degree = int(round(k ** 0.5)) - 1
+        return g
+
+    def clone(self):
+        return GaussianTensors(self.means.clone(), self.quats.clone(), self.scales.clone(), self.opacity.clone(),
+                               None if self.sh is None else self.sh.clone(), self.sh_degree, self.scale_mode,
+                               self.opacity_mode)
+
+
+@dataclass
+class SplatTensors:
+    rec: torch.Tensor       # [V,N,8] f32
+    cov2d: torch.Tensor     # [V,N,3] f32
+    rect: torch.Tensor      # [V,N,4] int16 storage of uint16
+    key: torch.Tensor       # [V,N] int32 storage of uint32
+    colors: torch.Tensor | None = None
+    clamped: torch.Tensor | None = None
+
+    @staticmethod
+    def alloc(V, N, device="cuda", colors=False):
+        z = lambda *s, dt=torch.float32: torch.empty(*s, dtype=dt, device=device)
+        return SplatTensors(z(V, N, 8), z(V, N, 3), z(V, N, 4, dt=torch.int16), z(V, N, dt=torch.int32),
+                            z(V, N, 3) if colors else None, z(V, N, 3, dt=torch.uint8) if colors else None)
+
+    def c(self) -> _lib.Splats:
+        return _lib.Splats(_ptr(self.rec), _ptr(self.cov2d), _ptr(self.rect), _ptr(self.key), _ptr(self.colors),
+                           _ptr(self.clamped))
+
+
+@dataclass
+class BinTensors:
+    order: torch.Tensor        # [V,N] int32 (uint32 ids)
+    cell_ids: torch.Tensor     # [capacity] int32
+    cell_ranges: torch.Tensor  # [n_cells,2] int32
+    n_pairs: torch.Tensor      # [1] int64
+    overflow: torch.Tensor     # [1] int32
+    capacity: int
+
+    @staticmethod
+    def alloc(V, N, n_cells, capacity, device="cuda"):
+        return BinTensors(torch.empty(V, N, dtype=torch.int32, device=device),
+                          torch.empty(max(capacity, 1), dtype=torch.int32, device=device),
+                          torch.empty(n_cells, 2, dtype=torch.int32, device=device),
+                          torch.zeros(1, dtype=torch.int64, device=device),
+                          torch.zeros(1, dtype=torch.int32, device=device), int(capacity))
+
+    def c(self) -> _lib.Bins:
+        return _lib.Bins(_ptr(self.order), _ptr(self.cell_ids), _ptr(self.cell_ranges), _ptr(self.n_pairs),
+                         _ptr(self.overflow), int(self.capacity))
+
+
+# ---------------------------------------------------------------- wrappers
+def preprocess(g: GaussianTensors, cams, params, out: SplatTensors, stream=None):
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    gc, oc = g.c(), out.c()
+    check("tg_preprocess", lib().tg_preprocess(ctypes.byref(gc), g.n, cams, len(cams), ctypes.byref(params),
+                                               ctypes.byref(oc), stream_ptr(stream)))
+
+
+def bin_sort_ws_bytes(n, cams, params, capacity) -> int:
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    sc = _lib.Splats()
+    b = _lib.Bins()
+    b.capacity = int(capacity)
+    nb = ctypes.c_size_t(0)
+    check("tg_bin_sort", lib().tg_bin_sort(ctypes.byref(sc), n, cams, len(cams), ctypes.byref(params),
+                                           ctypes.byref(b), None, ctypes.byref(nb), None))
+    return int(nb.value)
+
+
+def bin_sort(s: SplatTensors, n, cams, params, bins: BinTensors, ws: torch.Tensor, stream=None):
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    sc, bc = s.c(), bins.c()
+    nb = ctypes.c_size_t(ws.numel() * ws.element_size())
+    check("tg_bin_sort", lib().tg_bin_sort(ctypes.byref(sc), n, cams, len(cams), ctypes.byref(params),
+                                           ctypes.byref(bc), _ptr(ws), ctypes.byref(nb), stream_ptr(stream)))
+
+
+def splat_accumulate(s: SplatTensors, bins: BinTensors, n, cams, disp, vis, params, acc, t_final=None,
+                     stats=None, stream=None):
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    sc, bc = s.c(), bins.c()
+    check("tg_splat_accumulate", lib().tg_splat_accumulate(
+        ctypes.byref(sc), ctypes.byref(bc), n, cams, len(cams), _ptr(disp), _ptr(vis), ctypes.byref(params),
+        _ptr(acc), _ptr(t_final), _ptr(stats), stream_ptr(stream)))
+
+
+def solve_views(acc, s: SplatTensors, n, V, params, mu_new, cov_new, vflags, stream=None):
+    sc = s.c()
+    check("tg_solve_views", lib().tg_solve_views(_ptr(acc), ctypes.byref(sc), n, V, ctypes.byref(params),
+                                                 _ptr(mu_new), _ptr(cov_new), _ptr(vflags), stream_ptr(stream)))
+
+
+def triangulate(mu_new, cov_new, vflags, acc, s: SplatTensors, g_in: GaussianTensors, cams, params,
+                g_out: GaussianTensors, status, stream=None):
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    sc, gi, go = s.c(), g_in.c(), g_out.c()
+    check("tg_triangulate", lib().tg_triangulate(
+        _ptr(mu_new), _ptr(cov_new), _ptr(vflags), _ptr(acc), ctypes.byref(sc), ctypes.byref(gi), g_in.n, cams,
+        len(cams), ctypes.byref(params), ctypes.byref(go), _ptr(status), stream_ptr(stream)))
+
+
+def bin_expand(s: SplatTensors, bins: BinTensors, n, cams, params, stream=None):
+    """Per-tile depth-ordered lists (tile_ids, tile_ranges [T,2]); syncs."""
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    L = lib()
+    T = L.tg_num_tiles(cams, len(cams))
+    sc, bc = s.c(), bins.c()
+    nb = ctypes.c_size_t(0)
+    check("tg_bin_expand", L.tg_bin_expand(ctypes.byref(sc), ctypes.byref(bc), n, cams, len(cams),
+                                           ctypes.byref(params), None, None, 0, None, None, ctypes.byref(nb), None))
+    dev = s.rec.device
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    ranges = torch.empty(T, 2, dtype=torch.int32, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = max(int(bins.capacity) * 64, 1)
+    for _ in range(2):
+        ids = torch.empty(cap, dtype=torch.int32, device=dev)
+        check("tg_bin_expand", L.tg_bin_expand(ctypes.byref(sc), ctypes.byref(bc), n, cams, len(cams),
+                                               ctypes.byref(params), _ptr(ids), _ptr(ranges), cap, _ptr(n_out),
+                                               _ptr(ws), ctypes.byref(nb), stream_ptr(stream)))
+        torch.cuda.synchronize()
+        tot = int(n_out.item())
+        if tot <= cap:
+            return ids[:tot], ranges
+        cap = tot
+    raise RuntimeError("tg_bin_expand: capacity did not converge")
+
+
+# ---------------------------------------------------------------- frame object
+class MotionTransfer:
+    """Buffers and calls for one frame of motion transfer (N Gaussians, V
+    views of one resolution).  All work is queued on the current stream."""
+
+    def __init__(self, cams, n, device="cuda", params=None, capacity=None):
+        self.cams_host = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+        self.V = len(self.cams_host)
+        self.N = int(n)
+        self.W = int(self.cams_host[0].width)
+        self.H = int(self.cams_host[0].height)
+        self.device = torch.device(device)
+        self.params = params if params is not None else _lib.default_params()
+        L = lib()
+        self.n_cells = int(L.tg_num_cells(self.cams_host, self.V, self.N, ctypes.byref(self.params)))
+        if self.n_cells < 0:
+            raise ValueError("unsupported camera set")
+        self.splats = SplatTensors.alloc(self.V, self.N, self.device)
+        if capacity is None:
+            capacity = max(1024, 4 * self.N * self.V)
+        self._alloc_bins(capacity)
+        VN = (self.V, self.N)
+        self.acc = torch.empty(*VN, 16, dtype=torch.float32, device=self.device)
+        self.mu_new = torch.empty(*VN, 2, dtype=torch.float32, device=self.device)
+        self.cov_new = torch.empty(*VN, 3, dtype=torch.float32, device=self.device)
+        self.vflags = torch.empty(*VN, dtype=torch.uint8, device=self.device)
+        self.status = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        self.t_final = None
+        self.stats = torch.zeros(2, dtype=torch.int64, device=self.device)
+
+    def _alloc_bins(self, capacity):
+        self.bins = BinTensors.alloc(self.V, self.N, self.n_cells, capacity, self.device)
+        nb = bin_sort_ws_bytes(self.N, self.cams_host, self.params, capacity)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+
+    # -- stages
+    def preprocess(self, g: GaussianTensors):
+        preprocess(g, self.cams_host, self.params, self.splats)
+
+    def bin_sort(self, check_overflow=True):
+        bin_sort(self.splats, self.N, self.cams_host, self.params, self.bins, self.ws)
+        if check_overflow:
+            torch.cuda.current_stream().synchronize()
+            if int(self.bins.overflow.item()):
+                need = int(self.bins.n_pairs.item())
+                self._alloc_bins(int(need * 1.1) + 1024)
+                bin_sort(self.splats, self.N, self.cams_host, self.params, self.bins, self.ws)
+
+    def accumulate(self, disp, vis=None, t_final=False, stats=False):
+        self.acc.zero_()
+        if t_final and self.t_final is None:
+            self.t_final = torch.empty(self.V, self.H, self.W, dtype=torch.float32, device=self.device)
+        if stats:
+            self.stats.zero_()
+        splat_accumulate(self.splats, self.bins, self.N, self.cams_host, disp, vis, self.params, self.acc,
+                         self.t_final if t_final else None, self.stats if stats else None)
+
+    def solve(self):
+        solve_views(self.acc, self.splats, self.N, self.V, self.params, self.mu_new, self.cov_new, self.vflags)
+
+    def triangulate(self, g_in: GaussianTensors, g_out: GaussianTensors):
+        triangulate(self.mu_new, self.cov_new, self.vflags, self.acc, self.splats, g_in, self.cams_host,
+                    self.params, g_out, self.status)
+
+    def run(self, g: GaussianTensors, disp, vis=None, g_out: GaussianTensors | None = None, check_overflow=True,
+            t_final=False, stats=False):
+        """Cold frame: preprocess -> bin_sort -> accumulate -> solve -> triangulate."""
+        if g_out is None:
+            g_out = GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.quats),
+                                    torch.empty_like(g.scales), g.opacity, g.sh, g.sh_degree, g.scale_mode,
+                                    g.opacity_mode)
+        self.preprocess(g)
+        self.bin_sort(check_overflow=check_overflow)
+        self.accumulate(disp, vis, t_final=t_final, stats=stats)
+        self.solve()
+        self.triangulate(g, g_out)
+        return g_out
+
+    def run_warm(self, g: GaussianTensors, disp, vis, g_out: GaussianTensors):
+        """Warm frame (splats and bins of the reference frame resident)."""
+        self.accumulate(disp, vis)
+        self.solve()
+        self.triangulate(g, g_out)
+        return g_out

@@ -1,0 +1,564 @@
+// tg_bin_sort / tg_bin_expand: depth ordering and coarse binning
+// (TrackerSplat Sec. 3.1: blending follows the Gaussians' depth order).
+//
+// Design for CDNA4: instead of sorting one 64-bit (tile | depth) key per
+// (tile, Gaussian) pair -- about 16M pairs per 1080p view at 1M Gaussians --
+// we (1) radix-sort the N depth keys of each view once, giving every Gaussian
+// a depth rank, then (2) emit one 32-bit key (coarse bin | depth rank) per
+// (coarse bin, Gaussian) pair, with coarse bins of 8x8 tiles, and radix-sort
+// those (about 2M pairs per view).  The rasteriser streams its coarse bin's
+// list in depth order and keeps the entries whose tile rectangle contains its
+// tile, which is exactly the per-tile depth-ordered list.
+//
+// The radix sort is LSD with 8-bit digits: per pass a histogram kernel, an
+// exclusive scan of the digit-major histogram, and a scatter kernel whose
+// block-local ranks are stable (wave64 ballot matching, wave prefix in LDS).
+#include "tg_internal.h"
+
+namespace {
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // 4096 keys per block
+constexpr int SORT_WAVES = SORT_THREADS / TG_WAVE;      // 4
+constexpr int WAVE_ITEMS = SORT_TILE / SORT_WAVES;      // 1024 keys per wave
+
+// Active length of a segment: fixed, or read from the device (single
+// dynamic segment), 0 when the device count exceeds the capacity.
+__device__ __forceinline__ int64_t seg_count(int64_t seg_len, const int64_t* dev_count) {
+    if (!dev_count) return seg_len;
+    int64_t n = *dev_count;
+    return n > seg_len ? 0 : n;
+}
+
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __restrict__ keys, int64_t seg_len,
+                                                             const int64_t* __restrict__ dev_count, int shift,
+                                                             uint32_t* __restrict__ ghist, int nblk)
+{
+    __shared__ uint32_t h[256];
+    const int seg = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t n = seg_count(seg_len, dev_count);
+    const int64_t base = (int64_t)b * SORT_TILE;
+    const uint32_t* kp = keys + (int64_t)seg * seg_len;
+    if (base < n) {
+        const int w = t >> 6, l = t & 63;
+#pragma unroll 4
+        for (int r = 0; r < SORT_ITEMS; ++r) {
+            int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
+            if (idx < n) atomicAdd(&h[(kp[idx] >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    ghist[((int64_t)seg * 256 + t) * nblk + b] = h[t];
+}
+
+// ---- exclusive scan of a [nseg][L] u32 array (three kernels) ------------
+constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[SCAN_THREADS / TG_WAVE];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    uint32_t inc = wave_scan_add_u32(v);
+    if (l == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t x = l < SCAN_THREADS / TG_WAVE ? wsum[l] : 0u;
+        uint32_t xi = wave_scan_add_u32(x);
+        if (l < SCAN_THREADS / TG_WAVE) wsum[l] = xi - x;
+        if (l == SCAN_THREADS / TG_WAVE - 1) *total = xi;
+    }
+    __syncthreads();
+    uint32_t r = wsum[w] + inc - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t* __restrict__ in, int64_t L,
+                                                              uint32_t* __restrict__ sums, int nchunk)
+{
+    __shared__ uint32_t tot;
+    const int seg = blockIdx.y;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    uint32_t s = 0;
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (base + i < L) s += in[(int64_t)seg * L + base + i];
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) sums[(int64_t)seg * nchunk + blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_sums(uint32_t* __restrict__ sums, int nchunk)
+{
+    // one block per segment; nchunk may exceed the block size
+    __shared__ uint32_t tot;
+    const int seg = blockIdx.x;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < nchunk; c0 += SCAN_THREADS) {
+        int c = c0 + threadIdx.x;
+        uint32_t v = c < nchunk ? sums[(int64_t)seg * nchunk + c] : 0u;
+        uint32_t ex = block_excl_scan(v, &tot);
+        if (c < nchunk) sums[(int64_t)seg * nchunk + c] = ex + carry;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(uint32_t* __restrict__ data, int64_t L,
+                                                            const uint32_t* __restrict__ sums, int nchunk)
+{
+    __shared__ uint32_t tot;
+    const int seg = blockIdx.y;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = base + i < L ? data[(int64_t)seg * L + base + i] : 0u;
+        s += v[i];
+    }
+    uint32_t ex = block_excl_scan(s, &tot) + sums[(int64_t)seg * nchunk + blockIdx.x];
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < L) data[(int64_t)seg * L + base + i] = ex;
+        ex += v[i];
+    }
+}
+
+// ---- stable scatter --------------------------------------------------------
+// Items of a block: wave w owns keys [w*1024, (w+1)*1024) of the block's 4096,
+// visited in 16 rounds of 64 consecutive keys, so order within the block is
+// (wave, round, lane) = input order.
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, int64_t seg_len, const int64_t* __restrict__ dev_count, int shift,
+    const uint32_t* __restrict__ goff, int nblk)
+{
+    __shared__ uint32_t woff[SORT_WAVES][256];
+    const int seg = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+    const int w = t >> 6, l = t & 63;
+    const int64_t n = seg_count(seg_len, dev_count);
+    const int64_t base = (int64_t)b * SORT_TILE;
+    if (base >= n) return;  // uniform per block
+    for (int i = t; i < SORT_WAVES * 256; i += SORT_THREADS) (&woff[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t so = (int64_t)seg * seg_len;
+    uint32_t k[SORT_ITEMS], val[SORT_ITEMS];
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
+        if (idx < n) {
+            k[r] = kin[so + idx];
+            val[r] = vin ? vin[so + idx] : (uint32_t)idx;
+            atomicAdd(&woff[w][(k[r] >> shift) & 255u], 1u);
+        } else {
+            k[r] = 0;
+            val[r] = 0;
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t run = goff[((int64_t)seg * 256 + t) * nblk + b];
+#pragma unroll
+        for (int ww = 0; ww < SORT_WAVES; ++ww) {
+            uint32_t c = woff[ww][t];
+            woff[ww][t] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
+        bool active = idx < n;
+        uint32_t d = (k[r] >> shift) & 255u;
+        uint64_t m = ballot64(active);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            bool set = (d >> bit) & 1u;
+            uint64_t bb = ballot64(active && set);
+            m &= set ? bb : ~bb;
+        }
+        if (active) {
+            uint32_t rank = (uint32_t)__popcll(m & lt);
+            uint32_t pos = woff[w][d] + rank;
+            if (pos < (uint64_t)n) {  // always true for a consistent histogram
+                if (kout) kout[so + pos] = k[r];
+                if (vout) vout[so + pos] = val[r];
+            }
+            if (rank == 0) woff[w][d] += (uint32_t)__popcll(m);
+        }
+    }
+}
+
+// ---- coarse-bin key emission ---------------------------------------------
+__global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ order, const ushort4* __restrict__ rect,
+                                              int64_t N, int V, GridPack gp, int cshift, int rbits,
+                                              uint32_t* __restrict__ keys, int64_t capacity,
+                                              unsigned long long* __restrict__ n_pairs, int32_t* __restrict__ overflow)
+{
+    __shared__ uint32_t tot;
+    __shared__ unsigned long long gbase;
+    const int v = blockIdx.y;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t cnt = 0;
+    int cx0 = 0, cx1 = 0, cy0 = 0, cy1 = 0;
+    if (k < N) {
+        uint32_t g = order[(int64_t)v * N + k];
+        ushort4 r = g < (uint64_t)N ? rect[(int64_t)v * N + g] : make_ushort4(0, 0, 0, 0);
+        if (r.z > r.x && r.w > r.y) {
+            cx0 = r.x >> cshift;
+            cx1 = ((r.z - 1) >> cshift) + 1;
+            cy0 = r.y >> cshift;
+            cy1 = ((r.w - 1) >> cshift) + 1;
+            cnt = (uint32_t)((cx1 - cx0) * (cy1 - cy0));
+        }
+    }
+    // block exclusive scan (256 threads = 4 waves)
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    uint32_t inc = wave_scan_add_u32(cnt);
+    if (l == 63) wsum[w] = inc;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t s = 0;
+        for (int i = 0; i < 4; ++i) { uint32_t c = wsum[i]; wsum[i] = s; s += c; }
+        tot = s;
+        gbase = s ? atomicAdd(n_pairs, (unsigned long long)s) : 0ull;
+    }
+    __syncthreads();
+    if (cnt == 0) return;
+    unsigned long long pos = gbase + wsum[w] + inc - cnt;
+    if (pos + cnt > (unsigned long long)capacity) {
+        *overflow = 1;
+        return;
+    }
+    const int cw = gp.cx[v];
+    const uint32_t cbase = (uint32_t)gp.cell_off[v];
+    for (int y = cy0; y < cy1; ++y)
+        for (int x = cx0; x < cx1; ++x) {
+            uint32_t cell = cbase + (uint32_t)(y * cw + x);
+            keys[pos++] = (cell << rbits) | (uint32_t)k;
+        }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t val) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = val;
+}
+__global__ void k_zero_counters(unsigned long long* n_pairs, int32_t* overflow) {
+    *n_pairs = 0ull;
+    *overflow = 0;
+}
+__global__ void k_check_overflow(const unsigned long long* n_pairs, int64_t capacity, int32_t* overflow) {
+    if (*n_pairs > (unsigned long long)capacity) *overflow = 1;
+}
+
+__device__ __forceinline__ int view_of_cell(const GridPack& gp, int V, uint32_t cell) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if ((uint32_t)gp.cell_off[mid] <= cell) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_cell_finalize(const uint32_t* __restrict__ skeys,
+                                                       const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                       int rbits, const uint32_t* __restrict__ order, int64_t N,
+                                                       GridPack gp, int V, uint32_t* __restrict__ cell_ids,
+                                                       uint2* __restrict__ ranges, int64_t ncell)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = *n_pairs;
+    if (n > capacity) n = 0;
+    if (i >= n) return;
+    const uint32_t key = skeys[i];
+    const uint32_t cell = key >> rbits;
+    const uint32_t rank = key & ((1u << rbits) - 1u);
+    if (cell >= (uint64_t)ncell || rank >= (uint64_t)N) return;  // consistent keys never hit this
+    const int v = view_of_cell(gp, V, cell);
+    cell_ids[i] = order[(int64_t)v * N + rank];
+    if (i == 0 || (skeys[i - 1] >> rbits) != cell) ranges[cell].x = (uint32_t)i;
+    if (i == n - 1 || (skeys[i + 1] >> rbits) != cell) ranges[cell].y = (uint32_t)(i + 1);
+}
+
+// ---- radix sort driver -------------------------------------------------------
+struct SortBufs {
+    uint32_t* hist;   // [nseg][256][nblk]
+    uint32_t* sums;   // [nseg][nchunk]
+};
+
+size_t sort_scratch_bytes(int64_t seg_len, int nseg) {
+    int64_t nblk = (seg_len + SORT_TILE - 1) / SORT_TILE;
+    int64_t L = 256 * nblk;
+    int64_t nchunk = (L + SCAN_TILE - 1) / SCAN_TILE;
+    return (size_t)nseg * (size_t)(L + nchunk + 64) * sizeof(uint32_t);
+}
+
+// Sorts nseg segments of seg_len keys (or one segment of *dev_count keys) by
+// bits [bit0, bit0 + 8*passes).  Buffers: ka/va hold the input; kb/vb are the
+// ping-pong partner.  Final keys/values go to kfinal/vfinal (either may be
+// null when not needed).  vin == null means values are the indices.
+tg_status radix_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va, uint32_t* kb,
+                     uint32_t* vb, uint32_t* kfinal, uint32_t* vfinal, int64_t seg_len, int nseg,
+                     const int64_t* dev_count, int bit0, int passes, void* scratch, hipStream_t s)
+{
+    const int nblk = (int)((seg_len + SORT_TILE - 1) / SORT_TILE);
+    if (nblk == 0) return TG_OK;
+    const int64_t L = 256LL * nblk;
+    const int nchunk = (int)((L + SCAN_TILE - 1) / SCAN_TILE);
+    uint32_t* hist = (uint32_t*)scratch;
+    uint32_t* sums = hist + (int64_t)nseg * L;
+    const uint32_t* ck = kin;
+    const uint32_t* cv = vin;
+    for (int p = 0; p < passes; ++p) {
+        const bool last = p == passes - 1;
+        uint32_t* ok = last ? kfinal : ((p & 1) ? kb : ka);
+        uint32_t* ov = last ? vfinal : ((p & 1) ? vb : va);
+        if (!last && !ok) return TG_ERR_INVALID_ARG;
+        const int shift = bit0 + 8 * p;
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, seg_len, dev_count, shift,
+                           hist, nblk);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
+        hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(SCAN_THREADS), 0, s, sums, nchunk);
+        hipLaunchKernelGGL(k_scan_down, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, cv, ok,
+                           (last && !vfinal) ? nullptr : ov, seg_len, dev_count, shift, hist, nblk);
+        TG_CHECK_LAUNCH();
+        ck = ok;
+        cv = ov;
+    }
+    return TG_OK;
+}
+
+inline int bitlen(uint64_t x) {  // number of bits to represent x-1 values [0, x)
+    int b = 0;
+    while (b < 63 && (1ull << b) < x) ++b;
+    return b < 1 ? 1 : b;
+}
+
+struct BinPlan {
+    int cshift, rbits, cbits, passes;
+    int64_t ncell;
+    GridPack gp;
+};
+
+tg_status plan_bins(const tg_camera* cams, int V, int64_t N, const tg_params* p, BinPlan* bp) {
+    if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
+    int cs = p->coarse_shift < 0 ? 0 : p->coarse_shift;
+    bp->rbits = bitlen((uint64_t)N);
+    for (;; ++cs) {
+        bp->ncell = fill_grid(cams, V, cs, &bp->gp);
+        bp->cbits = bitlen((uint64_t)bp->ncell);
+        if (bp->rbits + bp->cbits <= 32) break;
+        if (cs > 12) return TG_ERR_UNSUPPORTED;
+    }
+    bp->cshift = cs;
+    bp->passes = (bp->rbits + bp->cbits + 7) / 8;
+    return TG_OK;
+}
+
+// workspace layout
+struct BinWs {
+    uint32_t *dk_a, *dv_a, *dk_b, *dv_b;   // depth sort ping-pong [V*N]
+    uint32_t *pk_a, *pk_b;                  // pair keys [capacity]
+    void* scratch;
+    size_t bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+BinWs layout_ws(void* ws, int64_t N, int V, int64_t capacity) {
+    BinWs L;
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
+    size_t vn = (size_t)V * (size_t)N * 4;
+    size_t a = take(vn), b = take(vn), c = take(vn), d = take(vn);
+    size_t e = take((size_t)capacity * 4), f = take((size_t)capacity * 4);
+    size_t sc = sort_scratch_bytes(N, V);
+    size_t sc2 = sort_scratch_bytes(capacity, 1);
+    size_t g = take(sc > sc2 ? sc : sc2);
+    char* base = (char*)ws;
+    L.dk_a = (uint32_t*)(base + a);
+    L.dv_a = (uint32_t*)(base + b);
+    L.dk_b = (uint32_t*)(base + c);
+    L.dv_b = (uint32_t*)(base + d);
+    L.pk_a = (uint32_t*)(base + e);
+    L.pk_b = (uint32_t*)(base + f);
+    L.scratch = base + g;
+    L.bytes = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" int64_t tg_num_cells(const tg_camera* cams, int32_t V, int64_t N, const tg_params* p) {
+    if (!cams || !p || V < 1 || V > TG_MAX_VIEWS || N < 0) return -1;
+    BinPlan bp;
+    if (plan_bins(cams, V, N > 0 ? N : 1, p, &bp) != TG_OK) return -1;
+    return bp.ncell;
+}
+
+extern "C" int64_t tg_num_tiles(const tg_camera* cams, int32_t V) {
+    if (!cams || V < 1) return -1;
+    int64_t t = 0;
+    for (int v = 0; v < V; ++v) t += (int64_t)ceil_div(cams[v].width, TG_TILE) * ceil_div(cams[v].height, TG_TILE);
+    return t;
+}
+
+extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera* cams, int32_t V,
+                                 const tg_params* p, tg_bins* bins, void* ws, size_t* ws_bytes, void* stream)
+{
+    if (!sp || !cams || !p || !bins || !ws_bytes || N < 0 || V < 1) return TG_ERR_INVALID_ARG;
+    if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
+    if (N > (int64_t)0xFFFFFFFF || bins->capacity < 0 || bins->capacity > (int64_t)0xFFFFFFFF)
+        return TG_ERR_UNSUPPORTED;
+    BinPlan bp;
+    tg_status st = plan_bins(cams, V, N > 0 ? N : 1, p, &bp);
+    if (st != TG_OK) return st;
+    BinWs L = layout_ws(nullptr, N, V, bins->capacity);
+    if (!ws) {
+        *ws_bytes = L.bytes;
+        return TG_OK;
+    }
+    if (*ws_bytes < L.bytes) return TG_ERR_WORKSPACE;
+    if (!sp->key || !sp->rect || !bins->order || !bins->cell_ids || !bins->cell_ranges || !bins->n_pairs ||
+        !bins->overflow)
+        return TG_ERR_INVALID_ARG;
+    L = layout_ws(ws, N, V, bins->capacity);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(1), 0, s, (unsigned long long*)bins->n_pairs, bins->overflow);
+    {
+        int64_t n = 2 * bp.ncell;
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, bins->cell_ranges, n, 0u);
+    }
+    TG_CHECK_LAUNCH();
+    if (N == 0) return TG_OK;
+    // (1) depth order per view: 4 passes over the 32-bit depth keys
+    st = radix_sort(sp->key, nullptr, L.dk_a, L.dv_a, L.dk_b, L.dv_b, nullptr, bins->order, N, V, nullptr, 0, 4,
+                    L.scratch, s);
+    if (st != TG_OK) return st;
+    // (2) emit (coarse bin | depth rank) keys
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((N + 255) / 256), V), dim3(256), 0, s, bins->order,
+                       (const ushort4*)sp->rect, N, V, bp.gp, bp.cshift, bp.rbits, L.pk_a, bins->capacity,
+                       (unsigned long long*)bins->n_pairs, bins->overflow);
+    hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,
+                       bins->capacity, bins->overflow);
+    TG_CHECK_LAUNCH();
+    if (bins->capacity == 0) return TG_OK;
+    // (3) sort pair keys over their used bits; final keys land in pk_b or pk_a
+    uint32_t* final_keys = L.pk_b;
+    uint32_t* other = L.pk_a;
+    // ping-pong: pass p writes (p odd ? kb : ka) except the last -> kfinal.
+    // Input lives in pk_a, so use ka = pk_b, kb = pk_a, final = whichever the
+    // last pass would otherwise overwrite safely.
+    final_keys = (bp.passes & 1) ? L.pk_b : L.pk_a;
+    other = (bp.passes & 1) ? L.pk_a : L.pk_b;
+    (void)other;
+    st = radix_sort(L.pk_a, nullptr, L.pk_b, nullptr, L.pk_a, nullptr, final_keys, nullptr, bins->capacity, 1,
+                    bins->n_pairs, 0, bp.passes, L.scratch, s);
+    if (st != TG_OK) return st;
+    // (4) ranges and ids
+    hipLaunchKernelGGL(k_cell_finalize, dim3((unsigned)((bins->capacity + 255) / 256)), dim3(256), 0, s, final_keys,
+                       bins->n_pairs, bins->capacity, bp.rbits, bins->order, N, bp.gp, V, bins->cell_ids,
+                       (uint2*)bins->cell_ranges, bp.ncell);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}
+
+// ---- expansion of coarse lists into per-tile lists (tests / tools) -----------
+namespace {
+// One wave per tile: stream the coarse list, keep entries whose rectangle
+// contains the tile.  mode 0 counts, mode 1 writes.
+__global__ void __launch_bounds__(64) k_expand(const ushort4* __restrict__ rect, const uint32_t* __restrict__ cell_ids,
+                                               const uint2* __restrict__ ranges, const int32_t* __restrict__ overflow,
+                                               int64_t N, int V, GridPack gp, int cshift, uint32_t* __restrict__ counts,
+                                               const uint32_t* __restrict__ starts, uint32_t* __restrict__ out,
+                                               int64_t capacity, int mode)
+{
+    const int64_t tile = blockIdx.x;
+    if (*overflow) {
+        if (mode == 0 && threadIdx.x == 0) counts[tile] = 0;
+        return;
+    }
+    int v = 0;
+    while (v + 1 < V && gp.tile_off[v + 1] <= tile) ++v;
+    const int lt = (int)(tile - gp.tile_off[v]);
+    const int tx = lt % gp.tx[v], ty = lt / gp.tx[v];
+    const uint32_t cell = (uint32_t)gp.cell_off[v] + (uint32_t)((ty >> cshift) * gp.cx[v] + (tx >> cshift));
+    const uint2 rg = ranges[cell];
+    const int l = threadIdx.x;
+    const uint64_t lt_mask = lanemask_lt();
+    uint32_t n = 0;
+    uint32_t wpos = mode ? starts[tile] : 0u;
+    for (uint32_t i0 = rg.x; i0 < rg.y; i0 += 64) {
+        uint32_t i = i0 + l;
+        bool hit = false;
+        uint32_t g = 0;
+        if (i < rg.y) {
+            g = cell_ids[i];
+            if (g < (uint64_t)N) {
+                ushort4 r = rect[(int64_t)v * N + g];
+                hit = tx >= r.x && tx < r.z && ty >= r.y && ty < r.w;
+            }
+        }
+        uint64_t m = ballot64(hit);
+        if (mode && hit) {
+            uint64_t o = (uint64_t)wpos + n + (uint64_t)__popcll(m & lt_mask);
+            if (o < (uint64_t)capacity) out[o] = g;
+        }
+        n += (uint32_t)__popcll(m);
+    }
+    if (mode == 0 && l == 0) counts[tile] = n;
+}
+
+__global__ void k_ranges_from_starts(const uint32_t* __restrict__ starts, const uint32_t* __restrict__ counts,
+                                     int64_t T, uint2* __restrict__ ranges, int64_t capacity, int64_t* n_out) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T) ranges[t] = make_uint2(starts[t], starts[t] + counts[t]);
+    if (t == T - 1) *n_out = (int64_t)starts[t] + counts[t];
+}
+}  // namespace
+
+extern "C" tg_status tg_bin_expand(const tg_splats* sp, const tg_bins* bins, int64_t N, const tg_camera* cams,
+                                   int32_t V, const tg_params* p, uint32_t* tile_ids, uint32_t* tile_ranges,
+                                   int64_t capacity, int64_t* n_out, void* ws, size_t* ws_bytes, void* stream)
+{
+    if (!sp || !bins || !cams || !p || !ws_bytes || N < 0 || V < 1) return TG_ERR_INVALID_ARG;
+    if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
+    BinPlan bp;
+    tg_status st = plan_bins(cams, V, N > 0 ? N : 1, p, &bp);
+    if (st != TG_OK) return st;
+    const int64_t T = bp.gp.tile_off[V];
+    size_t need = align256((size_t)T * 4) * 2 + sort_scratch_bytes(T, 1) + 256;
+    if (!ws) {
+        *ws_bytes = need;
+        return TG_OK;
+    }
+    if (*ws_bytes < need) return TG_ERR_WORKSPACE;
+    if (!tile_ids || !tile_ranges || !n_out) return TG_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* counts = (uint32_t*)ws;
+    uint32_t* starts = (uint32_t*)((char*)ws + align256((size_t)T * 4));
+    uint32_t* scr = (uint32_t*)((char*)ws + 2 * align256((size_t)T * 4));
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)T), dim3(64), 0, s, (const ushort4*)sp->rect, bins->cell_ids,
+                       (const uint2*)bins->cell_ranges, bins->overflow, N, V, bp.gp, bp.cshift, counts, nullptr,
+                       nullptr, (int64_t)0, 0);
+    hipMemcpyAsync(starts, counts, (size_t)T * 4, hipMemcpyDeviceToDevice, s);
+    const int nchunk = (int)((T + SCAN_TILE - 1) / SCAN_TILE);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, 1), dim3(SCAN_THREADS), 0, s, starts, T, scr, nchunk);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, s, scr, nchunk);
+    hipLaunchKernelGGL(k_scan_down, dim3(nchunk, 1), dim3(SCAN_THREADS), 0, s, starts, T, scr, nchunk);
+    hipLaunchKernelGGL(k_ranges_from_starts, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, starts, counts, T,
+                       (uint2*)tile_ranges, capacity, n_out);
+    TG_CHECK_LAUNCH();
+    // Entries beyond `capacity` are dropped; *n_out reports the full count so
+    // the caller can re-size (counts are deterministic).
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)T), dim3(64), 0, s, (const ushort4*)sp->rect, bins->cell_ids,
+                       (const uint2*)bins->cell_ranges, bins->overflow, N, V, bp.gp, bp.cshift, counts, starts,
+                       tile_ids, capacity, 1);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}

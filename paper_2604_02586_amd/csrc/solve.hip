@@ -1,0 +1,481 @@
+// tg_solve_views and tg_triangulate: the batched small solves of PWI-LS and
+// of the multi-view update (TrackerSplat Sec. 4.2 Eq. 2, Sec. 4.3.4 Eq. 4,
+// Sec. 4.4.1-4.4.3, thresholds of Sec. 5.2), in FP64.
+//
+// Both are one thread per (view, Gaussian) or per Gaussian and are bound by
+// HBM traffic (the MI355X runs FP64 FMA at the rate of non-packed FP32, so a
+// few thousand FP64 flops per Gaussian are free next to its 21 bytes x V of
+// solved motions).  Eigen-decompositions use cyclic Jacobi, the covariance
+// system a 6x6 Cholesky of the normal equations.
+#include "tg_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------- per view
+__global__ void __launch_bounds__(256) k_solve_views(const float4* __restrict__ acc, const float4* __restrict__ rec,
+                                                     const float* __restrict__ cov2d, const ushort4* __restrict__ rect,
+                                                     int64_t VN, tg_params prm, float2* __restrict__ mu_new,
+                                                     float* __restrict__ cov_new, uint8_t* __restrict__ flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= VN) return;
+    const float4 a0 = acc[4 * i], a1 = acc[4 * i + 1], a2 = acc[4 * i + 2], a3 = acc[4 * i + 3];
+    const ushort4 r = rect[i];
+    // record: [Sw, Sux, Suy, Sxx, Sxy, Syy, Sdx, Sdy, Sxdx, Sxdy, Sydx, Sydy, n, ...]
+    const double Sw = a0.x, Sux = a0.y, Suy = a0.z, Sxx = a0.w;
+    const double Sxy = a1.x, Syy = a1.y, Sdx = a1.z, Sdy = a1.w;
+    const double Sxdx = a2.x, Sxdy = a2.y, Sydx = a2.z, Sydy = a2.w;
+    const double n = a3.x;
+    // V1 = [[Sxx, Sxy, Sux], [Sxy, Syy, Suy], [Sux, Suy, Sw]]
+    const double c00 = Syy * Sw - Suy * Suy;
+    const double c01 = Sux * Suy - Sxy * Sw;
+    const double c02 = Sxy * Suy - Syy * Sux;
+    const double c11 = Sxx * Sw - Sux * Sux;
+    const double c12 = Sxy * Sux - Sxx * Suy;
+    const double c22 = Sxx * Syy - Sxy * Sxy;
+    const double det = Sxx * c00 + Sxy * c01 + Sux * c02;
+    uint8_t f = 0;
+    if (!(r.z > r.x && r.w > r.y)) f |= 2;
+    if (n < (double)prm.pix_min) f |= 4;
+    if (!(Sw >= prm.wsum_min)) f |= 8;
+    if (!(det >= prm.det_min)) f |= 16;
+    {
+        // scale-invariant near-singularity: pixel offsets (nearly) collinear
+        const double iw = Sw > 0.0 ? 1.0 / Sw : 0.0;
+        const double mx = Sux * iw, my = Suy * iw;
+        const double ca = Sxx * iw - mx * mx, cb = Sxy * iw - mx * my, cc = Syy * iw - my * my;
+        const double tr = ca + cc;
+        if (!(tr > 0.0) || !(4.0 * (ca * cc - cb * cb) >= prm.iso_min * tr * tr)) f |= 16;
+    }
+    float2 mo = make_float2(0.f, 0.f);
+    float co[3] = {0.f, 0.f, 0.f};
+    if (f == 0) {
+        f = 1;
+        const double id = 1.0 / det;
+        // inverse of V1 (symmetric): adj / det
+        const double i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
+        const double i11 = c11 * id, i12 = c12 * id, i22 = c22 * id;
+        // Theta = V1^{-1} V2, V2 = [[Sxdx, Sxdy], [Sydx, Sydy], [Sdx, Sdy]]
+        const double t0x = i00 * Sxdx + i01 * Sydx + i02 * Sdx;
+        const double t0y = i00 * Sxdy + i01 * Sydy + i02 * Sdy;
+        const double t1x = i01 * Sxdx + i11 * Sydx + i12 * Sdx;
+        const double t1y = i01 * Sxdy + i11 * Sydy + i12 * Sdy;
+        const double t2x = i02 * Sxdx + i12 * Sydx + i22 * Sdx;
+        const double t2y = i02 * Sxdy + i12 * Sydy + i22 * Sdy;
+        // A = I + G with G = Theta[0:2]^T, c = Theta[2]
+        const double A00 = 1.0 + t0x, A01 = t1x, A10 = t0y, A11 = 1.0 + t1y;
+        const float4 rc = rec[2 * i];
+        mo = make_float2((float)((double)rc.x + t2x), (float)((double)rc.y + t2y));
+        const double sa = cov2d[3 * i], sb = cov2d[3 * i + 1], sc = cov2d[3 * i + 2];
+        // Sigma' = A Sigma A^T
+        const double m00 = A00 * sa + A01 * sb, m01 = A00 * sb + A01 * sc;
+        const double m10 = A10 * sa + A11 * sb, m11 = A10 * sb + A11 * sc;
+        co[0] = (float)(m00 * A00 + m01 * A01);
+        co[1] = (float)(m00 * A10 + m01 * A11);
+        co[2] = (float)(m10 * A10 + m11 * A11);
+    }
+    mu_new[i] = mo;
+    cov_new[3 * i] = co[0];
+    cov_new[3 * i + 1] = co[1];
+    cov_new[3 * i + 2] = co[2];
+    flags[i] = f;
+}
+
+// ---------------------------------------------------------------- helpers
+// Cyclic Jacobi for a symmetric n x n matrix (row-major, in place);
+// eigenvectors in the columns of Vm.
+template <int n>
+__device__ void jacobi_eig(double* A, double* Vm) {
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) Vm[i * n + j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 20; ++sweep) {
+        double off = 0.0, tot = 0.0;
+#pragma unroll
+        for (int i = 0; i < n; ++i)
+#pragma unroll
+            for (int j = 0; j < n; ++j) {
+                double x = A[i * n + j] * A[i * n + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+#pragma unroll
+        for (int p = 0; p < n - 1; ++p)
+#pragma unroll
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+                for (int k = 0; k < n; ++k) {  // A <- A J (columns p, q)
+                    const double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+#pragma unroll
+                for (int k = 0; k < n; ++k) {  // A <- J^T A (rows p, q)
+                    const double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+#pragma unroll
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = Vm[k * n + p], vkq = Vm[k * n + q];
+                    Vm[k * n + p] = c * vkp - s * vkq;
+                    Vm[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+}
+
+__device__ void quat_from_rot(const double* R, double* q) {
+    // Shepperd: pivot on the largest of tr, R00, R11, R22
+    const double tr = R[0] + R[4] + R[8];
+    double w, x, y, z;
+    if (tr >= R[0] && tr >= R[4] && tr >= R[8]) {
+        const double s = 2.0 * sqrt(fmax(1.0 + tr, 0.0));
+        w = 0.25 * s;
+        x = (R[7] - R[5]) / s;
+        y = (R[2] - R[6]) / s;
+        z = (R[3] - R[1]) / s;
+    } else if (R[0] >= R[4] && R[0] >= R[8]) {
+        const double s = 2.0 * sqrt(fmax(1.0 + R[0] - R[4] - R[8], 0.0));
+        w = (R[7] - R[5]) / s;
+        x = 0.25 * s;
+        y = (R[1] + R[3]) / s;
+        z = (R[2] + R[6]) / s;
+    } else if (R[4] >= R[8]) {
+        const double s = 2.0 * sqrt(fmax(1.0 - R[0] + R[4] - R[8], 0.0));
+        w = (R[2] - R[6]) / s;
+        x = (R[1] + R[3]) / s;
+        y = 0.25 * s;
+        z = (R[5] + R[7]) / s;
+    } else {
+        const double s = 2.0 * sqrt(fmax(1.0 - R[0] - R[4] + R[8], 0.0));
+        w = (R[3] - R[1]) / s;
+        x = (R[2] + R[6]) / s;
+        y = (R[5] + R[7]) / s;
+        z = 0.25 * s;
+    }
+    const double nn = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+    const double sg = w < 0.0 ? -nn : nn;
+    q[0] = w * sg;
+    q[1] = x * sg;
+    q[2] = y * sg;
+    q[3] = z * sg;
+}
+
+struct TriArgs {
+    const float2* mu_new;
+    const float* cov_new;
+    const uint8_t* vflags;
+    const float* acc;
+    const ushort4* rect;
+    const float* means_in;
+    const float* quats_in;
+    const float* scales_in;
+    float* means_out;
+    float* quats_out;
+    float* scales_out;
+    uint32_t* status;
+    int64_t N;
+    int V;
+    int scale_mode;
+};
+
+__global__ void __launch_bounds__(128) k_triangulate(TriArgs a, CamPack cams, tg_params prm)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.N) return;
+    const float om0 = a.means_in[3 * g], om1 = a.means_in[3 * g + 1], om2 = a.means_in[3 * g + 2];
+    const float oq0 = a.quats_in[4 * g], oq1 = a.quats_in[4 * g + 1], oq2 = a.quats_in[4 * g + 2],
+                oq3 = a.quats_in[4 * g + 3];
+    const float os0 = a.scales_in[3 * g], os1 = a.scales_in[3 * g + 1], os2 = a.scales_in[3 * g + 2];
+    float nm[3] = {om0, om1, om2};
+    float nq[4] = {oq0, oq1, oq2, oq3};
+    float ns[3] = {os0, os1, os2};
+    uint32_t st = 0;
+
+    // ---- totals and DLT normal matrix (4x4, upper triangle)
+    double M[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) M[i] = 0.0;
+    int nv = 0;
+    double sw = 0.0, nt = 0.0;
+    for (int v = 0; v < a.V; ++v) {
+        const int64_t o = (int64_t)v * a.N + g;
+        const ushort4 r = a.rect[o];
+        if (r.z > r.x && r.w > r.y) {
+            sw += (double)a.acc[o * TG_ACC_STRIDE + 0];
+            nt += (double)a.acc[o * TG_ACC_STRIDE + 12];
+        }
+        if (a.vflags[o] != 1) continue;
+        ++nv;
+        const tg_camera& c = cams.cam[v];
+        const float2 mu = a.mu_new[o];
+        const double xn = ((double)mu.x - c.cx) / c.fx, yn = ((double)mu.y - c.cy) / c.fy;
+        double r1[4], r2[4];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            r1[j] = xn * c.R[6 + j] - c.R[j];
+            r2[j] = yn * c.R[6 + j] - c.R[3 + j];
+        }
+        r1[3] = xn * c.t[2] - c.t[0];
+        r2[3] = yn * c.t[2] - c.t[1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) M[i * 4 + j] += r1[i] * r1[j] + r2[i] * r2[j];
+    }
+    if (nv < prm.views_min) st |= 4;
+    if (!(sw >= prm.wsum_total_min)) st |= 8;
+    if (nt < (double)prm.pix_total_min) st |= 16;
+    if (st == 0) {
+        double E[16];
+        jacobi_eig<4>(M, E);
+        int kmin = 0;
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (M[k * 4 + k] < M[kmin * 4 + kmin]) kmin = k;
+        double h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = E[i * 4 + kmin];
+        const double hn = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2] + h[3] * h[3]);
+        if (!(fabs(h[3]) >= 1e-12 * hn)) st |= 64;
+        double mu3[3] = {0, 0, 0};
+        if (st == 0) {
+            mu3[0] = h[0] / h[3];
+            mu3[1] = h[1] / h[3];
+            mu3[2] = h[2] / h[3];
+            for (int v = 0; v < a.V; ++v) {
+                if (a.vflags[(int64_t)v * a.N + g] != 1) continue;
+                const tg_camera& c = cams.cam[v];
+                const double pz = c.R[6] * mu3[0] + c.R[7] * mu3[1] + c.R[8] * mu3[2] + c.t[2];
+                if (!(pz > prm.near_z)) st |= 128;
+            }
+        }
+        if (st == 0) {
+            st |= 1;
+            nm[0] = (float)mu3[0];
+            nm[1] = (float)mu3[1];
+            nm[2] = (float)mu3[2];
+            // ---- covariance system: unknowns (S00, S01, S02, S11, S12, S22)
+            double AtA[36], Atb[6];
+#pragma unroll
+            for (int i = 0; i < 36; ++i) AtA[i] = 0.0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Atb[i] = 0.0;
+            for (int v = 0; v < a.V; ++v) {
+                const int64_t o = (int64_t)v * a.N + g;
+                if (a.vflags[o] != 1) continue;
+                const tg_camera& c = cams.cam[v];
+                double p[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    p[i] = c.R[3 * i] * mu3[0] + c.R[3 * i + 1] * mu3[1] + c.R[3 * i + 2] * mu3[2] + c.t[i];
+                const double limx = (double)prm.j_clamp * (0.5 * c.width / (double)c.fx);
+                const double limy = (double)prm.j_clamp * (0.5 * c.height / (double)c.fy);
+                const double tx = fmin(limx, fmax(-limx, p[0] / p[2]));
+                const double ty = fmin(limy, fmax(-limy, p[1] / p[2]));
+                const double J00 = c.fx / p[2], J02 = -c.fx * tx / p[2];
+                const double J11 = c.fy / p[2], J12 = -c.fy * ty / p[2];
+                double T0[3], T1[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    T0[j] = J00 * c.R[j] + J02 * c.R[6 + j];
+                    T1[j] = J11 * c.R[3 + j] + J12 * c.R[6 + j];
+                }
+                const double rhs[3] = {a.cov_new[3 * o], a.cov_new[3 * o + 1], a.cov_new[3 * o + 2]};
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const double* Ta = e == 2 ? T1 : T0;
+                    const double* Tb = e == 0 ? T0 : T1;
+                    double row[6];
+                    row[0] = Ta[0] * Tb[0];
+                    row[1] = Ta[0] * Tb[1] + Ta[1] * Tb[0];
+                    row[2] = Ta[0] * Tb[2] + Ta[2] * Tb[0];
+                    row[3] = Ta[1] * Tb[1];
+                    row[4] = Ta[1] * Tb[2] + Ta[2] * Tb[1];
+                    row[5] = Ta[2] * Tb[2];
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) {
+                        Atb[i] += row[i] * rhs[e];
+#pragma unroll
+                        for (int j = 0; j < 6; ++j) AtA[i * 6 + j] += row[i] * row[j];
+                    }
+                }
+            }
+            // Cholesky AtA = L L^T
+            double dmax = 0.0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) dmax = fmax(dmax, AtA[i * 6 + i]);
+            bool pd = dmax > 0.0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                double d = AtA[j * 6 + j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) d -= AtA[j * 6 + k] * AtA[j * 6 + k];
+                if (!(d > 1e-24 * dmax)) pd = false;
+                d = sqrt(fmax(d, 1e-300));
+                AtA[j * 6 + j] = d;
+#pragma unroll
+                for (int i = j + 1; i < 6; ++i) {
+                    double s = AtA[i * 6 + j];
+#pragma unroll
+                    for (int k = 0; k < j; ++k) s -= AtA[i * 6 + k] * AtA[j * 6 + k];
+                    AtA[i * 6 + j] = s / d;
+                }
+            }
+            double sol[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {  // forward
+                double s = Atb[i];
+#pragma unroll
+                for (int k = 0; k < i; ++k) s -= AtA[i * 6 + k] * sol[k];
+                sol[i] = s / AtA[i * 6 + i];
+            }
+#pragma unroll
+            for (int i = 5; i >= 0; --i) {  // backward
+                double s = sol[i];
+#pragma unroll
+                for (int k = i + 1; k < 6; ++k) s -= AtA[k * 6 + i] * sol[k];
+                sol[i] = s / AtA[i * 6 + i];
+            }
+            double S[9] = {sol[0], sol[1], sol[2], sol[1], sol[3], sol[4], sol[2], sol[4], sol[5]};
+            double Ev[9];
+            jacobi_eig<3>(S, Ev);
+            double lam[3] = {S[0], S[4], S[8]};
+            if (!pd || !(lam[0] > 0.0 && lam[1] > 0.0 && lam[2] > 0.0)) {
+                st |= 32;
+            } else {
+                // ascending eigen-order (stable for ties)
+                int ord[3] = {0, 1, 2};
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2 - i; ++j)
+                        if (lam[ord[j + 1]] < lam[ord[j]]) {
+                            int t = ord[j]; ord[j] = ord[j + 1]; ord[j + 1] = t;
+                        }
+                // rank of each old scale among the old scales (stable)
+                const float so[3] = {os0, os1, os2};
+                int rk[3];
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    int r = 0;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        if (so[j] < so[kx] || (so[j] == so[kx] && j < kx)) ++r;
+                    rk[kx] = r;
+                }
+                // old rotation (FP64, normalised quaternion)
+                const double qn = sqrt((double)oq0 * oq0 + (double)oq1 * oq1 + (double)oq2 * oq2 + (double)oq3 * oq3);
+                const double w = oq0 / qn, x = oq1 / qn, y = oq2 / qn, z = oq3 / qn;
+                const double Ro[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                                      2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                                      2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+                double Rn[9], sc[3], dots[3];
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int e = ord[rk[kx]];
+                    double dt = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        Rn[i * 3 + kx] = Ev[i * 3 + e];
+                        dt += Ev[i * 3 + e] * Ro[i * 3 + kx];
+                    }
+                    if (dt < 0.0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) Rn[i * 3 + kx] = -Rn[i * 3 + kx];
+                        dt = -dt;
+                    }
+                    dots[kx] = dt;
+                    sc[kx] = lam[e];
+                }
+                const double det = Rn[0] * (Rn[4] * Rn[8] - Rn[5] * Rn[7]) - Rn[1] * (Rn[3] * Rn[8] - Rn[5] * Rn[6]) +
+                                   Rn[2] * (Rn[3] * Rn[7] - Rn[4] * Rn[6]);
+                if (det < 0.0) {
+                    int km = 0;
+                    if (dots[1] < dots[km]) km = 1;
+                    if (dots[2] < dots[km]) km = 2;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) Rn[i * 3 + km] = -Rn[i * 3 + km];
+                }
+                double qq[4];
+                quat_from_rot(Rn, qq);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) nq[i] = (float)qq[i];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) ns[i] = a.scale_mode == 1 ? (float)(0.5 * log(sc[i])) : (float)sqrt(sc[i]);
+                st |= 2;
+            }
+        }
+    }
+    a.means_out[3 * g] = nm[0];
+    a.means_out[3 * g + 1] = nm[1];
+    a.means_out[3 * g + 2] = nm[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a.quats_out[4 * g + i] = nq[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a.scales_out[3 * g + i] = ns[i];
+    if (a.status) a.status[g] = st;
+}
+
+}  // namespace
+
+extern "C" tg_status tg_solve_views(const float* acc, const tg_splats* s, int64_t N, int32_t V, const tg_params* p,
+                                    float* mu2d_new, float* cov2d_new, uint8_t* vflags, void* stream)
+{
+    if (!acc || !s || !p || !mu2d_new || !cov2d_new || !vflags || N < 0 || V < 1) return TG_ERR_INVALID_ARG;
+    if (!s->rec || !s->cov2d || !s->rect) return TG_ERR_INVALID_ARG;
+    if (!aligned16(acc) || !aligned16(s->rec) || ((uintptr_t)mu2d_new & 7u)) return TG_ERR_ALIGNMENT;
+    const int64_t VN = (int64_t)V * N;
+    if (VN == 0) return TG_OK;
+    hipLaunchKernelGGL(k_solve_views, dim3((unsigned)((VN + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       (const float4*)acc, (const float4*)s->rec, s->cov2d, (const ushort4*)s->rect, VN, *p,
+                       (float2*)mu2d_new, cov2d_new, vflags);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}
+
+extern "C" tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_new, const uint8_t* vflags,
+                                    const float* acc, const tg_splats* s, const tg_gaussians* g_in, int64_t N,
+                                    const tg_camera* cams, int32_t V, const tg_params* p, tg_gaussians* g_out,
+                                    uint32_t* status, void* stream)
+{
+    if (!mu2d_new || !cov2d_new || !vflags || !acc || !s || !g_in || !cams || !p || !g_out || N < 0 || V < 1)
+        return TG_ERR_INVALID_ARG;
+    if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
+    if (!s->rect || !g_in->means || !g_in->quats || !g_in->scales || !g_out->means || !g_out->quats ||
+        !g_out->scales)
+        return TG_ERR_INVALID_ARG;
+    if (g_in->scale_mode < 0 || g_in->scale_mode > 1) return TG_ERR_INVALID_ARG;
+    if (((uintptr_t)mu2d_new & 7u)) return TG_ERR_ALIGNMENT;
+    if (N == 0) return TG_OK;
+    TriArgs a;
+    a.mu_new = (const float2*)mu2d_new;
+    a.cov_new = cov2d_new;
+    a.vflags = vflags;
+    a.acc = acc;
+    a.rect = (const ushort4*)s->rect;
+    a.means_in = g_in->means;
+    a.quats_in = g_in->quats;
+    a.scales_in = g_in->scales;
+    a.means_out = g_out->means;
+    a.quats_out = g_out->quats;
+    a.scales_out = g_out->scales;
+    a.status = status;
+    a.N = N;
+    a.V = V;
+    a.scale_mode = g_in->scale_mode;
+    CamPack cp;
+    for (int v = 0; v < V; ++v) cp.cam[v] = cams[v];
+    hipLaunchKernelGGL(k_triangulate, dim3((unsigned)((N + 127) / 128)), dim3(128), 0, (hipStream_t)stream, a, cp,
+                       *p);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}

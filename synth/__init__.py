@@ -311,11 +311,13 @@ def body_field_motion(rng, scene: Scene, cams, *, n_bodies=8, ball_radius=2.0,
 # --------------------------------------------------------------------------
 # proxy track fields
 # --------------------------------------------------------------------------
-def _surface_points(cam: Camera, radius):
+def _surface_points(cam: Camera, radius, xs=None, ys=None):
     """First intersection of each pixel ray with the sphere |x| = radius
-    (closest approach to the origin where the ray misses)."""
-    H, W = cam.H, cam.W
-    cc, rr = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    (closest approach to the origin where the ray misses).  xs/ys select a
+    lattice of pixel columns/rows (default: every pixel)."""
+    xs = np.arange(cam.W, dtype=np.float64) if xs is None else np.asarray(xs, np.float64)
+    ys = np.arange(cam.H, dtype=np.float64) if ys is None else np.asarray(ys, np.float64)
+    cc, rr = np.meshgrid(xs, ys)
     dirc = np.stack([(cc - cam.cx) / cam.fx, (rr - cam.cy) / cam.fy, np.ones_like(cc)], -1)
     R = cam.R.astype(np.float64)
     dw = dirc @ R                    # camera -> world direction (R^T d)
@@ -330,30 +332,58 @@ def _surface_points(cam: Camera, radius):
     return o + dw * s[..., None]
 
 
+def _lattice(n, stride):
+    xs = np.arange(0, n, stride)
+    if xs[-1] != n - 1:
+        xs = np.append(xs, n - 1)
+    return xs
+
+
+def _lerp_axis(a, nodes, n, axis):
+    """Linear interpolation of `a` sampled at `nodes` along `axis` to 0..n-1."""
+    f = np.arange(n, dtype=np.float64)
+    i0 = np.clip(np.searchsorted(nodes, f, side="right") - 1, 0, len(nodes) - 2)
+    t = (f - nodes[i0]) / (nodes[i0 + 1] - nodes[i0])
+    a0 = np.take(a, i0, axis=axis)
+    a1 = np.take(a, i0 + 1, axis=axis)
+    shape = [1] * a.ndim
+    shape[axis] = n
+    t = t.reshape(shape)
+    return a0 * (1.0 - t) + a1 * t
+
+
 def proxy_tracks(rng, cams, motion_fn, *, radius, noise_px=0.5, outlier_rate=0.0,
-                 vis_rate=1.0, cap_px=None):
-    """disp[V,H,W,2] float32 and vis[V,H,W] uint8 for every first-frame pixel."""
+                 vis_rate=1.0, cap_px=None, stride=4):
+    """disp[V,H,W,2] float32 and vis[V,H,W] uint8 for every first-frame pixel.
+
+    The smooth ground-truth flow is evaluated on a lattice of every
+    `stride`-th pixel and interpolated bilinearly; noise, outliers and
+    visibility are drawn per pixel."""
     V = len(cams)
     H, W = cams[0].H, cams[0].W
     disp = np.empty((V, H, W, 2), np.float32)
     vis = np.empty((V, H, W), np.uint8)
-    cc, rr = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
-    x0 = np.stack([cc, rr], -1)
+    xs, ys = _lattice(W, stride), _lattice(H, stride)
+    gx, gy = np.meshgrid(xs.astype(np.float64), ys.astype(np.float64))
+    x0 = np.stack([gx, gy], -1)
     for v, cam in enumerate(cams):
-        X = _surface_points(cam, radius)
+        X = _surface_points(cam, radius, xs, ys)
         Xm = motion_fn(X.reshape(-1, 3)).reshape(X.shape)
         x1, _ = _pinhole(cam, Xm)
-        d = x1 - x0
+        dl = x1 - x0
         if cap_px is not None:
-            m = np.linalg.norm(d, axis=-1, keepdims=True)
-            d = np.where(m > cap_px, d * (cap_px / np.maximum(m, 1e-30)), d)
+            m = np.linalg.norm(dl, axis=-1, keepdims=True)
+            dl = np.where(m > cap_px, dl * (cap_px / np.maximum(m, 1e-30)), dl)
+        d = _lerp_axis(_lerp_axis(dl, xs, W, 1), ys, H, 0).astype(np.float32)
         if noise_px > 0:
-            d = d + rng.normal(0.0, noise_px, d.shape)
+            d += rng.normal(0.0, noise_px, d.shape).astype(np.float32)
         if outlier_rate > 0:
             om = rng.random((H, W)) < outlier_rate
-            tgt = np.stack([rng.uniform(0, W, (H, W)), rng.uniform(0, H, (H, W))], -1)
-            d = np.where(om[..., None], tgt - x0, d)
-        disp[v] = d.astype(np.float32)
+            k = int(om.sum())
+            rr, cc = np.nonzero(om)
+            d[rr, cc, 0] = (rng.uniform(0, W, k) - cc).astype(np.float32)
+            d[rr, cc, 1] = (rng.uniform(0, H, k) - rr).astype(np.float32)
+        disp[v] = d
         if vis_rate < 1.0:
             vis[v] = (rng.random((H, W)) < vis_rate).astype(np.uint8)
         else:

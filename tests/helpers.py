@@ -1,0 +1,117 @@
+"""Shared helpers for the GPU parity tests (HIP path vs the CPU oracle).
+
+Inputs come from `synth` only; expected values from `oracle` only.
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(wl, capacity=None, t_final=True, stats=True, params=None, vis=True, disp=None):
+    """Cold frame on the GPU; returns a dict of host arrays."""
+    import torch
+    from paper_2604_02586_amd import api
+    dev = torch.device("cuda:0")
+    g = api.GaussianTensors.from_scene(wl.scene, dev)
+    mt = api.MotionTransfer(wl.cams, wl.scene.n, dev, params=params, capacity=capacity)
+    d = torch.as_tensor(wl.disp if disp is None else disp).to(dev).contiguous()
+    vv = torch.as_tensor(wl.vis).to(dev).contiguous() if vis else None
+    out = mt.run(g, d, vv, t_final=t_final, stats=stats)
+    torch.cuda.synchronize()
+    h = lambda t: t.detach().cpu().numpy()
+    res = dict(mt=mt, rec=h(mt.splats.rec), cov2d=h(mt.splats.cov2d),
+                rect=h(mt.splats.rect).view(np.uint16), key=h(mt.splats.key).view(np.uint32),
+                order=h(mt.bins.order).view(np.uint32), cell_ids=h(mt.bins.cell_ids).view(np.uint32),
+                cell_ranges=h(mt.bins.cell_ranges).view(np.uint32), n_pairs=int(mt.bins.n_pairs.item()),
+                overflow=int(mt.bins.overflow.item()), acc=h(mt.acc),
+                t_final=h(mt.t_final) if t_final else None, stats=h(mt.stats),
+                mu_new=h(mt.mu_new), cov_new=h(mt.cov_new), vflags=h(mt.vflags),
+                status=h(mt.status).view(np.uint32), means=h(out.means), quats=h(out.quats),
+                scales=h(out.scales))
+    return res
+
+
+def dump(name, res):
+    """Save GPU results for offline analysis when TG_DUMP_DIR is set."""
+    import os
+    d = os.environ.get("TG_DUMP_DIR")
+    if not d:
+        return
+    os.makedirs(d, exist_ok=True)
+    np.savez_compressed(os.path.join(d, f"{name}.npz"),
+                        **{k: v for k, v in res.items() if isinstance(v, np.ndarray)})
+
+
+def compare_accumulators(acc, comp, rel=1e-4):
+    """|gpu - oracle| <= rel * sum|term| + slack per entry (slack covers
+    decisions within a band of their thresholds); counts within the number
+    of marginal decisions.  Returns (n_bad, n_checked, info)."""
+    mom, absm, slack, nmarg = comp["mom"], comp["absm"], comp["slack"], comp["nmarg"]
+    a = acc[..., :15].astype(np.float64)
+    m = mom[..., :15]
+    tol = rel * absm[..., :15] + slack[..., :15] + 1e-30
+    err = np.abs(a - m)
+    bad = err > tol
+    # counts (slots 12, 13) are integers: exact up to marginal decisions
+    cnt_bad = np.abs(a[..., 12] - m[..., 12]) > nmarg
+    bad[..., 12] = cnt_bad
+    bad_rec = bad.any(-1)
+    info = dict(worst=float((err / tol)[..., :12].max()) if err.size else 0.0,
+                marginal_frac=float((slack[..., 0] > 0).mean()),
+                bad_entries=int(bad.sum()))
+    return int(bad_rec.sum()), int(bad_rec.size), info
+
+
+def oracle_full(wl, raw=False):
+    return oracle.motion_transfer(wl.scene, wl.cams, wl.disp, wl.vis, raw=raw)
+
+
+def rotation_angle_deg(qa, qb):
+    qa = qa / np.linalg.norm(qa, axis=-1, keepdims=True)
+    qb = qb / np.linalg.norm(qb, axis=-1, keepdims=True)
+    d = np.clip(np.abs((qa * qb).sum(-1)), 0, 1)
+    return np.degrees(2 * np.arccos(d))
+
+
+def sensitivity_mask(wl, ref, rel=1e-5, seeds=(1, 2), pos_tol=1e-3, rot_tol=0.05):
+    """Gaussians whose oracle result moves by more than half the tolerance
+    when the oracle's own FP64 accumulators are perturbed by `rel` (the size
+    of FP32 accumulation error).  Those results are not determined at FP32
+    input precision and are excluded from strict comparison."""
+    comp, geom, cov = ref["comp"], ref["geom"], ref["cov"]
+    unstable = np.zeros(wl.scene.n, bool)
+    for s in seeds:
+        rng = np.random.default_rng(s)
+        mom = comp["mom"] * (1.0 + rel * rng.standard_normal(comp["mom"].shape))
+        # decisions within a band of their thresholds may go the other way in
+        # FP32: move each entry anywhere inside its slack bound, and the pixel
+        # counts by up to the number of such decisions
+        mom = mom + comp["slack"] * rng.uniform(-1.0, 1.0, comp["mom"].shape)
+        mom[..., 12:] = comp["mom"][..., 12:]
+        mom[..., 12] += np.round(comp["nmarg"] * rng.uniform(-1.0, 1.0, comp["nmarg"].shape))
+        sv = oracle.solve_views(mom, geom.mu, cov, geom.valid)
+        tri = oracle.triangulate(wl.scene, wl.cams, sv, mom, geom.valid)
+        t0 = ref["tri"]
+        unstable |= tri["status"] != t0["status"]
+        unstable |= np.linalg.norm(tri["means"] - t0["means"], axis=-1) > 0.5 * pos_tol
+        ang = rotation_angle_deg(tri["quats"], t0["quats"])
+        unstable |= ang > 0.5 * rot_tol
+        unstable |= np.abs(tri["scales"] / t0["scales"] - 1).max(-1) > 1e-3
+        unstable |= (sv["flags"] != ref["sv"]["flags"]).any(0)
+    return unstable
+
+
+def eigen_gap(eig):
+    e = np.sort(eig, axis=-1)
+    return np.minimum(e[..., 1] - e[..., 0], e[..., 2] - e[..., 1]) / np.maximum(e[..., 2], 1e-300)

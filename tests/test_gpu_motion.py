@@ -1,0 +1,160 @@
+"""GPU parity of the motion-transfer path (HIP via the C ABI) against the
+CPU oracle, stage by stage and end to end, on seeded synthetic inputs."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import (compare_accumulators, dump, eigen_gap, log, oracle_full, rotation_angle_deg, run_gpu,
+                     sensitivity_mask)
+
+pytestmark = pytest.mark.gpu
+
+# small sizes that still span several tiles and coarse bins plus a ragged tail
+CASES = {
+    "small": dict(name="small"),                                     # 2k G, 4 views, 128x128
+    "ragged": dict(name="small", seed=7, n=3000, views=3, width=333, height=250),
+    "medium_lite": dict(name="medium", seed=5, n=20000, views=5, width=420, height=300),
+}
+
+
+def _workload(case):
+    kw = dict(CASES[case])
+    return synth.make_workload(kw.pop("name"), **kw)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request):
+    log(f"[case {request.param}] generating")
+    wl = _workload(request.param)
+    log(f"[case {request.param}] oracle")
+    ref = oracle_full(wl)
+    log(f"[case {request.param}] gpu")
+    gpu = run_gpu(wl)
+    dump(request.param, gpu)
+    log(f"[case {request.param}] ready")
+    return request.param, wl, ref, gpu
+
+
+def test_preprocess_parity(pair):
+    case, wl, ref, gpu = pair
+    g = ref["geom"]
+    valid = g.valid.astype(bool)
+    rect = gpu["rect"].astype(np.int32)
+    gvalid = (rect[..., 2] > rect[..., 0]) & (rect[..., 3] > rect[..., 1])
+    np.testing.assert_array_equal(gvalid, valid)
+    # integer-deciding FP32 quantities: bit-exact
+    np.testing.assert_array_equal(gpu["key"][valid], g.key[valid])
+    np.testing.assert_array_equal(rect[valid], g.rect[valid])
+    np.testing.assert_array_equal(gpu["rec"][..., 0:2][valid].view(np.uint32), g.mu[valid].view(np.uint32))
+    # FP64-formed conic / covariance, rounded once to FP32
+    conic = gpu["rec"][..., 2:5][valid].astype(np.float64)
+    np.testing.assert_allclose(conic, ref["conic"][valid], rtol=2e-6, atol=1e-9 * np.abs(ref["conic"]).max())
+    cov = gpu["cov2d"][valid].astype(np.float64)
+    scale = np.abs(ref["cov"][valid]).max(-1, keepdims=True)
+    assert np.all(np.abs(cov - ref["cov"][valid]) <= 2e-6 * scale + 1e-12)
+    np.testing.assert_array_equal(gpu["rec"][..., 5][valid], np.broadcast_to(wl.scene.opacity, valid.shape)[valid])
+
+
+def test_bin_sort_bit_exact(pair):
+    case, wl, ref, gpu = pair
+    V, N = ref["geom"].key.shape
+    assert gpu["overflow"] == 0
+    orders = oracle.depth_order(ref["geom"])
+    for v in range(V):
+        o = orders[v]
+        np.testing.assert_array_equal(gpu["order"][v, :o.size], o)
+    mt = gpu["mt"]
+    cell = 1 << 3
+    starts, ids = oracle.cell_lists(ref["geom"], wl.cams, cell)
+    assert gpu["n_pairs"] == ids.size
+    rg = gpu["cell_ranges"].reshape(-1, 2)
+    assert rg.shape[0] == starts.size - 1
+    for c in range(rg.shape[0]):
+        a, b = int(starts[c]), int(starts[c + 1])
+        if a == b:
+            assert rg[c, 0] == rg[c, 1]
+            continue
+        np.testing.assert_array_equal(gpu["cell_ids"][rg[c, 0]:rg[c, 1]], ids[a:b])
+    # expanded per-tile lists equal the brute-force per-tile lists
+    from paper_2604_02586_amd import api
+    tids, tr = api.bin_expand(mt.splats, mt.bins, N, wl.cams, mt.params)
+    tids = tids.cpu().numpy().view(np.uint32)
+    tr = tr.cpu().numpy().view(np.uint32)
+    ts, tl = oracle.cell_lists(ref["geom"], wl.cams, 1)
+    assert tids.size == tl.size
+    for t in range(tr.shape[0]):
+        np.testing.assert_array_equal(tids[tr[t, 0]:tr[t, 1]], tl[ts[t]:ts[t + 1]])
+
+
+def test_accumulate_parity(pair):
+    case, wl, ref, gpu = pair
+    comp = ref["comp"]
+    nbad, ntot, info = compare_accumulators(gpu["acc"], comp)
+    log(f"[{case}] accumulators: {nbad}/{ntot} outside tolerance, {info}")
+    assert nbad == 0, info
+    # final transmittance per pixel (Sigma w = 1 - T_final), marginal pixels excluded
+    ok = comp["pixmarg"] == 0
+    np.testing.assert_allclose(gpu["t_final"][ok], comp["tfinal"][ok], rtol=1e-4, atol=1e-6)
+    # pair counters: evaluated and contributing pairs in the sequential semantics
+    ev, ec = comp["counters"].sum(0)
+    assert abs(int(gpu["stats"][1]) - ec) <= max(3, 1e-4 * ec)
+    assert abs(int(gpu["stats"][0]) - ev) <= max(3, 1e-4 * ev)
+
+
+def test_solve_views_parity(pair):
+    case, wl, ref, gpu = pair
+    sv = ref["sv"]
+    comp = ref["comp"]
+    # flags agree except where the oracle's value sits within 1e-3 of a threshold
+    m = comp["mom"]
+    near = (np.abs(m[..., oracle.S_W] / oracle.WSUM_MIN - 1) < 1e-3) | \
+           (np.abs(sv["det"] / oracle.DET_MIN - 1) < 1e-2) | (comp["slack"][..., 0] > 0)
+    diff = (gpu["vflags"] != sv["flags"]) & ~near
+    assert diff.sum() <= max(2, 1e-3 * diff.size), (diff.sum(), diff.size)
+    both = (gpu["vflags"] == oracle.VF_OK) & (sv["flags"] == oracle.VF_OK) & ~near
+    # conditioning-aware: relative perturbation 1e-5 of the oracle's moments
+    V1, V2 = oracle.v1_v2(m)
+    cond = np.linalg.cond(np.where(both[..., None, None], V1, np.eye(3)))
+    well = both & (cond < 1e4)
+    err_mu = np.abs(gpu["mu_new"][well] - sv["mu_new"][well]).max(-1)
+    assert np.all(err_mu <= 1e-2 + 1e-6 * cond[well] * 10), err_mu.max()
+    log(f"[{case}] solve: {well.sum()} well-conditioned views, max |dmu'| = {err_mu.max():.2e} px")
+
+
+def test_end_to_end_parity(pair):
+    case, wl, ref, gpu = pair
+    tri = ref["tri"]
+    unstable = sensitivity_mask(wl, ref)
+    st_g, st_o = gpu["status"], tri["status"]
+    mism = (st_g != st_o) & ~unstable
+    log(f"[{case}] status mismatches {mism.sum()} / {st_o.size}; unstable excluded {unstable.sum()}")
+    assert mism.sum() <= max(2, 2e-3 * st_o.size)
+    pos = ((st_g & oracle.ST_POS) > 0) & ((st_o & oracle.ST_POS) > 0) & ~unstable
+    dpos = np.linalg.norm(gpu["means"][pos].astype(np.float64) - tri["means"][pos], axis=-1)
+    assert np.all(dpos <= 1e-3), dpos.max()
+    cov = ((st_g & oracle.ST_COV) > 0) & ((st_o & oracle.ST_COV) > 0) & ~unstable
+    gap = eigen_gap(tri["eig"])
+    rot = cov & (gap >= 1e-2)
+    ang = rotation_angle_deg(gpu["quats"][rot].astype(np.float64), tri["quats"][rot])
+    assert np.all(ang <= 0.05), ang.max()
+    assert np.all(gpu["quats"][rot][:, 0] >= 0)
+    # degenerate eigen-gap: compare Sigma_3D' instead
+    deg = cov & (gap < 1e-2)
+    if deg.any():
+        Rg = oracle.quat_to_rot(gpu["quats"][deg].astype(np.float64))
+        Ro = oracle.quat_to_rot(tri["quats"][deg])
+        Sg = Rg @ (gpu["scales"][deg][:, :, None] ** 2 * np.swapaxes(Rg, -1, -2))
+        So = Ro @ (tri["scales"][deg][:, :, None] ** 2 * np.swapaxes(Ro, -1, -2))
+        rel = np.linalg.norm(Sg - So, axis=(1, 2)) / np.linalg.norm(So, axis=(1, 2))
+        assert np.all(rel <= 1e-3), rel.max()
+    sc = np.abs(gpu["scales"][cov] / tri["scales"][cov] - 1)
+    assert np.all(sc <= 1e-3), sc.max()
+    # what was not updated is copied bit-exactly
+    keep = (st_g & oracle.ST_POS) == 0
+    np.testing.assert_array_equal(gpu["means"][keep], wl.scene.means[keep])
+    keepc = (st_g & oracle.ST_COV) == 0
+    np.testing.assert_array_equal(gpu["quats"][keepc], wl.scene.quats[keepc])
+    np.testing.assert_array_equal(gpu["scales"][keepc], wl.scene.scales[keepc])
+    log(f"[{case}] e2e: pos {pos.sum()} max {dpos.max() if dpos.size else 0:.2e}; rot {rot.sum()} "
+        f"max {ang.max() if ang.size else 0:.2e} deg")
