@@ -107,8 +107,8 @@ def main():
     # one untimed launch with pair counters
     mt.accumulate(disp, vis, stats=True)
     torch.cuda.synchronize()
-    e_eval, e_contrib = (int(x) for x in mt.stats.cpu())
-    log(f"  pairs evaluated {e_eval}, contributing {e_contrib}")
+    e_eval, e_contrib, n_steps, n_refill = (int(x) for x in mt.stats.cpu())
+    log(f"  pairs evaluated {e_eval}, contributing {e_contrib}, pixel steps {n_steps}, list refills {n_refill}")
 
     stream = torch.cuda.current_stream()
     names = ["preprocess", "bin_sort", "zero_acc", "accumulate", "solve", "triangulate"]
@@ -188,7 +188,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(frame_ms, 50)), "p99": float(np.percentile(frame_ms, 99))},
         "stages_ms": stage_ms,
         "hbm_fraction_of_frame": b_alg / (ms * 1e-3) / HBM_PEAK,
-        "pairs": {"coarse": n_pairs, "evaluated": e_eval, "contributing": e_contrib},
+        "pairs": {"coarse": n_pairs, "evaluated": e_eval, "contributing": e_contrib, "pixel_steps": n_steps, "list_refill_rounds": n_refill},
         "status": {"position_updated": float(((st & 1) > 0).mean()),
                    "covariance_updated": float(((st & 2) > 0).mean())},
         "roofline": {"kernel": "tg_splat_accumulate", "bound": "alu", "achieved": achieved / 1e12,

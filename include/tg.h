@@ -215,8 +215,11 @@ tg_status tg_bin_sort(const tg_splats* s, int64_t N, const tg_camera* cams, int3
  * uint8 or NULL (all visible).  All views must share one resolution.
  * acc: device [V,N,16] float32, zeroed by the caller (results are added).
  * t_final: device [V,H,W] or NULL: final transmittance per pixel.
- * stats: device int64 [2] or NULL: adds (pairs evaluated, pairs
- * contributing) over the launch.
+ * stats: device int64 [4] or NULL: adds (pairs evaluated, pairs
+ * contributing, pixel steps, list refill rounds) over the launch.  Evaluated pairs count the
+ * depth-ordered list entries visited up to each pixel's termination, after
+ * exact culling of Gaussians whose alpha stays below alpha_min on the whole
+ * tile; a pixel step evaluates one pixel against up to 64 Gaussians.
  */
 tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins, int64_t N,
                               const tg_camera* cams, int32_t V, const float* disp,
@@ -263,6 +266,49 @@ tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_new, const ui
                          const float* acc, const tg_splats* s, const tg_gaussians* g_in,
                          int64_t N, const tg_camera* cams, int32_t V, const tg_params* p,
                          tg_gaussians* g_out, uint32_t* status, void* stream);
+
+/*
+ * tg_raster_fwd -- forward rasteriser for the refinement (Sec. 4.6), same
+ * compositing rules as the motion path (Sec. 3.1): per pixel, in depth order,
+ * C = sum_i c_i alpha_i T_i + T_final bg.  s->colors must be filled
+ * (tg_preprocess with SH).  bg: host float[3] or NULL (black).
+ * image: device [V,H,W,3]; t_final: device [V,H,W] or NULL; n_proc: device
+ * int32 [V,H,W], the number of the tile's filtered depth-ordered entries the
+ * pixel processed (the backward replays exactly these).
+ */
+tg_status tg_raster_fwd(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams, int32_t V,
+                        const float* bg, const tg_params* p, float* image, float* t_final, int32_t* n_proc,
+                        void* stream);
+
+/*
+ * tg_raster_bwd -- gradients of a loss w.r.t. the 2D splats, given dL/dimage
+ * and the forward's image and n_proc.  grad2d: device [V,N,9], zeroed by the
+ * caller, receives (adds) per (view, Gaussian): dL/dmu_x, dL/dmu_y, dL/dconic
+ * (a, b, c; power = -1/2 (a dx^2 + c dy^2) - b dx dy), dL/dopacity (activated),
+ * dL/dcolour (r, g, b).  Clamped alpha (alpha_max) passes no gradient.
+ */
+tg_status tg_raster_bwd(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams, int32_t V,
+                        const float* image, const float* dl_dimage, const int32_t* n_proc, const tg_params* p,
+                        float* grad2d, void* stream);
+
+/*
+ * tg_project_bwd -- chain rule from the 2D splat gradients (grad2d) through
+ * Eq. 1 (EWA projection, Jacobian clamp, dilation), the SH colour (including
+ * the viewing-direction term; clamped channels pass nothing), the opacity and
+ * scale activations and the quaternion normalisation, summed over views.
+ * grads: device buffers with the layout of g (written, not added).
+ */
+tg_status tg_project_bwd(const tg_gaussians* g, const tg_splats* s, int64_t N, const tg_camera* cams, int32_t V,
+                         const float* grad2d, const tg_params* p, tg_gaussians* grads, void* stream);
+
+/* L1 loss: grad[i] = scale * sign(image[i] - target[i]); adds
+ * scale * sum |image - target| to *loss_sum (device float, nullable). */
+tg_status tg_l1_loss_grad(const float* image, const float* target, int64_t n, float scale, float* grad,
+                          float* loss_sum, void* stream);
+
+/* Adam (bias-corrected, step >= 1), in place on param, m, v. */
+tg_status tg_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                       float beta2, float eps, int32_t step, void* stream);
 
 /* Linear index of tiles and coarse bins, for tests and tools: expands the
  * coarse lists into the per-tile depth-ordered lists.  tile_ranges [T,2]

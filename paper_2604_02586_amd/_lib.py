@@ -82,12 +82,13 @@ def lib():
         "tg_solve_views": ([P, P, c_i64, c_i32, P, P, P, P, P], st),
         "tg_triangulate": ([P, P, P, P, P, P, c_i64, P, c_i32, P, P, P, P], st),
         "tg_bin_expand": ([P, P, c_i64, P, c_i32, P, P, P, c_i64, P, P, P, P], st),
-    }
-    optional = {
         "tg_raster_fwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),
-        "tg_raster_bwd": ([P, P, P, P, c_i64, P, c_i32, P, P, P, P, P, P, P], st),
+        "tg_raster_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),
+        "tg_project_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P], st),
         "tg_l1_loss_grad": ([P, P, c_i64, c_f, P, P, P], st),
         "tg_adam_step": ([P, P, P, P, c_i64, c_f, c_f, c_f, c_f, c_i32, P], st),
+    }
+    optional = {
         "tg_accumulate_batch": ([P, P, c_i64, P, c_i32, c_i32, P, P, P, P, c_i64, P, P], st),
     }
     for name, (args, res) in list(sig.items()) + list(optional.items()):
@@ -106,7 +107,8 @@ def lib():
 def exported_symbols():
     return [n for n in ("tg_abi_version", "tg_status_string", "tg_default_params", "tg_num_cells",
                         "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_splat_accumulate",
-                        "tg_solve_views", "tg_triangulate", "tg_bin_expand")]
+                        "tg_solve_views", "tg_triangulate", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
+                        "tg_project_bwd", "tg_l1_loss_grad", "tg_adam_step")]
 
 
 def check(fn, code):

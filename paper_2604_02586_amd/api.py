@@ -220,7 +220,7 @@ class MotionTransfer:
         self.vflags = torch.empty(*VN, dtype=torch.uint8, device=self.device)
         self.status = torch.empty(self.N, dtype=torch.int32, device=self.device)
         self.t_final = None
-        self.stats = torch.zeros(2, dtype=torch.int64, device=self.device)
+        self.stats = torch.zeros(4, dtype=torch.int64, device=self.device)
 
     def _alloc_bins(self, capacity):
         self.bins = BinTensors.alloc(self.V, self.N, self.n_cells, capacity, self.device)

@@ -27,7 +27,6 @@
 
 namespace {
 
-constexpr int ACC_WAVES = 4;
 constexpr int QCAP = 128;
 constexpr float LOG2E = 1.4426950408889634f;
 
@@ -37,7 +36,6 @@ struct AccArgs {
     const uint32_t* cell_ids;
     const uint2* ranges;
     const int32_t* overflow;
-    const float2* disp;
     const uint8_t* vis;
     float* acc;
     float* t_final;
@@ -50,18 +48,24 @@ struct AccArgs {
     float alpha_min, alpha_max, t_min, static2;
 };
 
-__global__ void __launch_bounds__(256) k_accumulate(AccArgs a, GridPack gp)
+// One wave (64 threads) per workgroup and per 16x16 tile, so tiles of very
+// different work never hold each other's resources.
+template <bool STATS>
+__global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const float2* __restrict__ disp)
 {
-    __shared__ uint32_t queue[ACC_WAVES][QCAP];
+    // 3.5 KB of LDS per wave keeps 8 waves per SIMD resident:
+    // queue of filtered list entries (ids), per-pixel column/row offsets
+    // inside the tile (as floats) and per-pixel transmittance
+    __shared__ uint32_t qi[QCAP];
+    __shared__ float2 CR[256];
+    __shared__ float T_[256];
     if (*a.overflow) return;
-    // XCD-aware remap: hardware places block b on XCD (b mod 8).
+    // XCD-aware remap: hardware places workgroup b on XCD (b mod 8); give
+    // each XCD a contiguous range of tiles (its L2 then holds those bins).
     const int64_t b = blockIdx.x;
-    const int64_t lb = (b & 7) * a.blocks_per_xcd + (b >> 3);
-    if (lb >= a.blocks) return;
-    const int w = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int64_t L = lb * ACC_WAVES + w;
+    const int64_t L = (b & 7) * a.blocks_per_xcd + (b >> 3);
     if (L >= a.n_enum) return;
+    const int lane = threadIdx.x;
     const int k = 1 << a.cshift;
     const int kk = k * k;
     const uint32_t gcell = (uint32_t)(L / kk);
@@ -81,25 +85,28 @@ __global__ void __launch_bounds__(256) k_accumulate(AccArgs a, GridPack gp)
     if (tx >= gp.tx[v] || ty >= gp.ty[v]) return;
     const uint2 rg = a.ranges[gcell];
     const int64_t vN = (int64_t)v * a.N;
+    const int px0 = tx * TG_TILE, py0 = ty * TG_TILE;
+    const int64_t row_base = (int64_t)v * a.H;
 
-    // pixel state: pixel j = g*64 + lane -> (tx*16 + (j&15), ty*16 + (j>>4))
-    float Tg[4], dxg[4], dyg[4];
+    // pixel state: pixel j = g*64 + lane -> (px0 + (j&15), py0 + (j>>4))
     uint64_t alive[4], visb[4], statb[4];
+    float dxg[4], dyg[4];   // track of pixel g*64 + lane
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int j = g * 64 + lane;
-        const int px = tx * TG_TILE + (j & 15), py = ty * TG_TILE + (j >> 4);
+        const int px = px0 + (j & 15), py = py0 + (j >> 4);
         const bool in = px < a.W && py < a.H;
         float ddx = 0.f, ddy = 0.f;
         bool vv = false;
         if (in) {
-            const int64_t pi = ((int64_t)v * a.H + py) * a.W + px;
-            float2 d = a.disp[pi];
+            const int64_t pi = (row_base + py) * a.W + px;
+            const float2 d = disp[pi];
             ddx = d.x;
             ddy = d.y;
             vv = a.vis ? a.vis[pi] != 0 : true;
         }
-        Tg[g] = 1.0f;
+        CR[j] = make_float2((float)(j & 15), (float)(j >> 4));
+        T_[j] = 1.0f;
         dxg[g] = ddx;
         dyg[g] = ddy;
         alive[g] = ballot64(in);
@@ -112,51 +119,65 @@ __global__ void __launch_bounds__(256) k_accumulate(AccArgs a, GridPack gp)
         }
         statb[g] = ballot64(in && s2 < a.static2);
     }
-    uint64_t n_eval = 0, n_contrib = 0;
-    const bool want_stats = a.stats != nullptr;
-
+    uint64_t n_eval = 0, n_contrib = 0, n_iter = 0, n_refill = 0;
+    const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min;
+    const float log_amin = __logf(amin);
     const uint64_t ltmask = lanemask_lt();
-    uint32_t* q = queue[w];
+    const bool lane0 = lane == 0;
+    float pex_reg = 1.0f;   // lane 0 is never written by the wave shift below
     int qn = 0;
     uint32_t pos = rg.x;
-    const float fx0 = (float)(tx * TG_TILE), fy0 = (float)(ty * TG_TILE);
+    // pixel-centre extent of the tile (conservative for the ellipse test)
+    const float ex0 = (float)px0, ex1 = (float)(px0 + TG_TILE - 1);
+    const float ey0 = (float)py0, ey1 = (float)(py0 + TG_TILE - 1);
+    // prefetched ids of the next 64 list entries
+    uint32_t nid = (pos + lane < rg.y) ? a.cell_ids[pos + lane] : 0xFFFFFFFFu;
 
     while ((alive[0] | alive[1] | alive[2] | alive[3]) != 0ull) {
-        // refill the queue with list entries whose rectangle contains this tile
+        // Refill: list entries whose rectangle contains this tile and whose
+        // alpha >= alpha_min region can reach it.  The second test is exact
+        // culling: q >= 2 ln(o / alpha_min) everywhere on the tile means
+        // alpha < alpha_min at every pixel, so the Gaussian neither adds nor
+        // attenuates (a margin keeps it conservative under FP32 rounding).
         while (qn < 64 && pos < rg.y) {
+            const uint32_t gid = nid;
             const uint32_t i = pos + lane;
+            pos += 64;
+            nid = (pos + lane < rg.y) ? a.cell_ids[pos + lane] : 0xFFFFFFFFu;
             bool hit = false;
-            uint32_t gid = 0;
-            if (i < rg.y) {
-                gid = a.cell_ids[i];
-                if (gid < (uint64_t)a.N) {
-                    const ushort4 r = a.rect[vN + gid];
-                    hit = tx >= r.x && tx < r.z && ty >= r.y && ty < r.w;
-                }
+            if (i < rg.y && gid < (uint64_t)a.N) {
+                const ushort4 r = a.rect[vN + gid];
+                hit = tx >= r.x && tx < r.z && ty >= r.y && ty < r.w;
+                if (hit)
+                    hit = splat_reaches_tile(a.rec[2 * (vN + gid)], a.rec[2 * (vN + gid) + 1], log_amin, amin, ex0,
+                                             ex1, ey0, ey1);
             }
             const uint64_t m = ballot64(hit);
-            if (hit) q[qn + __popcll(m & ltmask)] = gid;
+            if (hit) qi[qn + __popcll(m & ltmask)] = gid;
             qn += __popcll(m);
-            pos += 64;
+            if (STATS) n_refill += 1;
         }
         if (qn == 0) break;
         const int nb = qn < 64 ? qn : 64;
-        const uint32_t gid = lane < nb ? q[lane] : 0u;
-        const uint32_t moved = (lane + 64 < qn) ? q[lane + 64] : 0u;
-        if (lane + 64 < qn) q[lane] = moved;
-        qn -= nb;
-
-        float mx = 0.f, my = 0.f, ca = 0.f, cb = 0.f, cc = 0.f, op = 0.f;
+        uint32_t gid = 0;
+        float dxl = 0.f, dyl = 0.f, ca = 0.f, cb = 0.f, cc = 0.f, op = 0.f;
         if (lane < nb) {
+            gid = qi[lane];
             const float4 r0 = a.rec[2 * (vN + gid)];
             const float4 r1 = a.rec[2 * (vN + gid) + 1];
-            mx = r0.x;
-            my = r0.y;
+            dxl = (float)px0 - r0.x;   // u = (px0 + column) - mu_x
+            dyl = (float)py0 - r0.y;
             ca = -0.5f * LOG2E * r0.z;
             cb = -LOG2E * r0.w;
             cc = -0.5f * LOG2E * r1.x;
             op = r1.y;
         }
+        if (lane + 64 < qn) {
+            const uint32_t g2 = qi[lane + 64];
+            qi[lane] = g2;
+        }
+        qn -= nb;
+
         float s_w = 0.f, s_ux = 0.f, s_uy = 0.f, s_xx = 0.f, s_xy = 0.f, s_yy = 0.f;
         float s_dx = 0.f, s_dy = 0.f, s_xdx = 0.f, s_xdy = 0.f, s_ydx = 0.f, s_ydy = 0.f;
         float s_n = 0.f, s_sn = 0.f, s_sa = 0.f;
@@ -164,60 +185,110 @@ __global__ void __launch_bounds__(256) k_accumulate(AccArgs a, GridPack gp)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             uint64_t m = alive[g];
+            uint64_t dead = 0;
+            const uint64_t vg = visb[g], sg = statb[g];
+            // two pixels per step: their dependency chains interleave
             while (m) {
-                const int j = __builtin_ctzll(m);
+                const int j1 = __builtin_ctzll(m);
                 m &= m - 1;
-                const int pj = g * 64 + j;
-                const float T = readlane_f(Tg[g], j);
-                const float ddx = readlane_f(dxg[g], j);
-                const float ddy = readlane_f(dyg[g], j);
-                const float ux = (fx0 + (float)(pj & 15)) - mx;
-                const float uy = (fy0 + (float)(pj >> 4)) - my;
-                const float p2 = ux * (ca * ux + cb * uy) + cc * uy * uy;
-                const float al = fminf(a.alpha_max, op * __builtin_amdgcn_exp2f(p2));
-                const bool valid = (p2 <= 0.0f) && (al >= a.alpha_min);
-                const float qv = valid ? 1.0f - al : 1.0f;
-                const float P = wave_scan_mul(qv);
-                const uint64_t tm = ballot64(valid && (T * P < a.t_min));
-                uint64_t cm = ballot64(valid);
-                float Tn;
-                if (tm) {
-                    const int kt = __builtin_ctzll(tm);
-                    cm &= (kt == 0) ? 0ull : (~0ull >> (64 - kt));
-                    Tn = kt == 0 ? T : T * readlane_f(P, kt - 1);
-                    alive[g] &= ~(1ull << j);
-                    if (want_stats) n_eval += (uint64_t)(kt + 1);
-                } else {
-                    Tn = T * readlane_f(P, 63);
-                    if (want_stats) n_eval += (uint64_t)nb;
+                const bool two = m != 0;
+                const int j2 = two ? (int)__builtin_ctzll(m) : j1;
+                if (two) m &= m - 1;
+                const int p1 = g * 64 + j1, p2i = g * 64 + j2;
+                const float2 cr1 = CR[p1], cr2 = CR[p2i];
+                const float T1 = T_[p1], T2 = T_[p2i];
+                const float ux1 = dxl + cr1.x, uy1 = dyl + cr1.y;
+                const float ux2 = dxl + cr2.x, uy2 = dyl + cr2.y;
+                const float q1 = ux1 * (ca * ux1 + cb * uy1) + cc * uy1 * uy1;
+                const float q2 = ux2 * (ca * ux2 + cb * uy2) + cc * uy2 * uy2;
+                // alpha = min(alpha_max, o e^power), clamped with one v_med3
+                const float al1 = __builtin_amdgcn_fmed3f(op * __builtin_amdgcn_exp2f(q1), 0.0f, amax);
+                const float al2 = __builtin_amdgcn_fmed3f(op * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
+                // valid lanes: power <= 0 and alpha >= alpha_min
+                const uint64_t vm1 = ballot64(q1 <= 0.0f) & ballot64(al1 >= amin);
+                const uint64_t vm2 = two ? (ballot64(q2 <= 0.0f) & ballot64(al2 >= amin)) : 0ull;
+                float P1 = __builtin_amdgcn_inverse_ballot_w64(vm1) ? 1.0f - al1 : 1.0f;
+                float P2 = __builtin_amdgcn_inverse_ballot_w64(vm2) ? 1.0f - al2 : 1.0f;
+                wave_scan_mul_fused2(P1, P2);
+                const uint64_t tm1 = ballot64(T1 * P1 < tmin) & vm1;
+                const uint64_t tm2 = ballot64(T2 * P2 < tmin) & vm2;
+                const int kt1 = (int)__builtin_ctzll(tm1 | (1ull << 63));
+                const int kt2 = (int)__builtin_ctzll(tm2 | (1ull << 63));
+                const uint64_t cm1 = vm1 & (tm1 ? ((1ull << kt1) - 1ull) : ~0ull);
+                const uint64_t cm2 = vm2 & (tm2 ? ((1ull << kt2) - 1ull) : ~0ull);
+                const float Pk1 = tm1 ? (kt1 == 0 ? 1.0f : readlane_f(P1, kt1 - 1)) : readlane_f(P1, 63);
+                const float Pk2 = tm2 ? (kt2 == 0 ? 1.0f : readlane_f(P2, kt2 - 1)) : readlane_f(P2, 63);
+                if (lane0) {
+                    T_[p1] = T1 * Pk1;
+                    if (two) T_[p2i] = T2 * Pk2;
                 }
-                Tg[g] = writelane_f(Tg[g], Tn, j);
-                if (want_stats) n_contrib += (uint64_t)__popcll(cm);
-                if (cm && ((visb[g] >> j) & 1ull)) {
-                    const float Pex = wave_shr1(P, 1.0f);
-                    if ((cm >> lane) & 1ull) {
-                        const float wgt = al * (T * Pex);
-                        const float wx = wgt * ux, wy = wgt * uy;
+                if (tm1) dead |= 1ull << j1;
+                if (tm2) dead |= 1ull << j2;
+                if (STATS) {
+                    n_eval += (uint64_t)(tm1 ? kt1 + 1 : nb);
+                    n_contrib += (uint64_t)__popcll(cm1);
+                    n_iter += 1;
+                    if (two) {
+                        n_eval += (uint64_t)(tm2 ? kt2 + 1 : nb);
+                        n_contrib += (uint64_t)__popcll(cm2);
+                        n_iter += 1;
+                    }
+                }
+                // statistics of Eq. 4 for the lanes that contribute
+                if (cm1 && ((vg >> j1) & 1ull)) {
+                    const float tdx = readlane_f(dxg[g], j1), tdy = readlane_f(dyg[g], j1);
+                    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
+                                 : "+v"(pex_reg) : "v"(P1));
+                    if (__builtin_amdgcn_inverse_ballot_w64(cm1)) {
+                        const float wgt = al1 * (T1 * pex_reg);
+                        const float wx = wgt * ux1, wy = wgt * uy1;
                         s_w += wgt;
                         s_ux += wx;
                         s_uy += wy;
-                        s_xx += wx * ux;
-                        s_xy += wx * uy;
-                        s_yy += wy * uy;
-                        s_dx += wgt * ddx;
-                        s_dy += wgt * ddy;
-                        s_xdx += wx * ddx;
-                        s_xdy += wx * ddy;
-                        s_ydx += wy * ddx;
-                        s_ydy += wy * ddy;
+                        s_xx += wx * ux1;
+                        s_xy += wx * uy1;
+                        s_yy += wy * uy1;
+                        s_dx += wgt * tdx;
+                        s_dy += wgt * tdy;
+                        s_xdx += wx * tdx;
+                        s_xdy += wx * tdy;
+                        s_ydx += wy * tdx;
+                        s_ydy += wy * tdy;
                         s_n += 1.0f;
-                        if ((statb[g] >> j) & 1ull) {
+                        if ((sg >> j1) & 1ull) {
                             s_sn += 1.0f;
-                            s_sa += al;
+                            s_sa += al1;
+                        }
+                    }
+                }
+                if (cm2 && ((vg >> j2) & 1ull)) {
+                    const float tdx = readlane_f(dxg[g], j2), tdy = readlane_f(dyg[g], j2);
+                    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
+                                 : "+v"(pex_reg) : "v"(P2));
+                    if (__builtin_amdgcn_inverse_ballot_w64(cm2)) {
+                        const float wgt = al2 * (T2 * pex_reg);
+                        const float wx = wgt * ux2, wy = wgt * uy2;
+                        s_w += wgt;
+                        s_ux += wx;
+                        s_uy += wy;
+                        s_xx += wx * ux2;
+                        s_xy += wx * uy2;
+                        s_yy += wy * uy2;
+                        s_dx += wgt * tdx;
+                        s_dy += wgt * tdy;
+                        s_xdx += wx * tdx;
+                        s_xdy += wx * tdy;
+                        s_ydx += wy * tdx;
+                        s_ydy += wy * tdy;
+                        s_n += 1.0f;
+                        if ((sg >> j2) & 1ull) {
+                            s_sn += 1.0f;
+                            s_sa += al2;
                         }
                     }
                 }
             }
+            alive[g] &= ~dead;
         }
         if (lane < nb && s_n > 0.0f) {
             float* dst = a.acc + (vN + gid) * TG_ACC_STRIDE;
@@ -244,13 +315,15 @@ __global__ void __launch_bounds__(256) k_accumulate(AccArgs a, GridPack gp)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int j = g * 64 + lane;
-            const int px = tx * TG_TILE + (j & 15), py = ty * TG_TILE + (j >> 4);
-            if (px < a.W && py < a.H) a.t_final[((int64_t)v * a.H + py) * a.W + px] = Tg[g];
+            const int px = px0 + (j & 15), py = py0 + (j >> 4);
+            if (px < a.W && py < a.H) a.t_final[(row_base + py) * a.W + px] = T_[j];
         }
     }
-    if (want_stats && lane == 0) {
+    if (STATS && lane == 0) {
         atomicAdd(a.stats, (unsigned long long)n_eval);
         atomicAdd(a.stats + 1, (unsigned long long)n_contrib);
+        atomicAdd(a.stats + 2, (unsigned long long)n_iter);
+        atomicAdd(a.stats + 3, (unsigned long long)n_refill);
     }
 }
 
@@ -287,7 +360,6 @@ extern "C" tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins
     a.cell_ids = bins->cell_ids;
     a.ranges = (const uint2*)bins->cell_ranges;
     a.overflow = bins->overflow;
-    a.disp = (const float2*)disp;
     a.vis = vis;
     a.acc = acc;
     a.t_final = t_final;
@@ -298,14 +370,19 @@ extern "C" tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins
     a.H = cams[0].height;
     a.cshift = cs;
     a.n_enum = ncell << (2 * cs);
-    a.blocks = (a.n_enum + ACC_WAVES - 1) / ACC_WAVES;
-    a.blocks_per_xcd = (a.blocks + 7) / 8;
+    a.blocks = a.n_enum;
+    a.blocks_per_xcd = (a.n_enum + 7) / 8;
     a.alpha_min = p->alpha_min;
     a.alpha_max = p->alpha_max;
     a.t_min = p->t_min;
     a.static2 = p->static_px * p->static_px;
     const int64_t grid = a.blocks_per_xcd * 8;
-    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, a, gp);
+    if (stats)
+        hipLaunchKernelGGL(k_accumulate<true>, dim3((unsigned)grid), dim3(64), 0, (hipStream_t)stream, a, gp,
+                           (const float2*)disp);
+    else
+        hipLaunchKernelGGL(k_accumulate<false>, dim3((unsigned)grid), dim3(64), 0, (hipStream_t)stream, a, gp,
+                           (const float2*)disp);
     TG_CHECK_LAUNCH();
     return TG_OK;
 }

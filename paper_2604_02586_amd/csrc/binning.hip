@@ -193,38 +193,45 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
 }
 
 // ---- coarse-bin key emission ---------------------------------------------
+// Each thread takes EMIT_ITEMS depth ranks (strided by the block size, so the
+// order/rect reads stay coalesced), the block reserves its output range with
+// one atomic on the pair counter, and each thread writes its keys into its
+// own sub-range.  Key order is irrelevant here: the keys are sorted next.
+constexpr int EMIT_ITEMS = 8;
+
 __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ order, const ushort4* __restrict__ rect,
                                               int64_t N, int V, GridPack gp, int cshift, int rbits,
                                               uint32_t* __restrict__ keys, int64_t capacity,
                                               unsigned long long* __restrict__ n_pairs, int32_t* __restrict__ overflow)
 {
-    __shared__ uint32_t tot;
     __shared__ unsigned long long gbase;
-    const int v = blockIdx.y;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t cnt = 0;
-    int cx0 = 0, cx1 = 0, cy0 = 0, cy1 = 0;
-    if (k < N) {
-        uint32_t g = order[(int64_t)v * N + k];
-        ushort4 r = g < (uint64_t)N ? rect[(int64_t)v * N + g] : make_ushort4(0, 0, 0, 0);
-        if (r.z > r.x && r.w > r.y) {
-            cx0 = r.x >> cshift;
-            cx1 = ((r.z - 1) >> cshift) + 1;
-            cy0 = r.y >> cshift;
-            cy1 = ((r.w - 1) >> cshift) + 1;
-            cnt = (uint32_t)((cx1 - cx0) * (cy1 - cy0));
-        }
-    }
-    // block exclusive scan (256 threads = 4 waves)
     __shared__ uint32_t wsum[4];
+    const int v = blockIdx.y;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    uint32_t inc = wave_scan_add_u32(cnt);
+    const int64_t base = (int64_t)blockIdx.x * (256 * EMIT_ITEMS);
+    ushort4 cr[EMIT_ITEMS];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int it = 0; it < EMIT_ITEMS; ++it) {
+        const int64_t k = base + it * 256 + t;
+        ushort4 c = make_ushort4(0, 0, 0, 0);
+        if (k < N) {
+            const uint32_t g = order[(int64_t)v * N + k];
+            const ushort4 r = g < (uint64_t)N ? rect[(int64_t)v * N + g] : make_ushort4(0, 0, 0, 0);
+            if (r.z > r.x && r.w > r.y) {
+                c = make_ushort4((unsigned short)(r.x >> cshift), (unsigned short)(r.y >> cshift),
+                                 (unsigned short)(((r.z - 1) >> cshift) + 1), (unsigned short)(((r.w - 1) >> cshift) + 1));
+                cnt += (uint32_t)((c.z - c.x) * (c.w - c.y));
+            }
+        }
+        cr[it] = c;
+    }
+    const uint32_t inc = wave_scan_add_u32(cnt);
     if (l == 63) wsum[w] = inc;
     __syncthreads();
     if (t == 0) {
         uint32_t s = 0;
         for (int i = 0; i < 4; ++i) { uint32_t c = wsum[i]; wsum[i] = s; s += c; }
-        tot = s;
         gbase = s ? atomicAdd(n_pairs, (unsigned long long)s) : 0ull;
     }
     __syncthreads();
@@ -236,11 +243,13 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ order
     }
     const int cw = gp.cx[v];
     const uint32_t cbase = (uint32_t)gp.cell_off[v];
-    for (int y = cy0; y < cy1; ++y)
-        for (int x = cx0; x < cx1; ++x) {
-            uint32_t cell = cbase + (uint32_t)(y * cw + x);
-            keys[pos++] = (cell << rbits) | (uint32_t)k;
-        }
+#pragma unroll
+    for (int it = 0; it < EMIT_ITEMS; ++it) {
+        const ushort4 c = cr[it];
+        const uint32_t k = (uint32_t)(base + it * 256 + t);
+        for (int y = c.y; y < c.w; ++y)
+            for (int x = c.x; x < c.z; ++x) keys[pos++] = ((cbase + (uint32_t)(y * cw + x)) << rbits) | k;
+    }
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t val) {
@@ -441,7 +450,8 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
                     L.scratch, s);
     if (st != TG_OK) return st;
     // (2) emit (coarse bin | depth rank) keys
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((N + 255) / 256), V), dim3(256), 0, s, bins->order,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((N + 256 * EMIT_ITEMS - 1) / (256 * EMIT_ITEMS)), V), dim3(256), 0, s,
+                       bins->order,
                        (const ushort4*)sp->rect, N, V, bp.gp, bp.cshift, bp.rbits, L.pk_a, bins->capacity,
                        (unsigned long long*)bins->n_pairs, bins->overflow);
     hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,

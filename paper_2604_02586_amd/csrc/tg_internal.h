@@ -75,6 +75,147 @@ __device__ __forceinline__ float wave_scan_add(float v) {
 // Value of the previous lane (lane 0 gets `first`).
 __device__ __forceinline__ float wave_shr1(float v, float first) { return dpp_f<0x138, 0xf, 0xf>(first, v); }
 
+// Inclusive product scan across the wave as six fused v_mul_f32_dpp: lanes
+// whose DPP source is outside the row/wave are not written (bound_ctrl off),
+// which multiplies them by one.  Each step reads the previous VALU result, so
+// two wait states precede it.  All 64 lanes must be active.
+__device__ __forceinline__ float wave_scan_mul_fused(float x) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(x));
+    return x;
+}
+
+// Two independent inclusive product scans, interleaved so that each DPP step
+// reads a value written two instructions earlier (one extra wait state).
+__device__ __forceinline__ void wave_scan_mul_fused2(float& x, float& y) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(x), "+v"(y));
+}
+
+// Exact float of a wave-uniform integer n < 2^24, built on the scalar unit
+// (exponent from the leading bit, mantissa by shifting): no VALU conversion.
+__device__ __forceinline__ float uniform_u2f(uint32_t n) {
+    if (n == 0) return 0.0f;
+    const int e = 31 - __builtin_clz(n);
+    const uint32_t bits = ((uint32_t)(127 + e) << 23) | ((n << (23 - e)) & 0x7FFFFFu);
+    return __builtin_bit_cast(float, bits);
+}
+
+// Inclusive sum scan as six fused v_add_f32_dpp (lanes without a DPP source
+// are not written, i.e. add zero).  All 64 lanes must be active.
+__device__ __forceinline__ float wave_scan_add_fused(float x) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(x));
+    return x;
+}
+
+// Smallest value over the rectangle [x0,x1] x [y0,y1] of the positive-definite
+// form q(p) = a dx^2 + 2 b dx dy + c dy^2, (dx, dy) = p - (mx, my): zero when the
+// centre is inside, otherwise the least of the four edge minima (each a 1D
+// quadratic minimised on its segment).
+__device__ __forceinline__ float rect_min_form(float a, float b, float c, float mx, float my, float x0, float x1,
+                                               float y0, float y1) {
+    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.0f;
+    const float dx0 = x0 - mx, dx1 = x1 - mx, dy0 = y0 - my, dy1 = y1 - my;
+    const float ia = 1.0f / a, ic = 1.0f / c;
+    float best;
+    {
+        const float dy = fminf(dy1, fmaxf(dy0, -b * dx0 * ic));
+        best = a * dx0 * dx0 + (2.0f * b * dx0 + c * dy) * dy;
+    }
+    {
+        const float dy = fminf(dy1, fmaxf(dy0, -b * dx1 * ic));
+        best = fminf(best, a * dx1 * dx1 + (2.0f * b * dx1 + c * dy) * dy);
+    }
+    {
+        const float dx = fminf(dx1, fmaxf(dx0, -b * dy0 * ia));
+        best = fminf(best, c * dy0 * dy0 + (2.0f * b * dy0 + a * dx) * dx);
+    }
+    {
+        const float dx = fminf(dx1, fmaxf(dx0, -b * dy1 * ia));
+        best = fminf(best, c * dy1 * dy1 + (2.0f * b * dy1 + a * dx) * dx);
+    }
+    return best;
+}
+
+// Does the splat (record r0 = {mx, my, conic a, b}, r1 = {conic c, opacity,..})
+// reach alpha >= alpha_min anywhere on the tile's pixel centres?  Exact
+// culling: q >= 2 ln(o / alpha_min) on the whole tile means alpha < alpha_min
+// at every pixel (the Gaussian neither adds nor attenuates); the margin keeps
+// the test conservative under FP32 rounding.
+__device__ __forceinline__ bool splat_reaches_tile(float4 r0, float4 r1, float log_amin, float amin, float ex0,
+                                                   float ex1, float ey0, float ey1) {
+    const float tau = 2.0f * (__logf(r1.y) - log_amin);
+    const float qmin = rect_min_form(r0.z, r0.w, r1.x, r0.x, r0.y, ex0, ex1, ey0, ey1);
+    return r1.y >= amin && qmin <= tau + 1e-3f * (1.0f + fabsf(tau));
+}
+
+// Tile of a cell-major tile enumeration index L (coarse bins of k x k tiles,
+// views back to back).  Returns false for enumerated tiles outside the image.
+struct TileCoord {
+    int v, tx, ty;
+    uint32_t gcell;
+};
+__device__ __forceinline__ bool tile_of(int64_t L, int cshift, int V, const GridPack& gp, TileCoord* t) {
+    const int k = 1 << cshift;
+    const int kk = k * k;
+    const uint32_t gcell = (uint32_t)(L / kk);
+    const int ti = (int)(L % kk);
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if ((uint32_t)gp.cell_off[mid] <= gcell) lo = mid; else hi = mid - 1;
+    }
+    const int cl = (int)gcell - gp.cell_off[lo];
+    t->v = lo;
+    t->gcell = gcell;
+    t->tx = (cl % gp.cx[lo]) * k + (ti % k);
+    t->ty = (cl / gp.cx[lo]) * k + (ti / k);
+    return t->tx < gp.tx[lo] && t->ty < gp.ty[lo];
+}
+
 // Integer inclusive sum scan across the wave (used by binning).
 __device__ __forceinline__ uint32_t wave_scan_add_u32(uint32_t v) {
     for (int o = 1; o < 64; o <<= 1) {
@@ -104,6 +245,25 @@ inline int64_t fill_grid(const tg_camera* cams, int32_t V, int cshift, GridPack*
     g->cell_off[V] = (int32_t)cell;
     g->tile_off[V] = (int32_t)tile;
     return cell;
+}
+
+// Same coarse plan as tg_bin_sort (coarse size grows until bin and rank bits
+// fit 32); returns the number of coarse bins or -1.
+inline int64_t coarse_plan(const tg_camera* cams, int32_t V, int64_t N, const tg_params* p, GridPack* gp,
+                           int* cshift) {
+    int cs = p->coarse_shift < 0 ? 0 : p->coarse_shift;
+    int rbits = 1;
+    while (rbits < 63 && (1ull << rbits) < (uint64_t)(N > 0 ? N : 1)) ++rbits;
+    for (;; ++cs) {
+        const int64_t ncell = fill_grid(cams, V, cs, gp);
+        int cbits = 1;
+        while (cbits < 63 && (1ull << cbits) < (uint64_t)ncell) ++cbits;
+        if (rbits + cbits <= 32) {
+            *cshift = cs;
+            return ncell;
+        }
+        if (cs > 12) return -1;
+    }
 }
 
 #define TG_CHECK_LAUNCH()                                   \

@@ -96,10 +96,14 @@ def test_accumulate_parity(pair):
     # final transmittance per pixel (Sigma w = 1 - T_final), marginal pixels excluded
     ok = comp["pixmarg"] == 0
     np.testing.assert_allclose(gpu["t_final"][ok], comp["tfinal"][ok], rtol=1e-4, atol=1e-6)
-    # pair counters: evaluated and contributing pairs in the sequential semantics
+    # pair counters in the sequential semantics: contributions are the same;
+    # evaluations can only drop (exact culling of Gaussians whose alpha stays
+    # below alpha_min on a whole tile)
     ev, ec = comp["counters"].sum(0)
     assert abs(int(gpu["stats"][1]) - ec) <= max(3, 1e-4 * ec)
-    assert abs(int(gpu["stats"][0]) - ev) <= max(3, 1e-4 * ev)
+    assert ec <= int(gpu["stats"][0]) <= ev + max(3, 1e-4 * ev)
+    log(f"[{case}] pairs: evaluated {int(gpu['stats'][0])} (oracle lists {ev}), contributing "
+        f"{int(gpu['stats'][1])}, pixel steps {int(gpu['stats'][2])}")
 
 
 def test_solve_views_parity(pair):
