@@ -48,6 +48,8 @@ extern "C" {
 #define TG_MAX_VIEWS 32     /* views per launch; more views are chunked       */
 #define TG_ACC_STRIDE 16    /* floats per accumulator record                  */
 #define TG_REC_STRIDE 8     /* floats per splat record                        */
+#define TG_MAX_SLOTS 8      /* Gaussian sets per batched accumulate launch    */
+#define TG_MAX_FRAMES 4     /* frames sharing one alpha/T evaluation          */
 
 typedef enum tg_status {
     TG_OK = 0,
@@ -225,6 +227,48 @@ tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins, int64_t N
                               const tg_camera* cams, int32_t V, const float* disp,
                               const uint8_t* vis, const tg_params* p, float* acc,
                               float* t_final, int64_t* stats, void* stream);
+
+/*
+ * tg_splat_accumulate_batch -- the same statistics for several Gaussian sets
+ * and several frames per set in one launch.
+ *
+ * Each target frame of a clip is transferred from the clip's first frame
+ * (Sec. 4.7: motion compensation of a frame depends only on the tracks and
+ * on the first frame's Gaussians), so the F frames of a slot share its
+ * splats, bins, alpha and T, and differ only in their tracks: the kernel
+ * evaluates alpha T once per (pixel, Gaussian) and adds frame f's record
+ * (defined as for tg_splat_accumulate, with frame f's disp and vis) to
+ * acc[f].  The slots form one ragged list of (slot, view, tile)
+ * work; slots may differ in N, V and resolution (the views of one slot share
+ * one resolution).
+ *
+ * slots: host [n_slots], n_slots <= TG_MAX_SLOTS, read during the call.
+ * Per slot: s, bins (as from tg_preprocess / tg_bin_sort for that set),
+ * cams host [V]; F in 1..TG_MAX_FRAMES; for each frame f < F: disp[f]
+ * device [V,H,W,2], vis[f] device [V,H,W] uint8 or NULL, acc[f] device
+ * [V,N,16] zeroed by the caller (frames are separate buffers, so each can
+ * be uploaded and retired on its own); t_final device [V,H,W] or NULL.
+ * Slots with N = 0 are skipped.  A slot whose bins overflowed is skipped by
+ * the device (see tg_bin_sort).
+ * stats as for tg_splat_accumulate, summed over every slot (frames share
+ * the evaluation, so pairs count once per slot).  Results equal F separate
+ * tg_splat_accumulate calls up to the order of the FP32 atomic additions.
+ */
+typedef struct tg_acc_slot {
+    const tg_splats* s;
+    const tg_bins* bins;
+    const tg_camera* cams;
+    int64_t N;
+    int32_t V;
+    int32_t F;
+    const float* disp[TG_MAX_FRAMES];
+    const uint8_t* vis[TG_MAX_FRAMES];
+    float* acc[TG_MAX_FRAMES];
+    float* t_final;
+} tg_acc_slot;
+
+tg_status tg_splat_accumulate_batch(const tg_acc_slot* slots, int32_t n_slots, const tg_params* p,
+                                    int64_t* stats, void* stream);
 
 /*
  * tg_solve_views -- per (view, Gaussian) 2D affine motion (Sec. 4.3.4 Eq. 4,

@@ -62,79 +62,143 @@ def quat_to_rot_t(q):
         torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
 
 
-def render(means, quats, log_scales, logit_opacity, sh, cams, bg=(0.0, 0.0, 0.0), geom=None,
-           near=0.2, dil=0.3, jclamp=1.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4):
-    """FP64 reference images [V,H,W,3] (torch, differentiable).
+def _order(geom, v):
+    """Depth order of the view's valid Gaussians: ascending FP32 depth key,
+    ties by index (a stable sort of the keys)."""
+    idx = np.nonzero(geom.valid[v])[0]
+    return idx[np.lexsort((idx, geom.key[v, idx]))]
 
-    geom: oracle.Geometry for the FP32 decisions; computed from the inputs
-    (scales = exp(log_scales) in FP32) when None."""
+
+def _geom_of(means, quats, log_scales, cams):
+    n = means.shape[0]
+    sc = synth.Scene(means=means.detach().numpy().astype(np.float32),
+                     quats=quats.detach().numpy().astype(np.float32),
+                     scales=np.exp(log_scales.detach().numpy().astype(np.float32)),
+                     opacity=np.zeros(n, np.float32), rgb=np.zeros((n, 3), np.float32))
+    return oracle.geometry(sc, cams)
+
+
+def _project(means, S3, sh, deg, cam, dil, jclamp, sel):
+    """Centre, conic and view colour of the Gaussians `sel` in one view
+    (Eq. 1 with the low-pass dilation added before the inverse)."""
     dt = torch.float64
-    N = means.shape[0]
+    R = torch.tensor(cam.R, dtype=dt)
+    t = torch.tensor(cam.t, dtype=dt)
+    fx, fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
+    cx, cy = float(np.float32(cam.cx)), float(np.float32(cam.cy))
+    m = means[sel]
+    p = m @ R.T + t
+    pz = p[:, 2]
+    limx, limy = jclamp * 0.5 * cam.W / fx, jclamp * 0.5 * cam.H / fy
+    tx = torch.clamp(p[:, 0] / pz, -limx, limx)
+    ty = torch.clamp(p[:, 1] / pz, -limy, limy)
+    zero = torch.zeros_like(pz)
+    J = torch.stack([torch.stack([fx / pz, zero, -fx * tx / pz], -1),
+                     torch.stack([zero, fy / pz, -fy * ty / pz], -1)], -2)
+    T = J @ R
+    S2 = T @ S3[sel] @ T.transpose(-1, -2) + dil * torch.eye(2, dtype=dt)
+    Q = torch.linalg.inv(S2)
+    mu = torch.stack([fx * p[:, 0] / pz + cx, fy * p[:, 1] / pz + cy], -1)
+    centre = -R.T @ t
+    dirs = m - centre
+    dirs = dirs / dirs.norm(dim=-1, keepdim=True)
+    col = torch.clamp((sh_basis(deg, dirs)[..., None] * sh[sel]).sum(1) + 0.5, min=0.0)
+    return mu, Q, col
+
+
+def _composite(pix, mu, Q, o, col, rect, bg, alpha_min, alpha_max, t_min, margin_rel):
+    """Front-to-back compositing of depth-ordered Gaussians at pixels
+    pix [P,2]; returns colours [P,3] and, per pixel, whether a discrete
+    decision (alpha threshold, alpha clamp, termination) lies within
+    margin_rel (relative) of flipping."""
+    dt = torch.float64
+    ptx = (pix[:, 0] // 16).long()[:, None]
+    pty = (pix[:, 1] // 16).long()[:, None]
+    inrect = (ptx >= rect[None, :, 0]) & (ptx < rect[None, :, 2]) & (pty >= rect[None, :, 1]) & \
+             (pty < rect[None, :, 3])
+    d = pix[:, None, :] - mu[None, :, :]                                   # [P,K,2]
+    power = -0.5 * (Q[None, :, 0, 0] * d[..., 0] ** 2 + Q[None, :, 1, 1] * d[..., 1] ** 2) - \
+        Q[None, :, 0, 1] * d[..., 0] * d[..., 1]
+    raw = o[None, :] * torch.exp(power)
+    al = torch.clamp(raw, max=alpha_max)
+    use = inrect & (power <= 0) & (al >= alpha_min)
+    al = torch.where(use, al, torch.zeros_like(al))
+    # termination: first Gaussian whose inclusion takes T below t_min
+    with torch.no_grad():
+        Tin = torch.cumprod(1.0 - al, dim=1)
+        stop = use & (Tin < t_min)
+        K = stop.shape[1]
+        first = torch.full((stop.shape[0],), K)
+        if K > 0:
+            first = torch.where(stop.any(1), stop.float().argmax(1), first)
+        ar = torch.arange(K)[None, :]
+        keep = ar < first[:, None]
+        upto = ar <= first[:, None]
+        rawd = raw.detach()
+        marg = inrect & upto & (power.detach() <= 0) & (
+            ((rawd / alpha_min - 1).abs() < margin_rel) | ((rawd / alpha_max - 1).abs() < margin_rel) |
+            (use & ((Tin / t_min - 1).abs() < margin_rel)))
+        marginal = marg.any(1)
+    al = torch.where(keep, al, torch.zeros_like(al))
+    Tex = torch.cat([torch.ones_like(al[:, :1]), torch.cumprod(1.0 - al, dim=1)[:, :-1]], 1)
+    w = al * Tex
+    Tfin = torch.prod(1.0 - al, dim=1)
+    C = w @ col + Tfin[:, None] * torch.tensor(bg, dtype=dt)[None, :]
+    return C, marginal
+
+
+def render(means, quats, log_scales, logit_opacity, sh, cams, bg=(0.0, 0.0, 0.0), geom=None, pixels=None,
+           dil=0.3, jclamp=1.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, margin_rel=1e-3,
+           return_marginal=False):
+    """FP64 reference colours (torch, differentiable).
+
+    Dense images [V,H,W,3] when pixels is None; else pixels = (v, x, y)
+    integer arrays and the result is [P,3] in that order.  geom: oracle
+    Geometry holding the FP32 decisions (tile rectangles, depth keys);
+    computed from the inputs (scales = exp(log_scales) in FP32) when None.
+    With return_marginal, also a boolean mask (same leading shape) of
+    pixels holding a decision within margin_rel of flipping."""
+    dt = torch.float64
     if geom is None:
-        sc = synth.Scene(means=means.detach().numpy().astype(np.float32),
-                         quats=quats.detach().numpy().astype(np.float32),
-                         scales=np.exp(log_scales.detach().numpy().astype(np.float32)),
-                         opacity=np.zeros(N, np.float32), rgb=np.zeros((N, 3), np.float32))
-        geom = oracle.geometry(sc, cams)
+        geom = _geom_of(means, quats, log_scales, cams)
     s = torch.exp(log_scales)
     o = torch.sigmoid(logit_opacity)
     Rq = quat_to_rot_t(quats)
     M = Rq * s[:, None, :]
     S3 = M @ M.transpose(-1, -2)
-    k = sh.shape[1]
-    deg = int(round(math.sqrt(k))) - 1
-    imgs = []
-    for v, cam in enumerate(cams):
-        R = torch.tensor(cam.R, dtype=dt)
-        t = torch.tensor(cam.t, dtype=dt)
-        fx, fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
-        cx, cy = float(np.float32(cam.cx)), float(np.float32(cam.cy))
-        p = means @ R.T + t
-        pz = p[:, 2]
-        limx, limy = jclamp * 0.5 * cam.W / fx, jclamp * 0.5 * cam.H / fy
-        tx = torch.clamp(p[:, 0] / pz, -limx, limx)
-        ty = torch.clamp(p[:, 1] / pz, -limy, limy)
-        zero = torch.zeros_like(pz)
-        J = torch.stack([torch.stack([fx / pz, zero, -fx * tx / pz], -1),
-                         torch.stack([zero, fy / pz, -fy * ty / pz], -1)], -2)
-        T = J @ R
-        S2 = T @ S3 @ T.transpose(-1, -2) + dil * torch.eye(2, dtype=dt)
-        Q = torch.linalg.inv(S2)
-        mu = torch.stack([fx * p[:, 0] / pz + cx, fy * p[:, 1] / pz + cy], -1)
-        centre = -R.T @ t
-        dirs = means - centre
-        dirs = dirs / dirs.norm(dim=-1, keepdim=True)
-        col = torch.clamp(torch.einsum("nk,nkc->nc", sh_basis(deg, dirs), sh) + 0.5, min=0.0)
-        H, W = cam.H, cam.W
-        yy, xx = torch.meshgrid(torch.arange(H, dtype=dt), torch.arange(W, dtype=dt), indexing="ij")
-        pix = torch.stack([xx.reshape(-1), yy.reshape(-1)], -1)            # [P,2]
-        valid = torch.tensor(geom.valid[v] != 0)
-        idx = np.nonzero(geom.valid[v])[0]
-        order = idx[np.lexsort((idx, geom.key[v, idx]))]
-        order_t = torch.tensor(order.astype(np.int64))
-        rect = torch.tensor(geom.rect[v][order].astype(np.int64))        # [K,4]
-        ptx = (pix[:, 0] // 16).long()[:, None]
-        pty = (pix[:, 1] // 16).long()[:, None]
-        inrect = (ptx >= rect[None, :, 0]) & (ptx < rect[None, :, 2]) & (pty >= rect[None, :, 1]) & \
-                 (pty < rect[None, :, 3])
-        d = pix[:, None, :] - mu[order_t][None, :, :]                       # [P,K,2]
-        Qo = Q[order_t]
-        power = -0.5 * (Qo[None, :, 0, 0] * d[..., 0] ** 2 + Qo[None, :, 1, 1] * d[..., 1] ** 2) - \
-            Qo[None, :, 0, 1] * d[..., 0] * d[..., 1]
-        al = torch.clamp(o[order_t][None, :] * torch.exp(power), max=alpha_max)
-        use = inrect & (power <= 0) & (al >= alpha_min)
-        al = torch.where(use, al, torch.zeros_like(al))
-        # termination: first Gaussian whose inclusion takes T below t_min
-        with torch.no_grad():
-            Tin = torch.cumprod(1.0 - al, dim=1)
-            stop = use & (Tin < t_min)
-            first = torch.where(stop.any(1), stop.float().argmax(1), torch.full((stop.shape[0],), stop.shape[1]))
-            keep = torch.arange(al.shape[1])[None, :] < first[:, None]
-        al = torch.where(keep, al, torch.zeros_like(al))
-        Tex = torch.cat([torch.ones_like(al[:, :1]), torch.cumprod(1.0 - al, dim=1)[:, :-1]], 1)
-        w = al * Tex
-        Tfin = torch.prod(1.0 - al, dim=1)
-        C = w @ col[order_t] + Tfin[:, None] * torch.tensor(bg, dtype=dt)[None, :]
-        imgs.append(C.reshape(H, W, 3))
-        del valid
-    return torch.stack(imgs, 0)
+    deg = int(round(math.sqrt(sh.shape[1]))) - 1
+    args = (bg, alpha_min, alpha_max, t_min, margin_rel)
+    if pixels is None:
+        imgs, margs = [], []
+        for v, cam in enumerate(cams):
+            order = torch.tensor(_order(geom, v).astype(np.int64))
+            mu, Q, col = _project(means, S3, sh, deg, cam, dil, jclamp, order)
+            rect = torch.tensor(geom.rect[v][order.numpy()].astype(np.int64))
+            H, W = cam.H, cam.W
+            yy, xx = torch.meshgrid(torch.arange(H, dtype=dt), torch.arange(W, dtype=dt), indexing="ij")
+            pix = torch.stack([xx.reshape(-1), yy.reshape(-1)], -1)
+            C, mg = _composite(pix, mu, Q, o[order], col, rect, *args)
+            imgs.append(C.reshape(H, W, 3))
+            margs.append(mg.reshape(H, W))
+        out, marg = torch.stack(imgs, 0), torch.stack(margs, 0)
+    else:
+        pv, px, py = (np.asarray(a, np.int64) for a in pixels)
+        out = [None] * len(pv)
+        marg = torch.zeros(len(pv), dtype=torch.bool)
+        for v in np.unique(pv):
+            at = np.nonzero(pv == v)[0]
+            order = _order(geom, v)
+            rect_all = geom.rect[v][order].astype(np.int64)
+            tx, ty = px[at] // 16, py[at] // 16
+            cand = np.zeros(len(order), bool)
+            for a_, b_ in set(zip(tx.tolist(), ty.tolist())):
+                cand |= (rect_all[:, 0] <= a_) & (a_ < rect_all[:, 2]) & (rect_all[:, 1] <= b_) & (b_ < rect_all[:, 3])
+            sel = torch.tensor(order[cand])
+            mu, Q, col = _project(means, S3, sh, deg, cams[v], dil, jclamp, sel)
+            pix = torch.tensor(np.stack([px[at], py[at]], -1).astype(np.float64))
+            C, mg = _composite(pix, mu, Q, o[sel], col, torch.tensor(rect_all[cand]), *args)
+            for j, i in enumerate(at):
+                out[i] = C[j]
+            marg[torch.tensor(at)] = mg
+        out = torch.stack(out, 0)
+    return (out, marg) if return_marginal else out

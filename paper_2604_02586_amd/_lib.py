@@ -16,6 +16,8 @@ c_vp = ctypes.c_void_p
 TG_MAX_VIEWS = 32
 TG_ACC_STRIDE = 16
 TG_REC_STRIDE = 8
+TG_MAX_SLOTS = 8
+TG_MAX_FRAMES = 4
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "misaligned buffer", 3: "workspace too small",
           4: "capacity overflow", 5: "HIP runtime error", 6: "request exceeds the memory budget",
@@ -56,6 +58,12 @@ class Bins(ctypes.Structure):
                 ("overflow", c_vp), ("capacity", c_i64)]
 
 
+class AccSlot(ctypes.Structure):
+    _fields_ = [("s", c_vp), ("bins", c_vp), ("cams", c_vp), ("N", c_i64), ("V", c_i32), ("F", c_i32),
+                ("disp", c_vp * TG_MAX_FRAMES), ("vis", c_vp * TG_MAX_FRAMES), ("acc", c_vp * TG_MAX_FRAMES),
+                ("t_final", c_vp)]
+
+
 _lib = None
 
 
@@ -79,6 +87,7 @@ def lib():
         "tg_preprocess": ([P, c_i64, P, c_i32, P, P, P], st),
         "tg_bin_sort": ([P, c_i64, P, c_i32, P, P, P, P, P], st),
         "tg_splat_accumulate": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P, P], st),
+        "tg_splat_accumulate_batch": ([P, c_i32, P, P, P], st),
         "tg_solve_views": ([P, P, c_i64, c_i32, P, P, P, P, P], st),
         "tg_triangulate": ([P, P, P, P, P, P, c_i64, P, c_i32, P, P, P, P], st),
         "tg_bin_expand": ([P, P, c_i64, P, c_i32, P, P, P, c_i64, P, P, P, P], st),
@@ -88,16 +97,8 @@ def lib():
         "tg_l1_loss_grad": ([P, P, c_i64, c_f, P, P, P], st),
         "tg_adam_step": ([P, P, P, P, c_i64, c_f, c_f, c_f, c_f, c_i32, P], st),
     }
-    optional = {
-        "tg_accumulate_batch": ([P, P, c_i64, P, c_i32, c_i32, P, P, P, P, c_i64, P, P], st),
-    }
-    for name, (args, res) in list(sig.items()) + list(optional.items()):
-        try:
-            f = getattr(L, name)
-        except AttributeError:
-            if name in sig:
-                raise
-            continue
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
         f.argtypes = args
         f.restype = res
     _lib = L
@@ -107,7 +108,7 @@ def lib():
 def exported_symbols():
     return [n for n in ("tg_abi_version", "tg_status_string", "tg_default_params", "tg_num_cells",
                         "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_splat_accumulate",
-                        "tg_solve_views", "tg_triangulate", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
+                        "tg_splat_accumulate_batch", "tg_solve_views", "tg_triangulate", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
                         "tg_project_bwd", "tg_l1_loss_grad", "tg_adam_step")]
 
 

@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import check, lib
 
 __all__ = ["GaussianTensors", "SplatTensors", "BinTensors", "MotionTransfer", "preprocess", "bin_sort",
-           "splat_accumulate", "solve_views", "triangulate", "bin_expand", "stream_ptr", "default_params"]
+           "splat_accumulate", "splat_accumulate_batch", "solve_views", "triangulate", "bin_expand", "stream_ptr", "default_params"]
 
 default_params = _lib.default_params
 
@@ -148,6 +148,47 @@ def splat_accumulate(s: SplatTensors, bins: BinTensors, n, cams, disp, vis, para
     check("tg_splat_accumulate", lib().tg_splat_accumulate(
         ctypes.byref(sc), ctypes.byref(bc), n, cams, len(cams), _ptr(disp), _ptr(vis), ctypes.byref(params),
         _ptr(acc), _ptr(t_final), _ptr(stats), stream_ptr(stream)))
+
+
+def _addr(t):
+    p = _ptr(t)
+    return None if p is None else p.value
+
+
+def splat_accumulate_batch(slots, params, stats=None, stream=None):
+    """One launch over several Gaussian sets, each with F <= TG_MAX_FRAMES
+    frames of tracks sharing its alpha T.  slots: sequence of dicts with keys
+    splats, bins, n, cams, disp, vis, acc, t_final (optional); disp / vis /
+    acc are per-frame sequences (or tensors whose leading axis is the frame)
+    of [V,H,W,2] / [V,H,W] uint8 or None / [V,N,16] zeroed."""
+    if len(slots) > _lib.TG_MAX_SLOTS:
+        raise ValueError(f"at most {_lib.TG_MAX_SLOTS} slots per launch")
+    keep = []
+    arr = (_lib.AccSlot * max(1, len(slots)))()
+    for i, sl in enumerate(slots):
+        cams = sl["cams"] if isinstance(sl["cams"], ctypes.Array) else _lib.cameras(sl["cams"])
+        sc, bc = sl["splats"].c(), sl["bins"].c()
+        keep += [cams, sc, bc]
+        disp = list(sl["disp"])
+        acc = list(sl["acc"])
+        vis = sl.get("vis")
+        vis = [None] * len(disp) if vis is None else list(vis)
+        if not (len(disp) == len(acc) == len(vis)) or not 1 <= len(disp) <= _lib.TG_MAX_FRAMES:
+            raise ValueError("disp, vis and acc need one entry per frame, 1..TG_MAX_FRAMES frames")
+        arr[i].s = ctypes.addressof(sc)
+        arr[i].bins = ctypes.addressof(bc)
+        arr[i].cams = ctypes.addressof(cams)
+        arr[i].N = int(sl["n"])
+        arr[i].V = len(cams)
+        arr[i].F = len(disp)
+        for f in range(len(disp)):
+            arr[i].disp[f] = _addr(disp[f])
+            arr[i].vis[f] = _addr(vis[f])
+            arr[i].acc[f] = _addr(acc[f])
+        arr[i].t_final = _addr(sl.get("t_final"))
+    check("tg_splat_accumulate_batch", lib().tg_splat_accumulate_batch(
+        arr, len(slots), ctypes.byref(params), _ptr(stats), stream_ptr(stream)))
+    del keep
 
 
 def solve_views(acc, s: SplatTensors, n, V, params, mu_new, cov_new, vflags, stream=None):

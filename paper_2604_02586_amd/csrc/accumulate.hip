@@ -23,6 +23,14 @@
 // filtered by the tile rectangle with a ballot/popcount compaction into a
 // per-wave LDS queue.  Blocks are remapped so that each XCD receives a
 // contiguous range of coarse bins (its L2 holds that bin's list and splats).
+//
+// Batched form (tg_splat_accumulate_batch): one launch walks a ragged list of
+// (slot, view, tile) work over up to TG_MAX_SLOTS slots, each slot one
+// resident Gaussian set with its own size, views and resolution.  The frames
+// of one slot share the reference Gaussians and hence every alpha and T
+// (Sec. 4.7: each target frame is solved from the clip's first frame), so a
+// tile evaluates alpha T once and adds each frame's track statistics: up to
+// four frames ride on one evaluation, their sums side by side in registers.
 #include "tg_internal.h"
 
 namespace {
@@ -30,28 +38,73 @@ namespace {
 constexpr int QCAP = 128;
 constexpr float LOG2E = 1.4426950408889634f;
 
-struct AccArgs {
+// One slot of a launch: a Gaussian set (splats + bins of one frame set)
+// and F frames of tracks.  All views of a slot share one resolution, so the
+// tile grid is uniform over its views.
+struct SlotArgs {
     const float4* rec;
     const ushort4* rect;
     const uint32_t* cell_ids;
     const uint2* ranges;
     const int32_t* overflow;
-    const uint8_t* vis;
-    float* acc;
-    float* t_final;
-    unsigned long long* stats;
+    const float2* disp[TG_MAX_FRAMES];   // per frame [V,H,W]
+    const uint8_t* vis[TG_MAX_FRAMES];   // per frame [V,H,W] or null
+    float* acc[TG_MAX_FRAMES];           // per frame [V,N,16]
+    float* t_final;          // [V,H,W] or null
     int64_t N;
-    int V, W, H, cshift;
-    int64_t n_enum;          // tiles enumerated (cells * tiles per cell)
-    int64_t blocks;          // logical blocks
-    int64_t blocks_per_xcd;
-    float alpha_min, alpha_max, t_min, static2;
+    int64_t block0;          // first logical block of the slot
+    int32_t W, H, F, cshift;
+    int32_t cells_x, cells_pv, tiles_x, tiles_y;
 };
 
+struct BatchArgs {
+    SlotArgs slot[TG_MAX_SLOTS];
+    int32_t n_slots;
+    int64_t n_enum;          // logical blocks over all slots
+    int64_t blocks_per_xcd;
+    float alpha_min, alpha_max, t_min, static2;
+    unsigned long long* stats;
+};
+
+// Running sums of one frame for the lane's Gaussian (Eq. 4 record order).
+struct Sums {
+    float w, ux, uy, xx, xy, yy, dx, dy, xdx, xdy, ydx, ydy, n, sn, sa;
+};
+
+__device__ __forceinline__ void sums_zero(Sums& s) {
+    s.w = s.ux = s.uy = s.xx = s.xy = s.yy = 0.f;
+    s.dx = s.dy = s.xdx = s.xdy = s.ydx = s.ydy = 0.f;
+    s.n = s.sn = s.sa = 0.f;
+}
+
+// Adds one pixel's weighted record: w, w u, w u u^T (shared by the frames)
+// and the frame's track d.
+__device__ __forceinline__ void sums_add(Sums& s, float wgt, float wx, float wy, float wxx, float wxy, float wyy,
+                                         float tdx, float tdy, bool stat, float al) {
+    s.w += wgt;
+    s.ux += wx;
+    s.uy += wy;
+    s.xx += wxx;
+    s.xy += wxy;
+    s.yy += wyy;
+    s.dx += wgt * tdx;
+    s.dy += wgt * tdy;
+    s.xdx += wx * tdx;
+    s.xdy += wx * tdy;
+    s.ydx += wy * tdx;
+    s.ydy += wy * tdy;
+    s.n += 1.0f;
+    if (stat) {
+        s.sn += 1.0f;
+        s.sa += al;
+    }
+}
+
 // One wave (64 threads) per workgroup and per 16x16 tile, so tiles of very
-// different work never hold each other's resources.
-template <bool STATS>
-__global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const float2* __restrict__ disp)
+// different work never hold each other's resources.  FM: frames per slot the
+// launch is compiled for (a slot may carry fewer).
+template <int FM, bool STATS>
+__global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
 {
     // 3.5 KB of LDS per wave keeps 8 waves per SIMD resident:
     // queue of filtered list entries (ids), per-pixel column/row offsets
@@ -59,71 +112,83 @@ __global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const
     __shared__ uint32_t qi[QCAP];
     __shared__ float2 CR[256];
     __shared__ float T_[256];
-    if (*a.overflow) return;
     // XCD-aware remap: hardware places workgroup b on XCD (b mod 8); give
     // each XCD a contiguous range of tiles (its L2 then holds those bins).
     const int64_t b = blockIdx.x;
     const int64_t L = (b & 7) * a.blocks_per_xcd + (b >> 3);
     if (L >= a.n_enum) return;
-    const int lane = threadIdx.x;
-    const int k = 1 << a.cshift;
+    int si = 0;
+#pragma unroll
+    for (int s = 1; s < TG_MAX_SLOTS; ++s)
+        if (s < a.n_slots && L >= a.slot[s].block0) si = s;
+    si = __builtin_amdgcn_readfirstlane(si);
+    const SlotArgs& S = a.slot[si];
+    if (*S.overflow) return;
+    const int64_t N = S.N;
+    const int W = S.W, H = S.H, F = S.F;
+    const int k = 1 << S.cshift;
     const int kk = k * k;
-    const uint32_t gcell = (uint32_t)(L / kk);
-    const int ti = (int)(L % kk);
-    int v = 0;
-    {
-        int lo = 0, hi = a.V - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if ((uint32_t)gp.cell_off[mid] <= gcell) lo = mid; else hi = mid - 1;
-        }
-        v = lo;
-    }
-    const int cl = (int)gcell - gp.cell_off[v];
-    const int tx = (cl % gp.cx[v]) * k + (ti % k);
-    const int ty = (cl / gp.cx[v]) * k + (ti / k);
-    if (tx >= gp.tx[v] || ty >= gp.ty[v]) return;
-    const uint2 rg = a.ranges[gcell];
-    const int64_t vN = (int64_t)v * a.N;
+    const int64_t Ll = L - S.block0;
+    const uint32_t gcell = (uint32_t)(Ll / kk);
+    const int ti = (int)(Ll % kk);
+    const int v = (int)(gcell / (uint32_t)S.cells_pv);
+    const int cl = (int)gcell - v * S.cells_pv;
+    const int tx = (cl % S.cells_x) * k + (ti % k);
+    const int ty = (cl / S.cells_x) * k + (ti / k);
+    if (tx >= S.tiles_x || ty >= S.tiles_y) return;
+    const float4* __restrict__ rec = S.rec;
+    const ushort4* __restrict__ rect = S.rect;
+    const uint32_t* __restrict__ cell_ids = S.cell_ids;
+    const uint2 rg = S.ranges[gcell];
+    const int64_t vN = (int64_t)v * N;
     const int px0 = tx * TG_TILE, py0 = ty * TG_TILE;
-    const int64_t row_base = (int64_t)v * a.H;
+    const int64_t row_base = (int64_t)v * H;
+    const int lane = threadIdx.x;
 
-    // pixel state: pixel j = g*64 + lane -> (px0 + (j&15), py0 + (j>>4))
-    uint64_t alive[4], visb[4], statb[4];
-    float dxg[4], dyg[4];   // track of pixel g*64 + lane
+    // pixel state: pixel j = g*64 + lane -> (px0 + (j&15), py0 + (j>>4));
+    // flags of pixel j: bit f = track visible in frame f, bit 8+f = static
+    // in frame f
+    uint64_t alive[4];
+    uint32_t flg[4];
+    float dxg[FM][4], dyg[FM][4];   // track of pixel g*64 + lane per frame
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int j = g * 64 + lane;
         const int px = px0 + (j & 15), py = py0 + (j >> 4);
-        const bool in = px < a.W && py < a.H;
-        float ddx = 0.f, ddy = 0.f;
-        bool vv = false;
-        if (in) {
-            const int64_t pi = (row_base + py) * a.W + px;
-            const float2 d = disp[pi];
-            ddx = d.x;
-            ddy = d.y;
-            vv = a.vis ? a.vis[pi] != 0 : true;
+        const bool in = px < W && py < H;
+        uint32_t fl = 0;
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            float ddx = 0.f, ddy = 0.f;
+            if (in && f < F) {
+                const int64_t pi = (row_base + py) * W + px;
+                const float2 d = S.disp[f][pi];
+                ddx = d.x;
+                ddy = d.y;
+                const bool vv = S.vis[f] ? S.vis[f][pi] != 0 : true;
+                float s2;
+                {
+#pragma clang fp contract(off)
+                    s2 = ddx * ddx;
+                    s2 = s2 + ddy * ddy;
+                }
+                fl |= (vv ? 1u : 0u) << f;
+                fl |= (s2 < a.static2 ? 1u : 0u) << (8 + f);
+            }
+            dxg[f][g] = ddx;
+            dyg[f][g] = ddy;
         }
         CR[j] = make_float2((float)(j & 15), (float)(j >> 4));
         T_[j] = 1.0f;
-        dxg[g] = ddx;
-        dyg[g] = ddy;
+        flg[g] = fl;
         alive[g] = ballot64(in);
-        visb[g] = ballot64(in && vv);
-        float s2;
-        {
-#pragma clang fp contract(off)
-            s2 = ddx * ddx;
-            s2 = s2 + ddy * ddy;
-        }
-        statb[g] = ballot64(in && s2 < a.static2);
     }
     uint64_t n_eval = 0, n_contrib = 0, n_iter = 0, n_refill = 0;
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min;
     const float log_amin = __logf(amin);
     const uint64_t ltmask = lanemask_lt();
     const bool lane0 = lane == 0;
+    constexpr uint32_t VISM = (1u << FM) - 1u;
     float pex_reg = 1.0f;   // lane 0 is never written by the wave shift below
     int qn = 0;
     uint32_t pos = rg.x;
@@ -131,7 +196,7 @@ __global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const
     const float ex0 = (float)px0, ex1 = (float)(px0 + TG_TILE - 1);
     const float ey0 = (float)py0, ey1 = (float)(py0 + TG_TILE - 1);
     // prefetched ids of the next 64 list entries
-    uint32_t nid = (pos + lane < rg.y) ? a.cell_ids[pos + lane] : 0xFFFFFFFFu;
+    uint32_t nid = (pos + lane < rg.y) ? cell_ids[pos + lane] : 0xFFFFFFFFu;
 
     while ((alive[0] | alive[1] | alive[2] | alive[3]) != 0ull) {
         // Refill: list entries whose rectangle contains this tile and whose
@@ -143,13 +208,13 @@ __global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const
             const uint32_t gid = nid;
             const uint32_t i = pos + lane;
             pos += 64;
-            nid = (pos + lane < rg.y) ? a.cell_ids[pos + lane] : 0xFFFFFFFFu;
+            nid = (pos + lane < rg.y) ? cell_ids[pos + lane] : 0xFFFFFFFFu;
             bool hit = false;
-            if (i < rg.y && gid < (uint64_t)a.N) {
-                const ushort4 r = a.rect[vN + gid];
+            if (i < rg.y && gid < (uint64_t)N) {
+                const ushort4 r = rect[vN + gid];
                 hit = tx >= r.x && tx < r.z && ty >= r.y && ty < r.w;
                 if (hit)
-                    hit = splat_reaches_tile(a.rec[2 * (vN + gid)], a.rec[2 * (vN + gid) + 1], log_amin, amin, ex0,
+                    hit = splat_reaches_tile(rec[2 * (vN + gid)], rec[2 * (vN + gid) + 1], log_amin, amin, ex0,
                                              ex1, ey0, ey1);
             }
             const uint64_t m = ballot64(hit);
@@ -163,8 +228,8 @@ __global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const
         float dxl = 0.f, dyl = 0.f, ca = 0.f, cb = 0.f, cc = 0.f, op = 0.f;
         if (lane < nb) {
             gid = qi[lane];
-            const float4 r0 = a.rec[2 * (vN + gid)];
-            const float4 r1 = a.rec[2 * (vN + gid) + 1];
+            const float4 r0 = rec[2 * (vN + gid)];
+            const float4 r1 = rec[2 * (vN + gid) + 1];
             dxl = (float)px0 - r0.x;   // u = (px0 + column) - mu_x
             dyl = (float)py0 - r0.y;
             ca = -0.5f * LOG2E * r0.z;
@@ -178,15 +243,14 @@ __global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const
         }
         qn -= nb;
 
-        float s_w = 0.f, s_ux = 0.f, s_uy = 0.f, s_xx = 0.f, s_xy = 0.f, s_yy = 0.f;
-        float s_dx = 0.f, s_dy = 0.f, s_xdx = 0.f, s_xdy = 0.f, s_ydx = 0.f, s_ydy = 0.f;
-        float s_n = 0.f, s_sn = 0.f, s_sa = 0.f;
+        Sums sm[FM];
+#pragma unroll
+        for (int f = 0; f < FM; ++f) sums_zero(sm[f]);
 
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             uint64_t m = alive[g];
             uint64_t dead = 0;
-            const uint64_t vg = visb[g], sg = statb[g];
             // two pixels per step: their dependency chains interleave
             while (m) {
                 const int j1 = __builtin_ctzll(m);
@@ -234,89 +298,84 @@ __global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const
                         n_iter += 1;
                     }
                 }
-                // statistics of Eq. 4 for the lanes that contribute
-                if (cm1 && ((vg >> j1) & 1ull)) {
-                    const float tdx = readlane_f(dxg[g], j1), tdy = readlane_f(dyg[g], j1);
+                // statistics of Eq. 4 for the lanes that contribute, per frame
+                // whose track at this pixel is visible
+                const uint32_t fl1 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j1);
+                if (cm1 && (fl1 & VISM)) {
+                    float tdx[FM], tdy[FM];
+#pragma unroll
+                    for (int f = 0; f < FM; ++f) {
+                        tdx[f] = readlane_f(dxg[f][g], j1);
+                        tdy[f] = readlane_f(dyg[f][g], j1);
+                    }
                     asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
                                  : "+v"(pex_reg) : "v"(P1));
                     if (__builtin_amdgcn_inverse_ballot_w64(cm1)) {
                         const float wgt = al1 * (T1 * pex_reg);
                         const float wx = wgt * ux1, wy = wgt * uy1;
-                        s_w += wgt;
-                        s_ux += wx;
-                        s_uy += wy;
-                        s_xx += wx * ux1;
-                        s_xy += wx * uy1;
-                        s_yy += wy * uy1;
-                        s_dx += wgt * tdx;
-                        s_dy += wgt * tdy;
-                        s_xdx += wx * tdx;
-                        s_xdy += wx * tdy;
-                        s_ydx += wy * tdx;
-                        s_ydy += wy * tdy;
-                        s_n += 1.0f;
-                        if ((sg >> j1) & 1ull) {
-                            s_sn += 1.0f;
-                            s_sa += al1;
-                        }
+                        const float wxx = wx * ux1, wxy = wx * uy1, wyy = wy * uy1;
+#pragma unroll
+                        for (int f = 0; f < FM; ++f)
+                            if ((fl1 >> f) & 1u)
+                                sums_add(sm[f], wgt, wx, wy, wxx, wxy, wyy, tdx[f], tdy[f], (fl1 >> (8 + f)) & 1u,
+                                         al1);
                     }
                 }
-                if (cm2 && ((vg >> j2) & 1ull)) {
-                    const float tdx = readlane_f(dxg[g], j2), tdy = readlane_f(dyg[g], j2);
+                const uint32_t fl2 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j2);
+                if (cm2 && (fl2 & VISM)) {
+                    float tdx[FM], tdy[FM];
+#pragma unroll
+                    for (int f = 0; f < FM; ++f) {
+                        tdx[f] = readlane_f(dxg[f][g], j2);
+                        tdy[f] = readlane_f(dyg[f][g], j2);
+                    }
                     asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
                                  : "+v"(pex_reg) : "v"(P2));
                     if (__builtin_amdgcn_inverse_ballot_w64(cm2)) {
                         const float wgt = al2 * (T2 * pex_reg);
                         const float wx = wgt * ux2, wy = wgt * uy2;
-                        s_w += wgt;
-                        s_ux += wx;
-                        s_uy += wy;
-                        s_xx += wx * ux2;
-                        s_xy += wx * uy2;
-                        s_yy += wy * uy2;
-                        s_dx += wgt * tdx;
-                        s_dy += wgt * tdy;
-                        s_xdx += wx * tdx;
-                        s_xdy += wx * tdy;
-                        s_ydx += wy * tdx;
-                        s_ydy += wy * tdy;
-                        s_n += 1.0f;
-                        if ((sg >> j2) & 1ull) {
-                            s_sn += 1.0f;
-                            s_sa += al2;
-                        }
+                        const float wxx = wx * ux2, wxy = wx * uy2, wyy = wy * uy2;
+#pragma unroll
+                        for (int f = 0; f < FM; ++f)
+                            if ((fl2 >> f) & 1u)
+                                sums_add(sm[f], wgt, wx, wy, wxx, wxy, wyy, tdx[f], tdy[f], (fl2 >> (8 + f)) & 1u,
+                                         al2);
                     }
                 }
             }
             alive[g] &= ~dead;
         }
-        if (lane < nb && s_n > 0.0f) {
-            float* dst = a.acc + (vN + gid) * TG_ACC_STRIDE;
-            unsafeAtomicAdd(dst + 0, s_w);
-            unsafeAtomicAdd(dst + 1, s_ux);
-            unsafeAtomicAdd(dst + 2, s_uy);
-            unsafeAtomicAdd(dst + 3, s_xx);
-            unsafeAtomicAdd(dst + 4, s_xy);
-            unsafeAtomicAdd(dst + 5, s_yy);
-            unsafeAtomicAdd(dst + 6, s_dx);
-            unsafeAtomicAdd(dst + 7, s_dy);
-            unsafeAtomicAdd(dst + 8, s_xdx);
-            unsafeAtomicAdd(dst + 9, s_xdy);
-            unsafeAtomicAdd(dst + 10, s_ydx);
-            unsafeAtomicAdd(dst + 11, s_ydy);
-            unsafeAtomicAdd(dst + 12, s_n);
-            if (s_sn > 0.0f) {
-                unsafeAtomicAdd(dst + 13, s_sn);
-                unsafeAtomicAdd(dst + 14, s_sa);
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            const Sums& s = sm[f];
+            if (lane < nb && s.n > 0.0f) {
+                float* dst = S.acc[f] + (vN + gid) * TG_ACC_STRIDE;
+                unsafeAtomicAdd(dst + 0, s.w);
+                unsafeAtomicAdd(dst + 1, s.ux);
+                unsafeAtomicAdd(dst + 2, s.uy);
+                unsafeAtomicAdd(dst + 3, s.xx);
+                unsafeAtomicAdd(dst + 4, s.xy);
+                unsafeAtomicAdd(dst + 5, s.yy);
+                unsafeAtomicAdd(dst + 6, s.dx);
+                unsafeAtomicAdd(dst + 7, s.dy);
+                unsafeAtomicAdd(dst + 8, s.xdx);
+                unsafeAtomicAdd(dst + 9, s.xdy);
+                unsafeAtomicAdd(dst + 10, s.ydx);
+                unsafeAtomicAdd(dst + 11, s.ydy);
+                unsafeAtomicAdd(dst + 12, s.n);
+                if (s.sn > 0.0f) {
+                    unsafeAtomicAdd(dst + 13, s.sn);
+                    unsafeAtomicAdd(dst + 14, s.sa);
+                }
             }
         }
     }
-    if (a.t_final) {
+    if (S.t_final) {
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int j = g * 64 + lane;
             const int px = px0 + (j & 15), py = py0 + (j >> 4);
-            if (px < a.W && py < a.H) a.t_final[(row_base + py) * a.W + px] = T_[j];
+            if (px < W && py < H) S.t_final[(row_base + py) * W + px] = T_[j];
         }
     }
     if (STATS && lane == 0) {
@@ -327,6 +386,103 @@ __global__ void __launch_bounds__(64) k_accumulate(AccArgs a, GridPack gp, const
     }
 }
 
+// Validates one slot and fills its launch record; *blocks receives the
+// slot's logical block count.
+tg_status make_slot(const tg_acc_slot& in, const tg_params* p, SlotArgs* o, int64_t block0, int64_t* blocks) {
+    const tg_splats* s = in.s;
+    const tg_bins* bins = in.bins;
+    if (!s || !bins || !in.cams || in.N < 0 || in.V < 1) return TG_ERR_INVALID_ARG;
+    if (in.F < 1 || in.F > TG_MAX_FRAMES || in.V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
+    if (!s->rec || !s->rect || !bins->cell_ids || !bins->cell_ranges || !bins->overflow) return TG_ERR_INVALID_ARG;
+    if (!aligned16(s->rec)) return TG_ERR_ALIGNMENT;
+    for (int f = 0; f < in.F; ++f) {
+        if (!in.disp[f] || !in.acc[f]) return TG_ERR_INVALID_ARG;
+        if (!aligned16(in.acc[f]) || ((uintptr_t)in.disp[f] & 7u)) return TG_ERR_ALIGNMENT;
+    }
+    for (int v = 1; v < in.V; ++v)
+        if (in.cams[v].width != in.cams[0].width || in.cams[v].height != in.cams[0].height)
+            return TG_ERR_INVALID_ARG;
+    if (in.cams[0].width < 1 || in.cams[0].height < 1) return TG_ERR_INVALID_ARG;
+    if (in.N > (int64_t)0xFFFFFFFF) return TG_ERR_UNSUPPORTED;
+    *blocks = 0;
+    if (in.N == 0) return TG_OK;
+    // same coarse plan as tg_bin_sort
+    GridPack gp;
+    int cs = 0;
+    const int64_t ncell = coarse_plan(in.cams, in.V, in.N, p, &gp, &cs);
+    if (ncell < 0) return TG_ERR_UNSUPPORTED;
+    o->rec = (const float4*)s->rec;
+    o->rect = (const ushort4*)s->rect;
+    o->cell_ids = bins->cell_ids;
+    o->ranges = (const uint2*)bins->cell_ranges;
+    o->overflow = bins->overflow;
+    for (int f = 0; f < TG_MAX_FRAMES; ++f) {
+        const bool use = f < in.F;
+        o->disp[f] = use ? (const float2*)in.disp[f] : nullptr;
+        o->vis[f] = use ? in.vis[f] : nullptr;
+        o->acc[f] = use ? in.acc[f] : nullptr;
+    }
+    o->t_final = in.t_final;
+    o->N = in.N;
+    o->W = in.cams[0].width;
+    o->H = in.cams[0].height;
+    o->F = in.F;
+    o->cshift = cs;
+    o->block0 = block0;
+    o->cells_x = gp.cx[0];
+    o->cells_pv = gp.cx[0] * gp.cy[0];
+    o->tiles_x = gp.tx[0];
+    o->tiles_y = gp.ty[0];
+    *blocks = ncell << (2 * cs);
+    return TG_OK;
+}
+
+template <int FM>
+void launch(const BatchArgs& a, bool stats, hipStream_t st) {
+    const int64_t grid = a.blocks_per_xcd * 8;
+    if (stats)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accumulate<FM, true>), dim3((unsigned)grid), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accumulate<FM, false>), dim3((unsigned)grid), dim3(64), 0, st, a);
+}
+
+tg_status accumulate_slots(const tg_acc_slot* slots, int32_t n_slots, const tg_params* p, int64_t* stats,
+                           void* stream) {
+    if (!slots || !p || n_slots < 0) return TG_ERR_INVALID_ARG;
+    if (n_slots > TG_MAX_SLOTS) return TG_ERR_UNSUPPORTED;
+    BatchArgs a;
+    int64_t total = 0;
+    int fmax = 1, used = 0;
+    for (int i = 0; i < n_slots; ++i) {
+        int64_t nb = 0;
+        const tg_status st = make_slot(slots[i], p, &a.slot[used], total, &nb);
+        if (st != TG_OK) return st;
+        if (nb == 0) continue;
+        fmax = slots[i].F > fmax ? slots[i].F : fmax;
+        total += nb;
+        ++used;
+    }
+    if (used == 0) return TG_OK;
+    if (total > (int64_t)0x7FFFFFF0) return TG_ERR_UNSUPPORTED;
+    a.n_slots = used;
+    a.n_enum = total;
+    a.blocks_per_xcd = (total + 7) / 8;
+    a.alpha_min = p->alpha_min;
+    a.alpha_max = p->alpha_max;
+    a.t_min = p->t_min;
+    a.static2 = p->static_px * p->static_px;
+    a.stats = (unsigned long long*)stats;
+    const hipStream_t st = (hipStream_t)stream;
+    if (fmax == 1)
+        launch<1>(a, stats != nullptr, st);
+    else if (fmax == 2)
+        launch<2>(a, stats != nullptr, st);
+    else
+        launch<4>(a, stats != nullptr, st);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}
+
 }  // namespace
 
 extern "C" tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams,
@@ -334,55 +490,22 @@ extern "C" tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins
                                          float* acc, float* t_final, int64_t* stats, void* stream)
 {
     if (!s || !bins || !cams || !p || !disp || !acc || N < 0 || V < 1) return TG_ERR_INVALID_ARG;
-    if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
-    if (!s->rec || !s->rect || !bins->cell_ids || !bins->cell_ranges || !bins->overflow) return TG_ERR_INVALID_ARG;
-    if (!aligned16(s->rec) || !aligned16(acc) || ((uintptr_t)disp & 7u)) return TG_ERR_ALIGNMENT;
-    for (int v = 1; v < V; ++v)
-        if (cams[v].width != cams[0].width || cams[v].height != cams[0].height) return TG_ERR_INVALID_ARG;
-    if (N == 0) return TG_OK;
-    if (N > (int64_t)0xFFFFFFFF) return TG_ERR_UNSUPPORTED;
-    // same coarse plan as tg_bin_sort
-    int cs = p->coarse_shift < 0 ? 0 : p->coarse_shift;
-    int rbits = 1;
-    while (rbits < 63 && (1ull << rbits) < (uint64_t)N) ++rbits;
-    GridPack gp;
-    int64_t ncell;
-    for (;; ++cs) {
-        ncell = fill_grid(cams, V, cs, &gp);
-        int cbits = 1;
-        while (cbits < 63 && (1ull << cbits) < (uint64_t)ncell) ++cbits;
-        if (rbits + cbits <= 32) break;
-        if (cs > 12) return TG_ERR_UNSUPPORTED;
-    }
-    AccArgs a;
-    a.rec = (const float4*)s->rec;
-    a.rect = (const ushort4*)s->rect;
-    a.cell_ids = bins->cell_ids;
-    a.ranges = (const uint2*)bins->cell_ranges;
-    a.overflow = bins->overflow;
-    a.vis = vis;
-    a.acc = acc;
-    a.t_final = t_final;
-    a.stats = (unsigned long long*)stats;
-    a.N = N;
-    a.V = V;
-    a.W = cams[0].width;
-    a.H = cams[0].height;
-    a.cshift = cs;
-    a.n_enum = ncell << (2 * cs);
-    a.blocks = a.n_enum;
-    a.blocks_per_xcd = (a.n_enum + 7) / 8;
-    a.alpha_min = p->alpha_min;
-    a.alpha_max = p->alpha_max;
-    a.t_min = p->t_min;
-    a.static2 = p->static_px * p->static_px;
-    const int64_t grid = a.blocks_per_xcd * 8;
-    if (stats)
-        hipLaunchKernelGGL(k_accumulate<true>, dim3((unsigned)grid), dim3(64), 0, (hipStream_t)stream, a, gp,
-                           (const float2*)disp);
-    else
-        hipLaunchKernelGGL(k_accumulate<false>, dim3((unsigned)grid), dim3(64), 0, (hipStream_t)stream, a, gp,
-                           (const float2*)disp);
-    TG_CHECK_LAUNCH();
-    return TG_OK;
+    tg_acc_slot one = {};
+    one.s = s;
+    one.bins = bins;
+    one.cams = cams;
+    one.N = N;
+    one.V = V;
+    one.F = 1;
+    one.disp[0] = disp;
+    one.vis[0] = vis;
+    one.acc[0] = acc;
+    one.t_final = t_final;
+    return accumulate_slots(&one, 1, p, stats, stream);
+}
+
+extern "C" tg_status tg_splat_accumulate_batch(const tg_acc_slot* slots, int32_t n_slots, const tg_params* p,
+                                               int64_t* stats, void* stream)
+{
+    return accumulate_slots(slots, n_slots, p, stats, stream);
 }

@@ -467,3 +467,96 @@ def make_workload(name="small", *, seed=None, n=None, views=None, width=None, he
         vis = np.ones((nv, H, W), np.uint8)
     return Workload(name=name, scene=scene, cams=cams, motion=motion, disp=disp, vis=vis,
                     meta=dict(seed=seed, n=N, views=nv, W=W, H=H))
+
+
+# --------------------------------------------------------------------------
+# refinement workloads: ground-truth Gaussians with degree-3 SH colour and a
+# perturbed copy to refine against images of the ground truth
+# --------------------------------------------------------------------------
+REFINE_WORKLOADS = {
+    # gradient-check subset: 500 Gaussians, 64x64, two ring views
+    "refine_fd": dict(n=500, domain="cube", cams=("ring", 2, 3.0, 64, 64), seed=11),
+    # 500k Gaussians in a radius-2 ball, 16 hemisphere views at 1352x1014
+    "refine": dict(n=500_000, domain="ball", cams=("hemi", 16, 6.0, 1352, 1014), seed=4),
+}
+
+
+@dataclass
+class RefineWorkload:
+    name: str
+    gt: dict          # parameters of the ground truth (see refine_params)
+    init: dict        # perturbed parameters the refinement starts from
+    cams: list
+    meta: dict
+
+
+def refine_params(scene: Scene) -> dict:
+    """Unconstrained parameters: means, quats, log-scales, opacity logits,
+    SH coefficients [N, (deg+1)^2, 3]."""
+    n = scene.n
+    k = scene.sh.shape[1] // 3
+    return dict(means=scene.means.astype(np.float32), quats=scene.quats.astype(np.float32),
+                log_scales=np.log(scene.scales).astype(np.float32),
+                logit_opacity=np.log(scene.opacity / (1.0 - scene.opacity)).astype(np.float32),
+                sh=scene.sh.reshape(n, k, 3).astype(np.float32))
+
+
+def make_refine_workload(name="refine", *, seed=None, n=None, views=None, width=None, height=None,
+                         sigma_mean=0.01, sigma_log_scale=0.1, sigma_logit=0.2, sigma_sh=0.05,
+                         sigma_quat=0.05) -> RefineWorkload:
+    spec = dict(REFINE_WORKLOADS[name])
+    seed = spec["seed"] if seed is None else seed
+    rng = np.random.default_rng(seed)
+    kind, nv, rad, W, H = spec["cams"]
+    nv = nv if views is None else views
+    W = W if width is None else width
+    H = H if height is None else height
+    cams = make_cameras((kind, nv, rad, W, H))
+    N = spec["n"] if n is None else n
+    scene = random_gaussians(rng, N, domain=spec["domain"], radius=2.0, sh_degree=3)
+    gt = refine_params(scene)
+    init = dict(
+        means=(gt["means"] + rng.normal(0.0, sigma_mean, gt["means"].shape)).astype(np.float32),
+        quats=(gt["quats"] + rng.normal(0.0, sigma_quat, gt["quats"].shape)).astype(np.float32),
+        log_scales=(gt["log_scales"] + rng.normal(0.0, sigma_log_scale, gt["log_scales"].shape)).astype(np.float32),
+        logit_opacity=(gt["logit_opacity"] + rng.normal(0.0, sigma_logit, N)).astype(np.float32),
+        sh=(gt["sh"] + rng.normal(0.0, sigma_sh, gt["sh"].shape)).astype(np.float32))
+    return RefineWorkload(name=name, gt=gt, init=init, cams=cams,
+                          meta=dict(seed=seed, n=N, views=nv, W=W, H=H))
+
+
+# --------------------------------------------------------------------------
+# clips: a first frame's Gaussians plus F target frames of tracks (each
+# target frame is tracked from the first frame; frame f carries the motion
+# scaled to f / F, fresh noise, outliers and visibility)
+# --------------------------------------------------------------------------
+@dataclass
+class Clip:
+    name: str
+    scene: Scene
+    cams: list
+    disp: np.ndarray          # [F,V,H,W,2] float32
+    vis: np.ndarray           # [F,V,H,W] uint8
+    meta: dict = field(default_factory=dict)
+
+
+def make_clip(name="small", frames=3, *, seed=None, n=None, views=None, width=None, height=None) -> Clip:
+    spec = dict(WORKLOADS[name])
+    seed = spec["seed"] if seed is None else seed
+    wl = make_workload(name, seed=seed, n=n, views=views, width=width, height=height, with_tracks=False)
+    fn = wl.motion.field if wl.motion.field is not None else _nearest_gaussian_motion(wl.scene, wl.motion)
+    rng = np.random.default_rng(seed + 7919)
+    disp, vis = [], []
+    for f in range(1, frames + 1):
+        frac = f / frames
+
+        def fn_f(X, frac=frac):
+            return X + frac * (fn(X) - X)
+
+        d, v = proxy_tracks(rng, wl.cams, fn_f, radius=spec["proxy_radius"], noise_px=spec["noise"],
+                            outlier_rate=spec["outlier"], vis_rate=spec["vis"],
+                            cap_px=None if spec["cap"] is None else 1.25 * spec["cap"])
+        disp.append(d)
+        vis.append(v)
+    return Clip(name=name, scene=wl.scene, cams=wl.cams, disp=np.stack(disp), vis=np.stack(vis),
+                meta=dict(wl.meta, frames=frames))

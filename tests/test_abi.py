@@ -84,6 +84,44 @@ def test_host_side_validation(L):
                                  fake, None, None, None) == 1
 
 
+def test_batch_accumulate_validation(L):
+    from paper_2604_02586_amd import _lib
+    p = _lib.default_params()
+    cams = _cams(2)
+    fake = ctypes.c_void_p(0x10000)
+    s = _lib.Splats(fake, fake, fake, fake, None, None)
+    b = _lib.Bins(fake, fake, fake, fake, fake, 100)
+
+    def slot(F=1, N=10, V=2, cams_=cams, acc=0x10000):
+        sl = _lib.AccSlot(ctypes.addressof(s), ctypes.addressof(b), ctypes.addressof(cams_), N, V, F)
+        for f in range(_lib.TG_MAX_FRAMES):
+            sl.disp[f] = 0x10000
+            sl.acc[f] = acc
+        return sl
+
+    arr = (_lib.AccSlot * 9)(*[slot() for _ in range(9)])
+    # nothing to do
+    assert L.tg_splat_accumulate_batch(arr, 0, ctypes.byref(p), None, None) == 0
+    assert L.tg_splat_accumulate_batch(None, 1, ctypes.byref(p), None, None) == 1
+    # more slots than one launch takes
+    assert L.tg_splat_accumulate_batch(arr, 9, ctypes.byref(p), None, None) == 7
+    # frames per slot 1..4
+    for F, code in [(0, 7), (5, 7)]:
+        one = (_lib.AccSlot * 1)(slot(F=F))
+        assert L.tg_splat_accumulate_batch(one, 1, ctypes.byref(p), None, None) == code
+    # misaligned accumulators, mixed resolutions, negative sizes
+    one = (_lib.AccSlot * 1)(slot(acc=0x10004))
+    assert L.tg_splat_accumulate_batch(one, 1, ctypes.byref(p), None, None) == 2
+    mixed = (_lib.Camera * 2)(_cams(1, 64, 48)[0], _cams(1, 32, 32)[0])
+    one = (_lib.AccSlot * 1)(slot(cams_=mixed))
+    assert L.tg_splat_accumulate_batch(one, 1, ctypes.byref(p), None, None) == 1
+    one = (_lib.AccSlot * 1)(slot(N=-1))
+    assert L.tg_splat_accumulate_batch(one, 1, ctypes.byref(p), None, None) == 1
+    # an error in a later slot launches nothing (checked before any launch)
+    two = (_lib.AccSlot * 2)(slot(), slot(F=9))
+    assert L.tg_splat_accumulate_batch(two, 2, ctypes.byref(p), None, None) == 7
+
+
 def test_workspace_query_and_cell_counts(L):
     from paper_2604_02586_amd import _lib
     p = _lib.default_params()

@@ -95,25 +95,38 @@ def test_transmittance_agrees_with_c_oracle():
     np.testing.assert_allclose(img[..., 0][ok], 1 - r["tfinal"][ok], atol=1e-6)
 
 
-def test_reference_gradient_by_finite_differences():
-    sc = _scene(40, 5)
-    cams = synth.ring_cameras(2, 3.0, 32, 32)
+def test_pixel_subset_matches_dense():
+    sc = _scene(150, 7)
+    cams = synth.ring_cameras(3, 3.0, 40, 36)
     params = _torch_params(sc)
-    geom = None
-    out = raster_ref.render(*params, cams)
+    dense, marg = raster_ref.render(*params, cams, bg=(0.2, 0.1, 0.0), return_marginal=True)
+    rng = np.random.default_rng(2)
+    pv, px, py = rng.integers(0, 3, 60), rng.integers(0, 40, 60), rng.integers(0, 36, 60)
+    sub, msub = raster_ref.render(*params, cams, bg=(0.2, 0.1, 0.0), pixels=(pv, px, py), return_marginal=True)
+    np.testing.assert_allclose(sub.detach().numpy(), dense.detach().numpy()[pv, py, px], rtol=0, atol=1e-13)
+    assert (msub.numpy() == marg.numpy()[pv, py, px]).all()
+
+
+def test_reference_gradient_by_finite_differences():
+    """FP64 central differences (h = 1e-6) on 500 Gaussians, 64x64, two views;
+    pixels with a decision within 1e-3 (relative) of flipping get zero weight,
+    so no difference straddles a discontinuity."""
+    sc = _scene(500, 5)
+    cams = synth.ring_cameras(2, 3.0, 64, 64)
+    params = _torch_params(sc)
+    out, marg = raster_ref.render(*params, cams, return_marginal=True)
     rng = np.random.default_rng(1)
-    Wt = torch.tensor(rng.standard_normal(out.shape))
+    Wt = torch.tensor(rng.standard_normal(out.shape)) * (~marg)[..., None]
     (out * Wt).sum().backward()
     grads = [p.grad.clone() for p in params]
     # freeze the discrete decisions of the unperturbed forward
-    sc32 = synth.Scene(means=sc.means, quats=sc.quats, scales=np.exp(np.log(sc.scales).astype(np.float32)),
-                       opacity=sc.opacity, rgb=sc.rgb)
-    geom = oracle.geometry(sc32, cams)
+    geom = raster_ref._geom_of(*params[:3], cams)
     names = ["means", "quats", "log_scales", "logit", "sh"]
     checked = bad = 0
     for pi, p in enumerate(params):
         flat = p.detach().reshape(-1)
-        for k in rng.choice(flat.numel(), size=min(12, flat.numel()), replace=False):
+        nz = np.nonzero(grads[pi].reshape(-1).numpy())[0]
+        for k in rng.choice(nz, size=min(10, nz.size), replace=False):
             h = 1e-6 * max(1.0, abs(float(flat[k])))
             vals = []
             for sgn in (1, -1):
@@ -123,7 +136,7 @@ def test_reference_gradient_by_finite_differences():
             fd = (vals[0] - vals[1]) / (2 * h)
             an = float(grads[pi].reshape(-1)[k])
             checked += 1
-            if abs(fd - an) > 1e-4 * max(1.0, abs(an)):
+            if abs(fd - an) > 1e-5 * max(1.0, abs(an)):
                 bad += 1
                 print(names[pi], k, fd, an)
-    assert bad <= max(1, checked // 50), (bad, checked)
+    assert checked >= 40 and bad == 0, (bad, checked)
