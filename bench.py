@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -66,6 +67,188 @@ def cpu_baseline(wl, sample_views=2):
                        f"compositing parallel over views", seconds=t)
 
 
+def serving_bench(dev, n_frames=24, clients=4, rates=(2.0, 20.0), seed=12, n_templates=6, budget_gb=96.0):
+    """Serving form: clips drawn like the serving workload (Gaussians
+    log-uniform in [50k, 1M], views uniform in 8..27, resolution from
+    640x480 / 1352x1014 / 1920x1080, 1, 2 or 4 target frames per clip, tracks
+    of the medium workload's kind) from `clients` clients whose frame
+    requests form a Poisson stream at each rate, and with every request
+    waiting at t = 0 (saturation).  The server (continuous batching, HBM
+    budget, resident clips) runs against one-frame-at-a-time cold frames."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2604_02586_amd import api
+    from paper_2604_02586_amd.serving import Server
+
+    rng = np.random.default_rng(seed)
+    res = [(640, 480), (1352, 1014), (1920, 1080)]
+    templates = []
+    t0 = time.perf_counter()
+    for k in range(n_templates):
+        n = int(round(math.exp(rng.uniform(math.log(50_000), math.log(1_000_000)))))
+        V = int(rng.integers(8, 28))
+        W, H = res[int(rng.integers(0, 3))]
+        F = int(rng.choice([1, 2, 4]))
+        wl = synth.make_workload("medium", seed=100 + k, n=n, views=V, width=W, height=H)
+        frames = []
+        for f in range(1, F + 1):
+            d = torch.from_numpy((wl.disp * np.float32(f / F)).astype(np.float32)).pin_memory()
+            frames.append((d, torch.from_numpy(wl.vis).pin_memory()))
+        g = api.GaussianTensors.from_scene(wl.scene, dev)
+        templates.append(dict(n=n, V=V, W=W, H=H, F=F, cams=wl.cams, g=g, frames=frames,
+                              mt=api.MotionTransfer(wl.cams, n, dev)))
+        log(f"  serving template {k}: {n} G x {V} views x {W}x{H}, {F} frames")
+    log(f"  templates in {time.perf_counter() - t0:.1f} s")
+
+    def schedule(rate):
+        """[(arrival, client, clip_no, template, frame)] in arrival order."""
+        reqs, per = [], n_frames // clients
+        order = list(rng.permutation(n_templates))
+        ti = 0
+        for c in range(clients):
+            t, made, clip = 0.0, 0, 0
+            while made < per:
+                tpl = int(order[ti % n_templates])
+                ti += 1
+                for f in range(templates[tpl]["F"]):
+                    if made == per:
+                        break
+                    if rate:
+                        t += rng.exponential(clients / rate)
+                    reqs.append((t, c, clip, tpl, f))
+                    made += 1
+                clip += 1
+        reqs.sort(key=lambda r: (r[0], r[1], r[4]))
+        return reqs
+
+    def clip_sizes(reqs):
+        cnt = {}
+        for _, c, clip, tpl, f in reqs:
+            cnt[c, clip] = cnt.get((c, clip), 0) + 1
+        return cnt
+
+    def run_server(reqs):
+        srv = Server(budget_bytes=int(budget_gb * 2**30))
+        sizes = clip_sizes(reqs)
+        cids, frames, i = {}, [], 0
+        while i < len(reqs) or not srv.sched.idle() or srv.inflight:
+            now = srv.now()
+            while i < len(reqs) and reqs[i][0] <= now:
+                t, c, clip, tpl, f = reqs[i]
+                T = templates[tpl]
+                if (c, clip) not in cids:
+                    cids[c, clip] = len(cids)
+                    srv.open_clip(cids[c, clip], T["g"], T["cams"], sizes[c, clip], now=t)
+                d, v = T["frames"][f]
+                frames.append(srv.submit(cids[c, clip], f + 1, d, v, now=t))
+                i += 1
+            srv.poll()
+            if i < len(reqs) and not srv.inflight:
+                time.sleep(max(0.0, min(0.001, reqs[i][0] - srv.now())))
+            elif srv.inflight:
+                time.sleep(0.0001)
+        lat = np.array([f.done - f.arrival for f in frames])
+        span = max(f.done for f in frames) - min(f.arrival for f in frames)
+        return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                    frames_per_s=len(frames) / span, frames=len(frames), steps=srv.steps,
+                    mean_frames_per_step=float(np.mean(srv.frames_per_step)), max_admitted=srv.max_admitted)
+
+    def run_sequential(reqs):
+        stream = torch.cuda.current_stream()
+        t0 = time.perf_counter()
+        lat, done = [], []
+        for t, c, clip, tpl, f in reqs:
+            while time.perf_counter() - t0 < t:
+                time.sleep(0.0002)
+            T = templates[tpl]
+            mt = T["mt"]
+            d, v = T["frames"][f]
+            dd = d.to(dev, non_blocking=True)
+            vv = v.to(dev, non_blocking=True)
+            out = mt.run(T["g"], dd, vv)
+            stream.synchronize()
+            tn = time.perf_counter() - t0
+            lat.append(tn - t)
+            done.append(tn)
+            del out
+        lat = np.array(lat)
+        return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                    frames_per_s=len(reqs) / (max(done) - min(r[0] for r in reqs)), frames=len(reqs))
+
+    # warm both paths once (library load, allocator, first launches)
+    warm = schedule(0)[:4]
+    run_server(warm)
+    run_sequential(warm)
+    torch.cuda.synchronize()
+    out = {"clients": clients, "frames_per_run": n_frames, "budget_gb": budget_gb,
+           "templates": [dict(gaussians=T["n"], views=T["V"], width=T["W"], height=T["H"], frames=T["F"])
+                         for T in templates]}
+    for rate in list(rates) + [0]:
+        reqs = schedule(rate)
+        key = f"{rate:g}_fps" if rate else "saturation"
+        log(f"  serving at {key}: {len(reqs)} frames")
+        srv = run_server(reqs)
+        seq = run_sequential(reqs)
+        out[key] = {"server": srv, "one_frame_at_a_time": seq,
+                    "frames_per_s_ratio": srv["frames_per_s"] / seq["frames_per_s"]}
+        log(f"    server {srv['frames_per_s']:.1f} frames/s p50 {srv['p50_ms']:.1f} p99 {srv['p99_ms']:.1f} ms; "
+            f"one-at-a-time {seq['frames_per_s']:.1f} frames/s p50 {seq['p50_ms']:.1f} p99 {seq['p99_ms']:.1f} ms")
+    return out
+
+
+def refine_bench(dev, iters=100, warmup=3):
+    """Post-relocation refinement at the refinement workload's shape: 500k
+    Gaussians with degree-3 SH, 16 views at 1352x1014, L1 loss against
+    images rendered from the ground truth, Adam (lr 1e-3) from a perturbed
+    copy; one iteration = preprocess + binning + raster forward, L1,
+    raster backward + projection backward, Adam on every parameter."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2604_02586_amd.raster import Adam, L1Loss, RasterContext, rasterize
+
+    t0 = time.perf_counter()
+    wl = synth.make_refine_workload("refine")
+    N, V, W, H = wl.meta["n"], wl.meta["views"], wl.meta["W"], wl.meta["H"]
+    log(f"  refinement workload {N} G x {V} views x {W}x{H} in {time.perf_counter() - t0:.1f} s")
+    keys = ("means", "quats", "log_scales", "logit_opacity", "sh")
+    gt = [torch.tensor(wl.gt[k], device=dev) for k in keys]
+    rc = RasterContext(wl.cams, N, device=dev)
+    with torch.no_grad():
+        target = rasterize(*gt, rc).clone()
+    del gt
+
+    def fresh():
+        return [torch.tensor(wl.init[k], device=dev, requires_grad=True) for k in keys]
+
+    def run(params, n):
+        opt = Adam(params, lr=1e-3)
+        losses = []
+        for _ in range(n):
+            img = rasterize(*params, rc)
+            loss = L1Loss.apply(img, target)
+            opt.zero_grad()
+            loss.backward()
+            opt.step()
+            losses.append(loss.detach())
+        return losses
+
+    run(fresh(), warmup)
+    params = fresh()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = run(params, iters)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t1
+    losses = [float(x) for x in losses]
+    return {"workload": f"refine: {N} Gaussians (SH degree 3) x {V} views x {W}x{H}, L1 + Adam lr 1e-3",
+            "iterations": iters, "ms_per_iteration": t * 1e3 / iters, "iterations_per_s": iters / t,
+            "loss_first": losses[0], "loss_last": losses[-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +257,9 @@ def main():
     ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warm", action="store_true", help="also time warm frames (resident splats and bins)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-form measurement")
+    ap.add_argument("--serving-frames", type=int, default=24)
+    ap.add_argument("--no-refine", action="store_true", help="skip the refinement measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU frame parallelism is described in the design "
@@ -197,6 +383,17 @@ def main():
     }
     if warm is not None:
         out["warm_ms_per_frame"] = warm
+    if not args.no_serving:
+        log("serving form")
+        del disp, vis, mt
+        torch.cuda.empty_cache()
+        out["serving"] = serving_bench(dev, n_frames=args.serving_frames)
+    if not args.no_refine:
+        log("refinement")
+        torch.cuda.empty_cache()
+        out["refinement"] = refine_bench(dev)
+        log(f"  {out['refinement']['ms_per_iteration']:.2f} ms/iteration, loss {out['refinement']['loss_first']:.4f}"
+            f" -> {out['refinement']['loss_last']:.4f}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(wl)

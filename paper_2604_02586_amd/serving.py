@@ -267,12 +267,17 @@ class Server:
         self.max_inflight = max_inflight
         self.inflight = collections.deque()     # (event, groups, buffers)
         self.pending_clips = {}
-        self.t0_host = time.perf_counter()
+        # common origin of host and GPU clocks: the GPU reaches t0_event
+        # just before the host reads t0_host
         self.t0_event = torch.cuda.Event(enable_timing=True)
         self.t0_event.record(self.compute)
+        self.t0_event.synchronize()
+        self.t0_host = time.perf_counter()
         self.finished = []
         self.steps = 0
         self.slots_launched = 0
+        self.frames_per_step = []
+        self.max_admitted = 0
 
     def now(self):
         return time.perf_counter() - self.t0_host
@@ -305,6 +310,8 @@ class Server:
             with self.torch.cuda.stream(self.compute):
                 c.handle = _Resident(self.api, g, cams_host, self.params, cap)
             c.handle.prepare(self.compute)
+        n_adm = sum(1 for c in self.sched.clips.values() if c.state == "admitted")
+        self.max_admitted = max(self.max_admitted, n_adm)
 
     def _upload(self):
         torch = self.torch
@@ -371,6 +378,7 @@ class Server:
                 f.payload = None
         self.steps += 1
         self.slots_launched += len(groups)
+        self.frames_per_step.append(sum(len(fr) for _, fr in groups))
         return True
 
     def _retire(self):

@@ -5,8 +5,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import (compare_accumulators, dump, eigen_gap, log, oracle_full, rotation_angle_deg, run_gpu,
-                     sensitivity_mask)
+from helpers import check_end_to_end, compare_accumulators, dump, log, oracle_full, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -128,37 +127,4 @@ def test_solve_views_parity(pair):
 
 def test_end_to_end_parity(pair):
     case, wl, ref, gpu = pair
-    tri = ref["tri"]
-    unstable = sensitivity_mask(wl, ref)
-    st_g, st_o = gpu["status"], tri["status"]
-    mism = (st_g != st_o) & ~unstable
-    log(f"[{case}] status mismatches {mism.sum()} / {st_o.size}; unstable excluded {unstable.sum()}")
-    assert mism.sum() <= max(2, 2e-3 * st_o.size)
-    pos = ((st_g & oracle.ST_POS) > 0) & ((st_o & oracle.ST_POS) > 0) & ~unstable
-    dpos = np.linalg.norm(gpu["means"][pos].astype(np.float64) - tri["means"][pos], axis=-1)
-    assert np.all(dpos <= 1e-3), dpos.max()
-    cov = ((st_g & oracle.ST_COV) > 0) & ((st_o & oracle.ST_COV) > 0) & ~unstable
-    gap = eigen_gap(tri["eig"])
-    rot = cov & (gap >= 1e-2)
-    ang = rotation_angle_deg(gpu["quats"][rot].astype(np.float64), tri["quats"][rot])
-    assert np.all(ang <= 0.05), ang.max()
-    assert np.all(gpu["quats"][rot][:, 0] >= 0)
-    # degenerate eigen-gap: compare Sigma_3D' instead
-    deg = cov & (gap < 1e-2)
-    if deg.any():
-        Rg = oracle.quat_to_rot(gpu["quats"][deg].astype(np.float64))
-        Ro = oracle.quat_to_rot(tri["quats"][deg])
-        Sg = Rg @ (gpu["scales"][deg][:, :, None] ** 2 * np.swapaxes(Rg, -1, -2))
-        So = Ro @ (tri["scales"][deg][:, :, None] ** 2 * np.swapaxes(Ro, -1, -2))
-        rel = np.linalg.norm(Sg - So, axis=(1, 2)) / np.linalg.norm(So, axis=(1, 2))
-        assert np.all(rel <= 1e-3), rel.max()
-    sc = np.abs(gpu["scales"][cov] / tri["scales"][cov] - 1)
-    assert np.all(sc <= 1e-3), sc.max()
-    # what was not updated is copied bit-exactly
-    keep = (st_g & oracle.ST_POS) == 0
-    np.testing.assert_array_equal(gpu["means"][keep], wl.scene.means[keep])
-    keepc = (st_g & oracle.ST_COV) == 0
-    np.testing.assert_array_equal(gpu["quats"][keepc], wl.scene.quats[keepc])
-    np.testing.assert_array_equal(gpu["scales"][keepc], wl.scene.scales[keepc])
-    log(f"[{case}] e2e: pos {pos.sum()} max {dpos.max() if dpos.size else 0:.2e}; rot {rot.sum()} "
-        f"max {ang.max() if ang.size else 0:.2e} deg")
+    check_end_to_end(case, wl, ref, gpu)
