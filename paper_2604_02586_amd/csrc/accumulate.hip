@@ -106,12 +106,13 @@ __device__ __forceinline__ void sums_add(Sums& s, float wgt, float wx, float wy,
 template <int FM, bool STATS>
 __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
 {
-    // 3.5 KB of LDS per wave keeps 8 waves per SIMD resident:
-    // queue of filtered list entries (ids), per-pixel column/row offsets
-    // inside the tile (as floats) and per-pixel transmittance
+    // 5.6 KB of LDS per wave (about 7 waves per SIMD): queue of filtered
+    // list entries (ids), per-pixel column/row offsets inside the tile (as
+    // floats), per-pixel transmittance and the atomics' transpose buffer
     __shared__ uint32_t qi[QCAP];
     __shared__ float2 CR[256];
     __shared__ float T_[256];
+    __shared__ float SA[32 * 17];   // 32 records in flight to the atomics
     // XCD-aware remap: hardware places workgroup b on XCD (b mod 8); give
     // each XCD a contiguous range of tiles (its L2 then holds those bins).
     const int64_t b = blockIdx.x;
@@ -345,28 +346,50 @@ __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
             }
             alive[g] &= ~dead;
         }
+        // Flush through LDS: each lane's record is transposed so that one
+        // atomic instruction adds 4 records (16 lanes each, one record per
+        // 64-byte half line) instead of touching 64 lines.  Zero sums are
+        // skipped (adding +0 never changes a sum that starts at +0), which
+        // also skips lanes without contributions and the static slots when
+        // no static pixel was seen.
 #pragma unroll
         for (int f = 0; f < FM; ++f) {
             const Sums& s = sm[f];
-            if (lane < nb && s.n > 0.0f) {
-                float* dst = S.acc[f] + (vN + gid) * TG_ACC_STRIDE;
-                unsafeAtomicAdd(dst + 0, s.w);
-                unsafeAtomicAdd(dst + 1, s.ux);
-                unsafeAtomicAdd(dst + 2, s.uy);
-                unsafeAtomicAdd(dst + 3, s.xx);
-                unsafeAtomicAdd(dst + 4, s.xy);
-                unsafeAtomicAdd(dst + 5, s.yy);
-                unsafeAtomicAdd(dst + 6, s.dx);
-                unsafeAtomicAdd(dst + 7, s.dy);
-                unsafeAtomicAdd(dst + 8, s.xdx);
-                unsafeAtomicAdd(dst + 9, s.xdy);
-                unsafeAtomicAdd(dst + 10, s.ydx);
-                unsafeAtomicAdd(dst + 11, s.ydy);
-                unsafeAtomicAdd(dst + 12, s.n);
-                if (s.sn > 0.0f) {
-                    unsafeAtomicAdd(dst + 13, s.sn);
-                    unsafeAtomicAdd(dst + 14, s.sa);
+            float* const accf = S.acc[f];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (32 * h >= nb) break;
+                const int rl = lane - 32 * h;
+                if (rl >= 0 && rl < 32) {
+                    float* r = SA + rl * 17;
+                    r[0] = s.w;
+                    r[1] = s.ux;
+                    r[2] = s.uy;
+                    r[3] = s.xx;
+                    r[4] = s.xy;
+                    r[5] = s.yy;
+                    r[6] = s.dx;
+                    r[7] = s.dy;
+                    r[8] = s.xdx;
+                    r[9] = s.xdy;
+                    r[10] = s.ydx;
+                    r[11] = s.ydy;
+                    r[12] = s.n;
+                    r[13] = s.sn;
+                    r[14] = s.sa;
+                    r[15] = __builtin_bit_cast(float, gid);
                 }
+                __syncthreads();
+                const int rec_n = min(32, nb - 32 * h);
+                const int k = lane & 15;
+                for (int q = 0; 4 * q < rec_n; ++q) {
+                    const int gl = 4 * q + (lane >> 4);
+                    const float val = SA[gl * 17 + k];
+                    const uint32_t gg = __builtin_bit_cast(uint32_t, SA[gl * 17 + 15]);
+                    if (k < 15 && gl < rec_n && val != 0.0f)
+                        unsafeAtomicAdd(accf + (vN + gg) * TG_ACC_STRIDE + k, val);
+                }
+                __syncthreads();
             }
         }
     }

@@ -313,7 +313,11 @@ __global__ void __launch_bounds__(128) k_triangulate(TriArgs a, CamPack cams, tg
             double dmax = 0.0;
 #pragma unroll
             for (int i = 0; i < 6; ++i) dmax = fmax(dmax, AtA[i * 6 + i]);
-            bool pd = dmax > 0.0;
+            // two solved views leave the 6-unknown system at rank 5 (the
+            // symmetric product of the two viewing rays is seen by neither),
+            // a structural fact that FP64 pivots cannot resolve (their
+            // rounding floor sits near 1e-16 of the largest)
+            bool pd = dmax > 0.0 && nv >= 3;
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
                 double d = AtA[j * 6 + j];

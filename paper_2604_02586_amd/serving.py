@@ -254,7 +254,7 @@ class Server:
     poll() -- admit, upload, launch, retire; returns finished frames
     """
 
-    def __init__(self, budget_bytes, params=None, max_inflight=3, device="cuda"):
+    def __init__(self, budget_bytes, params=None, max_inflight=3, device="cuda", keep_intermediate=False):
         import torch
         from . import api
         self.api = api
@@ -265,6 +265,7 @@ class Server:
         self.compute = torch.cuda.Stream(device=self.device)
         self.copy = torch.cuda.Stream(device=self.device)
         self.max_inflight = max_inflight
+        self.keep_intermediate = keep_intermediate
         self.inflight = collections.deque()     # (event, groups, buffers)
         self.pending_clips = {}
         # common origin of host and GPU clocks: the GPU reaches t0_event
@@ -368,7 +369,7 @@ class Server:
                                               g.scale_mode, g.opacity_mode)
                     api.solve_views(acc, r.splats, r.N, r.V, self.params, mu, cov, vfl)
                     api.triangulate(mu, cov, vfl, acc, r.splats, g, r.cams, self.params, out, st)
-                    f.result = (out, st)
+                    f.result = (out, st, acc, mu, cov, vfl) if self.keep_intermediate else (out, st)
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(self.compute)
         # the step holds its buffers until it retires

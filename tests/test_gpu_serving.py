@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import synth
-from helpers import check_end_to_end, eigen_gap, log, rotation_angle_deg, sensitivity_mask
+from helpers import check_end_to_end, compare_accumulators, dump, eigen_gap, log, rotation_angle_deg, sensitivity_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -23,9 +23,12 @@ CLIPS = [
 ]
 
 
-def _host(out, st):
+def _host(out, st, acc=None, mu=None, cov=None, vfl=None):
     h = lambda t: t.detach().cpu().numpy()
-    return dict(means=h(out.means), quats=h(out.quats), scales=h(out.scales), status=h(st).view(np.uint32))
+    r = dict(means=h(out.means), quats=h(out.quats), scales=h(out.scales), status=h(st).view(np.uint32))
+    if acc is not None:
+        r.update(acc=h(acc), mu_new=h(mu), cov_new=h(cov), vflags=h(vfl))
+    return r
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +47,7 @@ def runs():
             v = torch.as_tensor(c.vis[f]).to(dev).contiguous()
             out = mt.run(g, d, v)
             torch.cuda.synchronize()
-            alone[ci, f] = _host(out, mt.status)
+            alone[ci, f] = _host(out, mt.status, mt.acc, mt.mu_new, mt.cov_new, mt.vflags)
     log(f"alone: {len(alone)} frames")
     # mix: a budget that holds two clips at once
     probe = Server(budget_bytes=1 << 50)
@@ -54,7 +57,7 @@ def runs():
         need.append(cs.nbytes + frame_bytes(c.scene.n, len(c.cams), c.cams[0].H, c.cams[0].W))
     # room for any two clips at once, never for all three
     budget = sum(need) - 1
-    srv = Server(budget_bytes=budget)
+    srv = Server(budget_bytes=budget, keep_intermediate=True)
     for ci, (c, g) in enumerate(zip(clips, gs)):
         srv.open_clip(ci, g, c.cams, c.disp.shape[0])
     rng = np.random.default_rng(9)
@@ -75,6 +78,9 @@ def runs():
     srv.drain()
     torch.cuda.synchronize()
     mix = {k: _host(*fr.result) for k, fr in frames.items()}
+    for (ci, f), r in mix.items():
+        dump(f"serve_mix_{ci}_{f}", r)
+        dump(f"serve_alone_{ci}_{f}", alone[ci, f])
     log(f"mix: {srv.steps} steps, {srv.slots_launched} slots, max admitted {srv.max_admitted}")
     return clips, alone, mix, srv
 
@@ -86,6 +92,18 @@ def test_every_frame_finished_with_batching_and_queueing(runs):
     assert srv.max_admitted < len(clips)        # admission queued a clip
     assert srv.steps < len(mix)                 # some step carried several frames
     assert max(srv.frames_per_step) >= 2
+
+
+def test_mix_matches_oracle(runs):
+    clips, _, mix, _ = runs
+    for (ci, f), m in sorted(mix.items()):
+        c = clips[ci]
+        wl = SimpleNamespace(scene=c.scene, cams=c.cams)
+        ref = oracle.motion_transfer(c.scene, c.cams, c.disp[f], c.vis[f])
+        nbad, ntot, info = compare_accumulators(m["acc"], ref["comp"])
+        log(f"clip {ci} frame {f}: accumulators {nbad}/{ntot} outside tolerance {info}")
+        assert nbad == 0, info
+        check_end_to_end(f"clip {ci} frame {f}", wl, ref, m)
 
 
 def test_mix_equals_alone(runs):
@@ -109,12 +127,3 @@ def test_mix_equals_alone(runs):
         assert ang.size == 0 or ang.max() <= 0.05, ang.max()
         log(f"clip {ci} frame {f}: status diff {diff.sum()}, max dpos {dpos.max() if dpos.size else 0:.2e}, "
             f"max rot {ang.max() if ang.size else 0:.2e} deg")
-
-
-def test_mix_matches_oracle(runs):
-    clips, _, mix, _ = runs
-    for (ci, f), m in sorted(mix.items()):
-        c = clips[ci]
-        wl = SimpleNamespace(scene=c.scene, cams=c.cams)
-        ref = oracle.motion_transfer(c.scene, c.cams, c.disp[f], c.vis[f])
-        check_end_to_end(f"clip {ci} frame {f}", wl, ref, m)
