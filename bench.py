@@ -42,7 +42,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, sample_views=2):
+def cpu_baseline(wl, sample_views=8):
     """The oracle on a bounded sample: `sample_views` of the views, all
     pixels, all Gaussians, through solve and triangulation; extrapolated
     linearly in the number of views."""
@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-form measurement")
     ap.add_argument("--serving-frames", type=int, default=24)
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU frame parallelism is described in the design "
@@ -273,6 +275,13 @@ def main():
     from paper_2604_02586_amd import api
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 1 GiB read + 1 GiB written")
     log(f"generating workload '{args.workload}'")
     t0 = time.perf_counter()
     wl = synth.make_workload(args.workload)

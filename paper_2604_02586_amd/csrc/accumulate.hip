@@ -106,11 +106,11 @@ __device__ __forceinline__ void sums_add(Sums& s, float wgt, float wx, float wy,
 template <int FM, bool STATS>
 __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
 {
-    // 5.6 KB of LDS per wave (about 7 waves per SIMD): queue of filtered
-    // list entries (ids), per-pixel column/row offsets inside the tile (as
-    // floats), per-pixel transmittance and the atomics' transpose buffer
+    // 3.7 KB of LDS per wave: queue of filtered list entries (ids), column
+    // offsets as floats, per-pixel transmittance and the atomics' transpose
+    // buffer
     __shared__ uint32_t qi[QCAP];
-    __shared__ float2 CR[256];
+    __shared__ float CF[16];        // column offsets 0..15 as floats
     __shared__ float T_[256];
     __shared__ float SA[32 * 17];   // 32 records in flight to the atomics
     // XCD-aware remap: hardware places workgroup b on XCD (b mod 8); give
@@ -145,6 +145,7 @@ __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
     const int px0 = tx * TG_TILE, py0 = ty * TG_TILE;
     const int64_t row_base = (int64_t)v * H;
     const int lane = threadIdx.x;
+    if (lane < 16) CF[lane] = (float)lane;
 
     // pixel state: pixel j = g*64 + lane -> (px0 + (j&15), py0 + (j>>4));
     // flags of pixel j: bit f = track visible in frame f, bit 8+f = static
@@ -179,7 +180,6 @@ __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
             dxg[f][g] = ddx;
             dyg[f][g] = ddy;
         }
-        CR[j] = make_float2((float)(j & 15), (float)(j >> 4));
         T_[j] = 1.0f;
         flg[g] = fl;
         alive[g] = ballot64(in);
@@ -250,22 +250,29 @@ __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
 
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            uint64_t m = alive[g];
             uint64_t dead = 0;
-            // two pixels per step: their dependency chains interleave
-            while (m) {
-                const int j1 = __builtin_ctzll(m);
+            for (int rr = 0; rr < 4; ++rr) {
+              uint32_t m = (uint32_t)(alive[g] >> (16 * rr)) & 0xFFFFu;
+              if (m == 0u) continue;
+              // the row's share of the quadratic form, common to its pixels:
+              // q = ux (ca ux + cb uy) + cc uy^2
+              const float uy = dyl + (float)(4 * g + rr);
+              const float brow = cb * uy;
+              const float hrow = cc * uy * uy;
+              // two pixels per step: their dependency chains interleave
+              while (m) {
+                const int c1 = __builtin_ctz(m);
                 m &= m - 1;
                 const bool two = m != 0;
-                const int j2 = two ? (int)__builtin_ctzll(m) : j1;
+                const int c2 = two ? (int)__builtin_ctz(m) : c1;
                 if (two) m &= m - 1;
+                const int j1 = 16 * rr + c1, j2 = 16 * rr + c2;
                 const int p1 = g * 64 + j1, p2i = g * 64 + j2;
-                const float2 cr1 = CR[p1], cr2 = CR[p2i];
                 const float T1 = T_[p1], T2 = T_[p2i];
-                const float ux1 = dxl + cr1.x, uy1 = dyl + cr1.y;
-                const float ux2 = dxl + cr2.x, uy2 = dyl + cr2.y;
-                const float q1 = ux1 * (ca * ux1 + cb * uy1) + cc * uy1 * uy1;
-                const float q2 = ux2 * (ca * ux2 + cb * uy2) + cc * uy2 * uy2;
+                const float ux1 = dxl + CF[c1], ux2 = dxl + CF[c2];
+                const float uy1 = uy, uy2 = uy;
+                const float q1 = ux1 * (ca * ux1 + brow) + hrow;
+                const float q2 = ux2 * (ca * ux2 + brow) + hrow;
                 // alpha = min(alpha_max, o e^power), clamped with one v_med3
                 const float al1 = __builtin_amdgcn_fmed3f(op * __builtin_amdgcn_exp2f(q1), 0.0f, amax);
                 const float al2 = __builtin_amdgcn_fmed3f(op * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
@@ -343,6 +350,7 @@ __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
                                          al2);
                     }
                 }
+              }
             }
             alive[g] &= ~dead;
         }

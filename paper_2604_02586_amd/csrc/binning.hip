@@ -128,21 +128,30 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(uint32_t* __restrict
 // ---- stable scatter --------------------------------------------------------
 // Items of a block: wave w owns keys [w*1024, (w+1)*1024) of the block's 4096,
 // visited in 16 rounds of 64 consecutive keys, so order within the block is
-// (wave, round, lane) = input order.
+// (wave, round, lane) = input order.  Each key is first placed at its stable
+// rank inside the block (digit-major) in LDS; the block then writes the LDS
+// array out in order, so consecutive threads write consecutive addresses of
+// one digit's run instead of 64 scattered words per instruction.
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t seg_len, const int64_t* __restrict__ dev_count, int shift,
     const uint32_t* __restrict__ goff, int nblk)
 {
     __shared__ uint32_t woff[SORT_WAVES][256];
+    __shared__ uint32_t gdelta[256];     // global start of the digit minus its block-local start
+    __shared__ uint32_t wtot[SORT_WAVES];
+    __shared__ uint32_t LK[SORT_TILE];
+    __shared__ uint32_t LV[SORT_TILE];
     const int seg = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
     const int64_t n = seg_count(seg_len, dev_count);
     const int64_t base = (int64_t)b * SORT_TILE;
     if (base >= n) return;  // uniform per block
+    const int nvalid = (int)((n - base) < SORT_TILE ? (n - base) : SORT_TILE);
     for (int i = t; i < SORT_WAVES * 256; i += SORT_THREADS) (&woff[0][0])[i] = 0;
     __syncthreads();
     const int64_t so = (int64_t)seg * seg_len;
+    const bool with_v = vout != nullptr;
     uint32_t k[SORT_ITEMS], val[SORT_ITEMS];
 #pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
@@ -158,12 +167,27 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
     }
     __syncthreads();
     {
-        uint32_t run = goff[((int64_t)seg * 256 + t) * nblk + b];
+        // thread t owns digit t: block-local start of the digit (exclusive
+        // scan of the digit totals), then each wave's start inside it
+        uint32_t c[SORT_WAVES], tot = 0;
 #pragma unroll
         for (int ww = 0; ww < SORT_WAVES; ++ww) {
-            uint32_t c = woff[ww][t];
+            c[ww] = woff[ww][t];
+            tot += c[ww];
+        }
+        const uint32_t inc = wave_scan_add_u32(tot);
+        if (l == 63) wtot[w] = inc;
+        __syncthreads();
+        uint32_t start = inc - tot;
+#pragma unroll
+        for (int ww = 0; ww < SORT_WAVES; ++ww)
+            if (ww < w) start += wtot[ww];
+        gdelta[t] = goff[((int64_t)seg * 256 + t) * nblk + b] - start;
+        uint32_t run = start;
+#pragma unroll
+        for (int ww = 0; ww < SORT_WAVES; ++ww) {
             woff[ww][t] = run;
-            run += c;
+            run += c[ww];
         }
     }
     __syncthreads();
@@ -182,12 +206,21 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
         }
         if (active) {
             uint32_t rank = (uint32_t)__popcll(m & lt);
-            uint32_t pos = woff[w][d] + rank;
-            if (pos < (uint64_t)n) {  // always true for a consistent histogram
-                if (kout) kout[so + pos] = k[r];
-                if (vout) vout[so + pos] = val[r];
+            uint32_t pos = woff[w][d] + rank;       // < nvalid for a consistent histogram
+            if (pos < (uint32_t)nvalid) {
+                LK[pos] = k[r];
+                if (with_v) LV[pos] = val[r];
             }
             if (rank == 0) woff[w][d] += (uint32_t)__popcll(m);
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < nvalid; i += SORT_THREADS) {
+        const uint32_t key = LK[i];
+        const uint32_t pos = gdelta[(key >> shift) & 255u] + (uint32_t)i;
+        if (pos < (uint64_t)n) {  // always true for a consistent histogram
+            if (kout) kout[so + pos] = key;
+            if (with_v) vout[so + pos] = LV[i];
         }
     }
 }
