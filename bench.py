@@ -256,10 +256,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--warm", action="store_true", help="also time warm frames (resident splats and bins)")
+    ap.add_argument("--no-warm", action="store_true", help="skip timing warm frames (resident splats and bins)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-form measurement")
     ap.add_argument("--serving-frames", type=int, default=24)
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement measurement")
+    ap.add_argument("--only", choices=["serving", "refine"],
+                    help="run one secondary measurement alone (for profiling); prints its own JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -282,6 +284,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("copy calibration: 1 GiB read + 1 GiB written")
+    if args.only:
+        part = serving_bench(dev, n_frames=args.serving_frames) if args.only == "serving" else refine_bench(dev)
+        print(json.dumps({"metric": METRIC, "only": args.only, args.only: part}), flush=True)
+        return
     log(f"generating workload '{args.workload}'")
     t0 = time.perf_counter()
     wl = synth.make_workload(args.workload)
@@ -348,7 +354,7 @@ def main():
     st = mt.status.cpu().numpy().view(np.uint32)
 
     warm = None
-    if args.warm:
+    if not args.no_warm:
         for _ in range(args.warmup):
             mt.run_warm(g, disp, vis, g_out)
         torch.cuda.synchronize()

@@ -21,27 +21,28 @@ struct SplatOut {
     uint8_t* clamped;
 };
 
-// Real spherical harmonics up to degree 3 (Condon-Shortley phase), for a
-// unit direction; coefficients sh[k*3 + ch].
-__device__ inline void sh_color(const float* sh, int deg, float x, float y, float z, float out[3]) {
-    const float c0 = 0.28209479177387814f;
-    const float c1 = 0.48860251190291992f;
-    float b[16];
-    int nb = (deg + 1) * (deg + 1);
-    b[0] = c0;
-    if (deg > 0) {
+// Real spherical harmonics up to degree DEG (Condon-Shortley phase) at a
+// unit direction, dotted with the coefficients c[k*3 + ch] (held in
+// registers: DEG is a compile-time constant, so every index is static).
+template <int DEG>
+__device__ inline void sh_color(const float* c, float x, float y, float z, float out[3]) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    float b[NB];
+    b[0] = 0.28209479177387814f;
+    if constexpr (DEG > 0) {
+        const float c1 = 0.48860251190291992f;
         b[1] = -c1 * y;
         b[2] = c1 * z;
         b[3] = -c1 * x;
     }
-    if (deg > 1) {
-        float xx = x * x, yy = y * y, zz = z * z;
+    if constexpr (DEG > 1) {
+        const float xx = x * x, yy = y * y, zz = z * z;
         b[4] = 1.0925484305920792f * x * y;
         b[5] = -1.0925484305920792f * y * z;
         b[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
         b[7] = -1.0925484305920792f * x * z;
         b[8] = 0.54627421529603959f * (xx - yy);
-        if (deg > 2) {
+        if constexpr (DEG > 2) {
             b[9] = -0.59004358992664352f * y * (3.0f * xx - yy);
             b[10] = 2.8906114426405538f * x * y * z;
             b[11] = -0.45704579946446572f * y * (4.0f * zz - xx - yy);
@@ -51,17 +52,21 @@ __device__ inline void sh_color(const float* sh, int deg, float x, float y, floa
             b[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
         }
     }
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         float acc = 0.0f;
-        for (int k = 0; k < nb; ++k) acc += b[k] * sh[k * 3 + ch];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) acc += b[k] * c[k * 3 + ch];
         out[ch] = acc + 0.5f;
     }
 }
 
+// DEG: SH degree of the colours (-1: no SH coefficients).
+template <int DEG>
 __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ means, const float* __restrict__ quats,
     const float* __restrict__ scales, const float* __restrict__ opac,
-    const float* __restrict__ sh, int sh_deg, int scale_mode, int opacity_mode,
+    const float* __restrict__ sh, int scale_mode, int opacity_mode,
     int64_t N, int V, int64_t out_view0, CamPack cams, tg_params prm, SplatOut out)
 {
 #pragma clang fp contract(off)
@@ -118,6 +123,15 @@ __global__ void __launch_bounds__(256) k_preprocess(
                 D[k++] = dr[3 * i] * dr[3 * j] * ss[0] + dr[3 * i + 1] * dr[3 * j + 1] * ss[1] +
                          dr[3 * i + 2] * dr[3 * j + 2] * ss[2];
             }
+    }
+
+    // the Gaussian's SH coefficients, read once for all views
+    constexpr int NC = DEG >= 0 ? 3 * (DEG + 1) * (DEG + 1) : 1;
+    float shc[NC];
+    if constexpr (DEG >= 0) {
+        const float* src = sh + g * NC;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) shc[i] = src[i];
     }
 
     for (int v = 0; v < V; ++v) {
@@ -230,14 +244,14 @@ __global__ void __launch_bounds__(256) k_preprocess(
         if (out.colors) {
             float col[3] = {0.f, 0.f, 0.f};
             uint8_t cl[3] = {0, 0, 0};
-            if (ok && sh) {
+            if (DEG >= 0 && ok) {
                 // camera centre = -R^T t
                 float ccx = -(R[0] * c.t[0] + R[3] * c.t[1] + R[6] * c.t[2]);
                 float ccy = -(R[1] * c.t[0] + R[4] * c.t[1] + R[7] * c.t[2]);
                 float ccz = -(R[2] * c.t[0] + R[5] * c.t[1] + R[8] * c.t[2]);
                 float ex = m0 - ccx, ey = m1 - ccy, ez = m2 - ccz;
                 float il = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
-                sh_color(sh + g * 3 * (sh_deg + 1) * (sh_deg + 1), sh_deg, ex * il, ey * il, ez * il, col);
+                if constexpr (DEG >= 0) sh_color<DEG>(shc, ex * il, ey * il, ez * il, col);
                 for (int ch = 0; ch < 3; ++ch) {
                     if (col[ch] < 0.0f) { col[ch] = 0.0f; cl[ch] = 1; }
                 }
@@ -279,9 +293,19 @@ extern "C" tg_status tg_preprocess(const tg_gaussians* g, int64_t N, const tg_ca
         int nv = V - v0 < TG_MAX_VIEWS ? V - v0 : TG_MAX_VIEWS;
         CamPack cp;
         for (int i = 0; i < nv; ++i) cp.cam[i] = cams[v0 + i];
-        hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(threads), 0, s, g->means, g->quats,
-                           g->scales, g->opacity, g->sh, g->sh_degree, g->scale_mode, g->opacity_mode, N, nv,
-                           (int64_t)v0, cp, *p, so);
+        const int deg = (g->sh && out->colors) ? g->sh_degree : -1;
+#define TG_PRE_LAUNCH(D)                                                                                        \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_preprocess<D>), dim3((unsigned)blocks), dim3(threads), 0, s, g->means, \
+                       g->quats, g->scales, g->opacity, g->sh, g->scale_mode, g->opacity_mode, N, nv, (int64_t)v0, \
+                       cp, *p, so)
+        switch (deg) {
+            case 0: TG_PRE_LAUNCH(0); break;
+            case 1: TG_PRE_LAUNCH(1); break;
+            case 2: TG_PRE_LAUNCH(2); break;
+            case 3: TG_PRE_LAUNCH(3); break;
+            default: TG_PRE_LAUNCH(-1); break;
+        }
+#undef TG_PRE_LAUNCH
         TG_CHECK_LAUNCH();
     }
     return TG_OK;

@@ -150,12 +150,11 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                                                    const int32_t* __restrict__ n_proc, float* __restrict__ grad2d)
 {
     __shared__ uint32_t qi[QCAP];
-    // per pixel: absolute coordinates, final colour, dL/dC, and the running
-    // transmittance / front colour
-    __shared__ float2 XY[256];
-    __shared__ float4 CF[256];   // final colour, T
+    // per pixel: the colour still to come (final colour minus the front
+    // already composited) with the running transmittance, and dL/dC
+    __shared__ float4 RT[256];   // remaining colour (r, g, b), T
     __shared__ float4 GF[256];   // dL/dC, unused
-    __shared__ float4 FR[256];   // front colour (r, g, b), unused
+    __shared__ float CFt[16], RFt[4];   // column / row offsets as floats
     if (*a.overflow) return;
     const int64_t b = blockIdx.x;
     const int64_t L = (b & 7) * a.blocks_per_xcd + (b >> 3);
@@ -174,6 +173,8 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
 
     uint64_t alive[4];
     int npg[4];  // n_proc of pixel g*64 + lane
+    if (lane < 16) CFt[lane] = (float)lane;
+    if (lane < 4) RFt[lane] = (float)lane;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int j = g * 64 + lane;
@@ -187,10 +188,8 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
             gf = make_float4(dimage[3 * pi], dimage[3 * pi + 1], dimage[3 * pi + 2], 0.0f);
             np = n_proc[pi];
         }
-        XY[j] = make_float2((float)px, (float)py);
-        CF[j] = cf;
+        RT[j] = cf;
         GF[j] = gf;
-        FR[j] = make_float4(0.f, 0.f, 0.f, 0.f);
         npg[g] = np;
         alive[g] = ballot64(in && np > 0);
     }
@@ -248,21 +247,23 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
         const uint32_t my_idx = bstart + (uint32_t)lane;
 
         float g_mx = 0.f, g_my = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f;
+        const float fx0 = (float)px0;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             uint64_t m = alive[g];
             uint64_t dead = 0;
+            const float fy0 = (float)(py0 + 4 * g);
             while (m) {
                 const int j = __builtin_ctzll(m);
                 m &= m - 1;
                 const int pj = g * 64 + j;
                 const int np = __builtin_amdgcn_readlane(npg[g], j);
                 if ((uint32_t)np <= bstart + (uint32_t)nb) dead |= 1ull << j;  // last batch for this pixel
-                const float2 xy = XY[pj];
-                const float4 cf = CF[pj];
+                const float4 rt = RT[pj];
                 const float4 gf = GF[pj];
-                const float4 fr = FR[pj];
-                const float ux = xy.x - mx, uy = xy.y - my;
+                // pixel coordinates exactly as the forward forms them (integer
+                // sums are exact in FP32), so alpha is bit-identical
+                const float ux = (fx0 + CFt[j & 15]) - mx, uy = (fy0 + RFt[j >> 4]) - my;
                 const float p2 = ux * (ca * ux + cb * uy) + cc * uy * uy;
                 const float e2 = op * __builtin_amdgcn_exp2f(p2);
                 const float al = __builtin_amdgcn_fmed3f(e2, 0.0f, amax);
@@ -273,7 +274,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 P = wave_scan_mul_fused(P);
                 asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
                              : "+v"(pex_reg) : "v"(P));
-                const float Ti = cf.w * pex_reg;
+                const float Ti = rt.w * pex_reg;
                 const float wgt = valid ? al * Ti : 0.0f;
                 const float w0 = c0 * wgt, w1 = c1 * wgt, w2 = c2 * wgt;
                 const float F0 = wave_scan_add_fused(w0);
@@ -281,7 +282,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 const float F2 = wave_scan_add_fused(w2);
                 if (valid) {
                     // colour behind lane i (incl. background): C - front - own
-                    const float S0 = cf.x - fr.x - F0, S1 = cf.y - fr.y - F1, S2 = cf.z - fr.z - F2;
+                    const float S0 = rt.x - F0, S1 = rt.y - F1, S2 = rt.z - F2;
                     const float inv1m = 1.0f / (1.0f - al);
                     const float dal = gf.x * (c0 * Ti - S0 * inv1m) + gf.y * (c1 * Ti - S1 * inv1m) +
                                       gf.z * (c2 * Ti - S2 * inv1m);
@@ -298,14 +299,11 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                         g_C += dpow * (-0.5f * uy * uy);
                     }
                 }
-                // advance this pixel's transmittance and front colour
-                const float Tn = cf.w * readlane_f(P, 63);
-                const float f0 = fr.x + readlane_f(F0, 63), f1 = fr.y + readlane_f(F1, 63),
-                            f2 = fr.z + readlane_f(F2, 63);
-                if (lane0) {
-                    CF[pj] = make_float4(cf.x, cf.y, cf.z, Tn);
-                    FR[pj] = make_float4(f0, f1, f2, 0.0f);
-                }
+                // advance this pixel's transmittance and remaining colour
+                const float Tn = rt.w * readlane_f(P, 63);
+                const float r0 = rt.x - readlane_f(F0, 63), r1 = rt.y - readlane_f(F1, 63),
+                            r2 = rt.z - readlane_f(F2, 63);
+                if (lane0) RT[pj] = make_float4(r0, r1, r2, Tn);
             }
             alive[g] &= ~dead;
         }
@@ -326,48 +324,54 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
 }
 
 // ------------------------------------------------------- projection backward
-// d/d(direction) of the real SH basis (polynomial form, unit direction).
-__device__ inline void sh_basis_and_grad(int deg, float x, float y, float z, float Y[16], float dY[16][3]) {
+// Real SH basis Y_k (degree DEG) at a unit direction, and the direction
+// gradient sum_k a_k dY_k/d(x, y, z) (polynomial form) without storing dY.
+template <int DEG>
+__device__ inline void sh_basis_dir_grad(float x, float y, float z, float Y[(DEG + 1) * (DEG + 1)],
+                                         const float a[(DEG + 1) * (DEG + 1)], float g[3]) {
     const float c0 = 0.28209479177387814f, c1 = 0.48860251190291992f;
     const float k4 = 1.0925484305920792f, k6 = 0.31539156525252005f, k8 = 0.54627421529603959f;
     const float k9 = -0.59004358992664352f, k10 = 2.8906114426405538f, k11 = -0.45704579946446572f;
     const float k12 = 0.37317633259011540f, k13 = -0.45704579946446572f, k14 = 1.4453057213202769f;
     const float k15 = -0.59004358992664352f;
-    for (int i = 0; i < 16; ++i) {
-        Y[i] = 0.f;
-        dY[i][0] = dY[i][1] = dY[i][2] = 0.f;
-    }
+    float gx = 0.f, gy = 0.f, gz = 0.f;
     Y[0] = c0;
-    if (deg > 0) {
-        Y[1] = -c1 * y; dY[1][1] = -c1;
-        Y[2] = c1 * z;  dY[2][2] = c1;
-        Y[3] = -c1 * x; dY[3][0] = -c1;
+    if constexpr (DEG > 0) {
+        Y[1] = -c1 * y; gy -= c1 * a[1];
+        Y[2] = c1 * z;  gz += c1 * a[2];
+        Y[3] = -c1 * x; gx -= c1 * a[3];
     }
-    if (deg > 1) {
+    if constexpr (DEG > 1) {
         const float xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = k4 * x * y;   dY[4][0] = k4 * y; dY[4][1] = k4 * x;
-        Y[5] = -k4 * y * z;  dY[5][1] = -k4 * z; dY[5][2] = -k4 * y;
-        Y[6] = k6 * (2.f * zz - xx - yy); dY[6][0] = -2.f * k6 * x; dY[6][1] = -2.f * k6 * y; dY[6][2] = 4.f * k6 * z;
-        Y[7] = -k4 * x * z;  dY[7][0] = -k4 * z; dY[7][2] = -k4 * x;
-        Y[8] = k8 * (xx - yy); dY[8][0] = 2.f * k8 * x; dY[8][1] = -2.f * k8 * y;
-        if (deg > 2) {
+        Y[4] = k4 * x * y;   gx += a[4] * k4 * y; gy += a[4] * k4 * x;
+        Y[5] = -k4 * y * z;  gy -= a[5] * k4 * z; gz -= a[5] * k4 * y;
+        Y[6] = k6 * (2.f * zz - xx - yy);
+        gx -= a[6] * 2.f * k6 * x; gy -= a[6] * 2.f * k6 * y; gz += a[6] * 4.f * k6 * z;
+        Y[7] = -k4 * x * z;  gx -= a[7] * k4 * z; gz -= a[7] * k4 * x;
+        Y[8] = k8 * (xx - yy); gx += a[8] * 2.f * k8 * x; gy -= a[8] * 2.f * k8 * y;
+        if constexpr (DEG > 2) {
             Y[9] = k9 * y * (3.f * xx - yy);
-            dY[9][0] = 6.f * k9 * x * y; dY[9][1] = k9 * (3.f * xx - 3.f * yy);
+            gx += a[9] * 6.f * k9 * x * y; gy += a[9] * k9 * (3.f * xx - 3.f * yy);
             Y[10] = k10 * x * y * z;
-            dY[10][0] = k10 * y * z; dY[10][1] = k10 * x * z; dY[10][2] = k10 * x * y;
+            gx += a[10] * k10 * y * z; gy += a[10] * k10 * x * z; gz += a[10] * k10 * x * y;
             Y[11] = k11 * y * (4.f * zz - xx - yy);
-            dY[11][0] = -2.f * k11 * x * y; dY[11][1] = k11 * (4.f * zz - xx - 3.f * yy); dY[11][2] = 8.f * k11 * y * z;
+            gx -= a[11] * 2.f * k11 * x * y; gy += a[11] * k11 * (4.f * zz - xx - 3.f * yy);
+            gz += a[11] * 8.f * k11 * y * z;
             Y[12] = k12 * z * (2.f * zz - 3.f * xx - 3.f * yy);
-            dY[12][0] = -6.f * k12 * x * z; dY[12][1] = -6.f * k12 * y * z;
-            dY[12][2] = k12 * (6.f * zz - 3.f * xx - 3.f * yy);
+            gx -= a[12] * 6.f * k12 * x * z; gy -= a[12] * 6.f * k12 * y * z;
+            gz += a[12] * k12 * (6.f * zz - 3.f * xx - 3.f * yy);
             Y[13] = k13 * x * (4.f * zz - xx - yy);
-            dY[13][0] = k13 * (4.f * zz - 3.f * xx - yy); dY[13][1] = -2.f * k13 * x * y; dY[13][2] = 8.f * k13 * x * z;
+            gx += a[13] * k13 * (4.f * zz - 3.f * xx - yy); gy -= a[13] * 2.f * k13 * x * y;
+            gz += a[13] * 8.f * k13 * x * z;
             Y[14] = k14 * z * (xx - yy);
-            dY[14][0] = 2.f * k14 * x * z; dY[14][1] = -2.f * k14 * y * z; dY[14][2] = k14 * (xx - yy);
+            gx += a[14] * 2.f * k14 * x * z; gy -= a[14] * 2.f * k14 * y * z; gz += a[14] * k14 * (xx - yy);
             Y[15] = k15 * x * (xx - 3.f * yy);
-            dY[15][0] = k15 * (3.f * xx - 3.f * yy); dY[15][1] = -6.f * k15 * x * y;
+            gx += a[15] * k15 * (3.f * xx - 3.f * yy); gy -= a[15] * 6.f * k15 * x * y;
         }
     }
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = gz;
 }
 
 struct ProjArgs {
@@ -389,8 +393,11 @@ struct ProjArgs {
     int V;
 };
 
+// DEG: SH degree (-1: no SH coefficients)
+template <int DEG>
 __global__ void __launch_bounds__(128) k_project_bwd(ProjArgs a, CamPack cams, tg_params prm)
 {
+    constexpr int NB = DEG >= 0 ? (DEG + 1) * (DEG + 1) : 1;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.N) return;
     const float m0 = a.means[3 * g], m1 = a.means[3 * g + 1], m2 = a.means[3 * g + 2];
@@ -400,7 +407,6 @@ __global__ void __launch_bounds__(128) k_project_bwd(ProjArgs a, CamPack cams, t
         for (int i = 0; i < 3; ++i) s[i] = expf(s[i]);
     float o = a.opacity[g];
     if (a.opacity_mode == 1) o = 1.0f / (1.0f + expf(-o));
-    const int nsh = (a.sh_deg + 1) * (a.sh_deg + 1);
     // rotation of the normalised quaternion and Sigma_3D = M M^T, M = R S
     const float qn = sqrtf(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
     const float w = qw0 / qn, x = qx0 / qn, y = qy0 / qn, z = qz0 / qn;
@@ -416,8 +422,13 @@ __global__ void __launch_bounds__(128) k_project_bwd(ProjArgs a, CamPack cams, t
     float gS3[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float gmu[3] = {0.f, 0.f, 0.f};
     float go = 0.f;
-    float gsh[48];
-    for (int i = 0; i < 48; ++i) gsh[i] = 0.f;
+    // the coefficients (read once) and their gradient, in registers
+    float shc[3 * NB], gsh[3 * NB];
+#pragma unroll
+    for (int i = 0; i < 3 * NB; ++i) {
+        shc[i] = DEG >= 0 ? a.sh[g * 3 * NB + i] : 0.f;
+        gsh[i] = 0.f;
+    }
     for (int v = 0; v < a.V; ++v) {
         const int64_t o_ = (int64_t)v * a.N + g;
         const ushort4 rc = a.rect[o_];
@@ -496,28 +507,26 @@ __global__ void __launch_bounds__(128) k_project_bwd(ProjArgs a, CamPack cams, t
         for (int j = 0; j < 3; ++j) gmu[j] += Rc[j] * gp[0] + Rc[3 + j] * gp[1] + Rc[6 + j] * gp[2];
         go += gop;
         // --- colour: c = max(0, SH(dir) . coeffs + 0.5), dir = (mu - centre)/|mu - centre|
-        if (a.sh) {
+        if constexpr (DEG >= 0) {
             const float ccx = -(Rc[0] * c.t[0] + Rc[3] * c.t[1] + Rc[6] * c.t[2]);
             const float ccy = -(Rc[1] * c.t[0] + Rc[4] * c.t[1] + Rc[7] * c.t[2]);
             const float ccz = -(Rc[2] * c.t[0] + Rc[5] * c.t[1] + Rc[8] * c.t[2]);
             const float ex = m0 - ccx, ey = m1 - ccy, ez = m2 - ccz;
             const float il = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
             const float dx = ex * il, dy = ey * il, dz = ez * il;
-            float Y[16], dY[16][3];
-            sh_basis_and_grad(a.sh_deg, dx, dy, dz, Y, dY);
-            const float* shg = a.sh + g * 3 * nsh;
-            float gdir[3] = {0.f, 0.f, 0.f};
-            for (int ch = 0; ch < 3; ++ch) {
-                if (a.clamped && a.clamped[3 * o_ + ch]) continue;
-                const float gc = gcol[ch];
-                for (int k = 0; k < nsh; ++k) {
-                    gsh[k * 3 + ch] += gc * Y[k];
-                    const float co = shg[k * 3 + ch];
-                    gdir[0] += gc * co * dY[k][0];
-                    gdir[1] += gc * co * dY[k][1];
-                    gdir[2] += gc * co * dY[k][2];
-                }
-            }
+            // clamped channels (colour = 0) pass no gradient
+            float gc[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) gc[ch] = (a.clamped && a.clamped[3 * o_ + ch]) ? 0.f : gcol[ch];
+            float av[NB], Y[NB], gdir[3];
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+                av[k] = gc[0] * shc[k * 3] + gc[1] * shc[k * 3 + 1] + gc[2] * shc[k * 3 + 2];
+            sh_basis_dir_grad<DEG>(dx, dy, dz, Y, av, gdir);
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) gsh[k * 3 + ch] += gc[ch] * Y[k];
             // project out the radial part: d dir / d e = (I - d d^T) / |e|
             const float dd = gdir[0] * dx + gdir[1] * dy + gdir[2] * dz;
             gmu[0] += (gdir[0] - dd * dx) * il;
@@ -553,19 +562,22 @@ __global__ void __launch_bounds__(128) k_project_bwd(ProjArgs a, CamPack cams, t
     a.g_means[3 * g + 1] = gmu[1];
     a.g_means[3 * g + 2] = gmu[2];
     a.g_opacity[g] = a.opacity_mode == 1 ? go * o * (1.f - o) : go;
-    if (a.g_sh)
-        for (int i = 0; i < 3 * nsh; ++i) a.g_sh[g * 3 * nsh + i] = gsh[i];
+    if constexpr (DEG >= 0) {
+#pragma unroll
+        for (int i = 0; i < 3 * NB; ++i) a.g_sh[g * 3 * NB + i] = gsh[i];
+    }
 }
 
 // ------------------------------------------------------------ elementwise
-__global__ void k_l1(const float* __restrict__ img, const float* __restrict__ tgt, int64_t n, float scale,
-                     float* __restrict__ grad, float* __restrict__ loss) {
+__global__ void __launch_bounds__(256) k_l1(const float* __restrict__ img, const float* __restrict__ tgt, int64_t n,
+                                            float scale, float* __restrict__ grad, float* __restrict__ loss) {
     __shared__ float red[4];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // grid-stride: a bounded grid keeps the loss reduction to one atomic per
+    // block (a few thousand) instead of one per 256 elements
     float l = 0.f;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float d = img[i] - tgt[i];
-        l = fabsf(d);
+        l += fabsf(d);
         grad[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
     }
     // wave sums then one atomic per block
@@ -687,8 +699,14 @@ extern "C" tg_status tg_project_bwd(const tg_gaussians* g, const tg_splats* s, i
     a.V = V;
     CamPack cp;
     for (int v = 0; v < V; ++v) cp.cam[v] = cams[v];
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)((N + 127) / 128)), dim3(128), 0, (hipStream_t)stream, a, cp,
-                       *p);
+    const dim3 grid((unsigned)((N + 127) / 128));
+    switch (a.sh ? a.sh_deg : -1) {
+        case 0: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project_bwd<0>), grid, dim3(128), 0, (hipStream_t)stream, a, cp, *p); break;
+        case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project_bwd<1>), grid, dim3(128), 0, (hipStream_t)stream, a, cp, *p); break;
+        case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project_bwd<2>), grid, dim3(128), 0, (hipStream_t)stream, a, cp, *p); break;
+        case 3: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project_bwd<3>), grid, dim3(128), 0, (hipStream_t)stream, a, cp, *p); break;
+        default: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project_bwd<-1>), grid, dim3(128), 0, (hipStream_t)stream, a, cp, *p); break;
+    }
     TG_CHECK_LAUNCH();
     return TG_OK;
 }
@@ -698,8 +716,9 @@ extern "C" tg_status tg_l1_loss_grad(const float* image, const float* target, in
 {
     if (!image || !target || !grad || n < 0) return TG_ERR_INVALID_ARG;
     if (n == 0) return TG_OK;
-    hipLaunchKernelGGL(k_l1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, image, target, n,
-                       scale, grad, loss_sum);
+    const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_l1, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, image, target, n, scale, grad,
+                       loss_sum);
     TG_CHECK_LAUNCH();
     return TG_OK;
 }
