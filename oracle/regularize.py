@@ -1,0 +1,130 @@
+"""Motion regularisation (Sec. 4.5) -- TEST INFRASTRUCTURE ONLY.
+
+Plain numpy/scipy, FP64.  Steps in the paper's order:
+
+  static_mask()   Sec. 4.5.2: a Gaussian is static when, in at least 2
+                  views, it is hit by more than 9 pixels of which more than
+                  90% are static (|x' - x| < 1 px; counted by the
+                  accumulation, slots S_N and S_STATN).  Static Gaussians
+                  keep their first-frame parameters and take no further part.
+  deltas()        Sec. 4.5.1: the change of a Gaussian against the first
+                  frame: d_mu = mu' - mu, d_S = s' - s (linear scales) and
+                  the rotation change Q = R' R^T in Euler-angle form
+                  (Q = Rz(psi) Ry(theta) Rx(phi), angles (phi, theta, psi)).
+  knn()           the K = 8 nearest solved Gaussians (Sec. 5.2), by the
+                  Euclidean distance between first-frame means; a solved
+                  Gaussian's own entry is among them (distance 0).
+  regularize()    median filter (Sec. 4.5.1): a solved Gaussian takes the
+                  component-wise median of its neighbours' changes;
+                  propagation (Sec. 4.5.2): a Gaussian that is neither
+                  solved nor static takes the component-wise mean of its
+                  neighbours' filtered changes; the change is added to the
+                  first-frame parameters (rotation: R_new = Q(angles) R).
+
+"Solved" means position and covariance both updated by the multi-view step
+(status bits 1 and 2); Gaussians with only a position (negative eigenvalue
+or singular covariance system) are propagation targets, as the paper names
+negative eigenvalues among the unreliable cases.  A scale component that
+would become non-positive keeps its first-frame value.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+from . import S_N, S_STATN, ST_COV, ST_POS, quat_to_rot, rot_to_quat
+
+K = 8                 # neighbours (Sec. 5.2)
+STATIC_MIN_PIX = 9    # "hit by more than 9 pixels" (Sec. 4.5.2)
+STATIC_FRAC = 0.9     # "more than 90% of its pixels fixed"
+STATIC_VIEWS = 2      # "in at least 2 views"
+
+RG_STATIC, RG_FILTERED, RG_PROPAGATED = 1, 2, 4
+
+
+def static_mask(acc):
+    """acc [V,N,16] accumulator records -> bool [N]."""
+    n = acc[..., S_N].astype(np.float64)
+    sn = acc[..., S_STATN].astype(np.float64)
+    per_view = (n > STATIC_MIN_PIX) & (sn > STATIC_FRAC * n)
+    return per_view.sum(0) >= STATIC_VIEWS
+
+
+def euler_zyx(Q):
+    """Q = Rz(psi) Ry(theta) Rx(phi) -> (phi, theta, psi)."""
+    theta = np.arcsin(np.clip(-Q[..., 2, 0], -1.0, 1.0))
+    phi = np.arctan2(Q[..., 2, 1], Q[..., 2, 2])
+    psi = np.arctan2(Q[..., 1, 0], Q[..., 0, 0])
+    return np.stack([phi, theta, psi], -1)
+
+
+def rot_zyx(e):
+    """(phi, theta, psi) -> Rz(psi) Ry(theta) Rx(phi)."""
+    phi, theta, psi = np.moveaxis(np.asarray(e, np.float64), -1, 0)
+    cx, sx, cy, sy, cz, sz = np.cos(phi), np.sin(phi), np.cos(theta), np.sin(theta), np.cos(psi), np.sin(psi)
+    Rx = np.stack([np.stack([np.ones_like(cx), 0 * cx, 0 * cx], -1), np.stack([0 * cx, cx, -sx], -1),
+                   np.stack([0 * cx, sx, cx], -1)], -2)
+    Ry = np.stack([np.stack([cy, 0 * cy, sy], -1), np.stack([0 * cy, np.ones_like(cy), 0 * cy], -1),
+                   np.stack([-sy, 0 * cy, cy], -1)], -2)
+    Rz = np.stack([np.stack([cz, -sz, 0 * cz], -1), np.stack([sz, cz, 0 * cz], -1),
+                   np.stack([0 * cz, 0 * cz, np.ones_like(cz)], -1)], -2)
+    return Rz @ Ry @ Rx
+
+
+def deltas(means0, quats0, scales0, means1, quats1, scales1):
+    """[N,9]: d_mu (3), Euler angles of R' R^T (3), d_S (3)."""
+    R0 = quat_to_rot(quats0)
+    R1 = quat_to_rot(quats1)
+    d = np.zeros((means0.shape[0], 9))
+    d[:, 0:3] = np.asarray(means1, np.float64) - np.asarray(means0, np.float64)
+    d[:, 3:6] = euler_zyx(R1 @ np.swapaxes(R0, -1, -2))
+    d[:, 6:9] = np.asarray(scales1, np.float64) - np.asarray(scales0, np.float64)
+    return d
+
+
+def knn(points, sources, queries, k=K):
+    """Indices (into `sources`) of the min(k, |sources|) nearest sources of
+    each query point, nearest first, and their distances."""
+    pts = np.asarray(points, np.float64)
+    kk = min(k, len(sources))
+    tree = cKDTree(pts[sources])
+    dist, idx = tree.query(pts[queries], k=kk)
+    if kk == 1:
+        dist, idx = dist[:, None], idx[:, None]
+    return idx, dist
+
+
+def regularize(means0, quats0, scales0, means1, quats1, scales1, status, acc, k=K):
+    """Returns (means, quats, scales, reg_status) after Sec. 4.5."""
+    N = means0.shape[0]
+    status = np.asarray(status, np.uint32)
+    static = static_mask(acc)
+    solved = ((status & ST_POS) > 0) & ((status & ST_COV) > 0) & ~static
+    d = deltas(means0, quats0, scales0, means1, quats1, scales1)
+    out_d = np.zeros((N, 9))
+    reg = np.where(static, RG_STATIC, 0).astype(np.uint32)
+    src = np.nonzero(solved)[0]
+    if src.size:
+        # median filter of the solved Gaussians
+        idx, _ = knn(means0, src, src, k)
+        filt = np.median(d[src][idx], axis=1)                 # [n_src, 9]
+        out_d[src] = filt
+        reg[src] |= RG_FILTERED
+        # propagation of the filtered changes to the rest (not static)
+        tgt = np.nonzero(~solved & ~static)[0]
+        if tgt.size:
+            fd = np.zeros((N, 9))
+            fd[src] = filt
+            idx, _ = knn(means0, src, tgt, k)
+            out_d[tgt] = fd[src][idx].mean(axis=1)
+            reg[tgt] |= RG_PROPAGATED
+    moved = (reg & (RG_FILTERED | RG_PROPAGATED)) > 0
+    means = np.asarray(means0, np.float64).copy()
+    quats = np.asarray(quats0, np.float64).copy()
+    scales = np.asarray(scales0, np.float64).copy()
+    means[moved] += out_d[moved, 0:3]
+    R = rot_zyx(out_d[moved, 3:6]) @ quat_to_rot(quats0[moved])
+    quats[moved] = rot_to_quat(R)
+    s_new = scales[moved] + out_d[moved, 6:9]
+    scales[moved] = np.where(s_new > 0, s_new, scales[moved])
+    return means, quats, scales, reg

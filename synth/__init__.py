@@ -560,3 +560,64 @@ def make_clip(name="small", frames=3, *, seed=None, n=None, views=None, width=No
         vis.append(v)
     return Clip(name=name, scene=wl.scene, cams=wl.cams, disp=np.stack(disp), vis=np.stack(vis),
                 meta=dict(wl.meta, frames=frames))
+
+
+# --------------------------------------------------------------------------
+# regularisation inputs: first-frame Gaussians, a multi-view update of them
+# (a smooth rigid motion plus noise and salt-and-pepper outliers), the
+# update's status bits and per-view pixel counts
+# --------------------------------------------------------------------------
+@dataclass
+class RegCase:
+    scene: Scene              # first frame
+    means1: np.ndarray        # updated means [N,3]
+    quats1: np.ndarray        # updated quaternions [N,4]
+    scales1: np.ndarray       # updated scales [N,3]
+    status: np.ndarray        # uint32 [N] (1 position, 2 covariance, other bits: reasons)
+    acc: np.ndarray           # [V,N,16] float32, slots 12 (pixels) and 13 (static pixels) set
+    truth: dict               # ground-truth motion: means, quats, scales
+
+
+def make_reg_case(n=3000, views=4, *, seed=0, angle_deg=10.0, trans=0.1, noise=0.002, outlier_frac=0.05,
+                  unsolved_frac=0.1, posonly_frac=0.05, static_frac=0.1, uniform=False) -> RegCase:
+    rng = np.random.default_rng(seed)
+    sc = random_gaussians(rng, n, domain="ball", radius=2.0)
+    axis = rng.standard_normal(3)
+    axis /= np.linalg.norm(axis)
+    qR = _axis_angle_quat(axis, math.radians(angle_deg))
+    R = _quat_to_mat(qR)
+    t = rng.standard_normal(3)
+    t *= trans / np.linalg.norm(t)
+    c = rng.uniform(-1.0, 1.0, 3)
+    mu0 = sc.means.astype(np.float64)
+    if uniform:
+        # the same change for every Gaussian: translation plus a rotation of
+        # each Gaussian about its own centre
+        mu_t = mu0 + t
+    else:
+        mu_t = (mu0 - c) @ R.T + c + t
+    q_t = np.stack([_quat_mul(qR, q) for q in sc.quats.astype(np.float64)])
+    q_t[q_t[:, 0] < 0] *= -1.0
+    s_t = sc.scales.astype(np.float64)
+    truth = dict(means=mu_t, quats=q_t, scales=s_t)
+    mu1 = mu_t + (0.0 if uniform else noise) * rng.standard_normal(mu_t.shape)
+    q1 = q_t.copy()
+    s1 = s_t * (1.0 + (0.0 if uniform else 0.01) * rng.standard_normal(s_t.shape))
+    out = rng.random(n) < (0.0 if uniform else outlier_frac)
+    mu1[out] += rng.normal(0.0, 0.5, (out.sum(), 3))
+    q1[out] = _unit_quats(rng, out.sum())
+    s1[out] *= rng.uniform(0.3, 3.0, (out.sum(), 3))
+    status = np.full(n, 3, np.uint32)
+    u = rng.random(n)
+    status[u < unsolved_frac] = 4                                   # too few views
+    status[(u >= unsolved_frac) & (u < unsolved_frac + posonly_frac)] = 1 | 32   # position only
+    acc = np.zeros((views, n, 16), np.float32)
+    acc[:, :, 12] = rng.integers(0, 40, (views, n))
+    acc[:, :, 13] = np.floor(acc[:, :, 12] * rng.uniform(0.0, 0.5, (views, n)))
+    st = rng.random(n) < static_frac
+    for i in np.nonzero(st)[0]:
+        vs = rng.choice(views, 2, replace=False)
+        acc[vs, i, 12] = rng.integers(10, 40, 2)
+        acc[vs, i, 13] = acc[vs, i, 12]
+    return RegCase(scene=sc, means1=mu1.astype(np.float32), quats1=q1.astype(np.float32),
+                   scales1=s1.astype(np.float32), status=status, acc=acc, truth=truth)
