@@ -353,6 +353,27 @@ def main():
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
     st = mt.status.cpu().numpy().view(np.uint32)
 
+    # motion regularisation of the frame's result (Sec. 4.5), timed alone
+    reg_ms = None
+    if not args.no_warm:
+        g_reg = api.GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.quats),
+                                    torch.empty_like(g.scales), g.opacity)
+        reg_st = torch.empty(N, dtype=torch.int32, device=dev)
+        reg_ws = torch.empty(api.regularize_ws_bytes(N), dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            api.regularize(g, g_out, mt.status, mt.acc, mt.params, g_reg, reg_st, ws=reg_ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            api.regularize(g, g_out, mt.status, mt.acc, mt.params, g_reg, reg_st, ws=reg_ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reg_ms = e0.elapsed_time(e1) / args.steps
+        rs = reg_st.cpu().numpy()
+        log(f"regularisation {reg_ms:.3f} ms: filtered {int(((rs & 2) > 0).sum())}, "
+            f"propagated {int(((rs & 4) > 0).sum())}, static {int((rs == 1).sum())}")
+        del reg_ws
+
     warm = None
     if not args.no_warm:
         for _ in range(args.warmup):
@@ -398,6 +419,8 @@ def main():
     }
     if warm is not None:
         out["warm_ms_per_frame"] = warm
+    if reg_ms is not None:
+        out["regularisation_ms"] = reg_ms
     if not args.no_serving:
         log("serving form")
         del disp, vis, mt

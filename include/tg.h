@@ -50,6 +50,7 @@ extern "C" {
 #define TG_REC_STRIDE 8     /* floats per splat record                        */
 #define TG_MAX_SLOTS 8      /* Gaussian sets per batched accumulate launch    */
 #define TG_MAX_FRAMES 4     /* frames sharing one alpha/T evaluation          */
+#define TG_REG_K_MAX 8      /* neighbours of the regularisation               */
 
 typedef enum tg_status {
     TG_OK = 0,
@@ -99,6 +100,12 @@ typedef struct tg_params {
     int32_t views_min;
     int32_t pix_total_min;
     int32_t coarse_shift;   /* log2 of tiles per coarse-bin side (default 3)  */
+    /* motion regularisation (Sec. 4.5, Sec. 5.2) */
+    int32_t reg_k;          /* neighbours, 1..TG_REG_K_MAX (default 8)        */
+    int32_t static_min_pix; /* static in a view: more than this many pixels  */
+    double static_frac;     /* ... of which more than this fraction static   */
+    int32_t static_views;   /* static Gaussian: static in at least this many views */
+    int32_t reserved;
 } tg_params;
 
 /* 3D Gaussians (Sec. 3.1): mean, rotation, scale, opacity, optional SH
@@ -310,6 +317,33 @@ tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_new, const ui
                          const float* acc, const tg_splats* s, const tg_gaussians* g_in,
                          int64_t N, const tg_camera* cams, int32_t V, const tg_params* p,
                          tg_gaussians* g_out, uint32_t* status, void* stream);
+
+/*
+ * tg_regularize -- motion regularisation after the multi-view update
+ * (Sec. 4.5; K = 8 neighbours, Sec. 5.2).
+ *
+ * A Gaussian is static when, in at least p->static_views views, it is hit by
+ * more than p->static_min_pix pixels of which more than p->static_frac are
+ * static (acc slots 12 and 13 of tg_splat_accumulate); static Gaussians keep
+ * g_ref.  Solved Gaussians (status bits 1 and 2, not static) take the
+ * component-wise median, over their p->reg_k nearest solved Gaussians
+ * (themselves included; distances between g_ref means, FP64, ties by index),
+ * of the change against g_ref: d_mu = mu' - mu, d_S = s' - s and the Euler
+ * angles (phi, theta, psi) of R' R^T = Rz(psi) Ry(theta) Rx(phi).  Every
+ * other Gaussian takes the mean of its nearest solved Gaussians' filtered
+ * changes.  The change is added to g_ref (rotation: R = Q R_ref); a scale
+ * component that would not stay positive keeps g_ref's.  With no solved
+ * Gaussian at all, nothing moves.
+ *
+ * g_ref, g_upd, g_out: device, linear scales (scale_mode 0); g_out may alias
+ * either input; only means, quats and scales are written.  status: device
+ * uint32 [N] from tg_triangulate.  acc: device [V,N,16].  reg_status:
+ * device uint32 [N]: 1 static, 2 filtered, 4 propagated, 0 unchanged.
+ * Workspace: query with ws == NULL (about 190 B per Gaussian plus 16 MB).
+ */
+tg_status tg_regularize(const tg_gaussians* g_ref, const tg_gaussians* g_upd, const uint32_t* status,
+                        const float* acc, int64_t N, int32_t V, const tg_params* p, void* ws,
+                        size_t* ws_bytes, tg_gaussians* g_out, uint32_t* reg_status, void* stream);
 
 /*
  * tg_raster_fwd -- forward rasteriser for the refinement (Sec. 4.6), same

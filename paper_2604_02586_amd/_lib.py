@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
                 ("alpha_min", c_f), ("alpha_max", c_f), ("t_min", c_f), ("static_px", c_f),
                 ("det_min", c_d), ("iso_min", c_d), ("wsum_min", c_d), ("wsum_total_min", c_d),
                 ("pix_min", c_i32), ("views_min", c_i32), ("pix_total_min", c_i32),
-                ("coarse_shift", c_i32)]
+                ("coarse_shift", c_i32), ("reg_k", c_i32), ("static_min_pix", c_i32), ("static_frac", c_d),
+                ("static_views", c_i32), ("reserved", c_i32)]
 
 
 class Gaussians(ctypes.Structure):
@@ -88,6 +89,7 @@ def lib():
         "tg_bin_sort": ([P, c_i64, P, c_i32, P, P, P, P, P], st),
         "tg_splat_accumulate": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P, P], st),
         "tg_splat_accumulate_batch": ([P, c_i32, P, P, P], st),
+        "tg_regularize": ([P, P, P, P, c_i64, c_i32, P, P, P, P, P, P], st),
         "tg_solve_views": ([P, P, c_i64, c_i32, P, P, P, P, P], st),
         "tg_triangulate": ([P, P, P, P, P, P, c_i64, P, c_i32, P, P, P, P], st),
         "tg_bin_expand": ([P, P, c_i64, P, c_i32, P, P, P, c_i64, P, P, P, P], st),
@@ -108,7 +110,7 @@ def lib():
 def exported_symbols():
     return [n for n in ("tg_abi_version", "tg_status_string", "tg_default_params", "tg_num_cells",
                         "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_splat_accumulate",
-                        "tg_splat_accumulate_batch", "tg_solve_views", "tg_triangulate", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
+                        "tg_splat_accumulate_batch", "tg_regularize", "tg_solve_views", "tg_triangulate", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
                         "tg_project_bwd", "tg_l1_loss_grad", "tg_adam_step")]
 
 

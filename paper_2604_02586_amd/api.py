@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import check, lib
 
 __all__ = ["GaussianTensors", "SplatTensors", "BinTensors", "MotionTransfer", "preprocess", "bin_sort",
-           "splat_accumulate", "splat_accumulate_batch", "solve_views", "triangulate", "bin_expand", "stream_ptr", "default_params"]
+           "splat_accumulate", "splat_accumulate_batch", "regularize", "solve_views", "triangulate", "bin_expand", "stream_ptr", "default_params"]
 
 default_params = _lib.default_params
 
@@ -189,6 +189,26 @@ def splat_accumulate_batch(slots, params, stats=None, stream=None):
     check("tg_splat_accumulate_batch", lib().tg_splat_accumulate_batch(
         arr, len(slots), ctypes.byref(params), _ptr(stats), stream_ptr(stream)))
     del keep
+
+
+def regularize_ws_bytes(n) -> int:
+    nb = ctypes.c_size_t(0)
+    check("tg_regularize", lib().tg_regularize(None, None, None, None, int(n), 1, ctypes.byref(_lib.default_params()),
+                                               None, ctypes.byref(nb), None, None, None))
+    return int(nb.value)
+
+
+def regularize(g_ref: GaussianTensors, g_upd: GaussianTensors, status, acc, params, g_out: GaussianTensors,
+               reg_status, ws=None, stream=None):
+    """Motion regularisation (tg_regularize); acc [V,N,16]."""
+    n = g_ref.n
+    if ws is None:
+        ws = torch.empty(regularize_ws_bytes(n), dtype=torch.uint8, device=g_ref.means.device)
+    nb = ctypes.c_size_t(ws.numel())
+    gr, gu, go = g_ref.c(), g_upd.c(), g_out.c()
+    check("tg_regularize", lib().tg_regularize(ctypes.byref(gr), ctypes.byref(gu), _ptr(status), _ptr(acc), n,
+                                               int(acc.shape[0]), ctypes.byref(params), _ptr(ws), ctypes.byref(nb),
+                                               ctypes.byref(go), _ptr(reg_status), stream_ptr(stream)))
 
 
 def solve_views(acc, s: SplatTensors, n, V, params, mu_new, cov_new, vflags, stream=None):

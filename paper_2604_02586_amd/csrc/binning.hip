@@ -10,220 +10,10 @@
 // list in depth order and keeps the entries whose tile rectangle contains its
 // tile, which is exactly the per-tile depth-ordered list.
 //
-// The radix sort is LSD with 8-bit digits: per pass a histogram kernel, an
-// exclusive scan of the digit-major histogram, and a scatter kernel whose
-// block-local ranks are stable (wave64 ballot matching, wave prefix in LDS).
+// The radix sort (sort.hip) is LSD with 8-bit digits and stable ranks.
 #include "tg_internal.h"
 
 namespace {
-
-constexpr int SORT_THREADS = 256;
-constexpr int SORT_ITEMS = 16;
-constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // 4096 keys per block
-constexpr int SORT_WAVES = SORT_THREADS / TG_WAVE;      // 4
-constexpr int WAVE_ITEMS = SORT_TILE / SORT_WAVES;      // 1024 keys per wave
-
-// Active length of a segment: fixed, or read from the device (single
-// dynamic segment), 0 when the device count exceeds the capacity.
-__device__ __forceinline__ int64_t seg_count(int64_t seg_len, const int64_t* dev_count) {
-    if (!dev_count) return seg_len;
-    int64_t n = *dev_count;
-    return n > seg_len ? 0 : n;
-}
-
-__global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __restrict__ keys, int64_t seg_len,
-                                                             const int64_t* __restrict__ dev_count, int shift,
-                                                             uint32_t* __restrict__ ghist, int nblk)
-{
-    __shared__ uint32_t h[256];
-    const int seg = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
-    h[t] = 0;
-    __syncthreads();
-    const int64_t n = seg_count(seg_len, dev_count);
-    const int64_t base = (int64_t)b * SORT_TILE;
-    const uint32_t* kp = keys + (int64_t)seg * seg_len;
-    if (base < n) {
-        const int w = t >> 6, l = t & 63;
-#pragma unroll 4
-        for (int r = 0; r < SORT_ITEMS; ++r) {
-            int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
-            if (idx < n) atomicAdd(&h[(kp[idx] >> shift) & 255u], 1u);
-        }
-    }
-    __syncthreads();
-    ghist[((int64_t)seg * 256 + t) * nblk + b] = h[t];
-}
-
-// ---- exclusive scan of a [nseg][L] u32 array (three kernels) ------------
-constexpr int SCAN_THREADS = 1024;
-constexpr int SCAN_ITEMS = 4;
-constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
-
-__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
-    __shared__ uint32_t wsum[SCAN_THREADS / TG_WAVE];
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    uint32_t inc = wave_scan_add_u32(v);
-    if (l == 63) wsum[w] = inc;
-    __syncthreads();
-    if (w == 0) {
-        uint32_t x = l < SCAN_THREADS / TG_WAVE ? wsum[l] : 0u;
-        uint32_t xi = wave_scan_add_u32(x);
-        if (l < SCAN_THREADS / TG_WAVE) wsum[l] = xi - x;
-        if (l == SCAN_THREADS / TG_WAVE - 1) *total = xi;
-    }
-    __syncthreads();
-    uint32_t r = wsum[w] + inc - v;
-    __syncthreads();
-    return r;
-}
-
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t* __restrict__ in, int64_t L,
-                                                              uint32_t* __restrict__ sums, int nchunk)
-{
-    __shared__ uint32_t tot;
-    const int seg = blockIdx.y;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-    uint32_t s = 0;
-    for (int i = 0; i < SCAN_ITEMS; ++i)
-        if (base + i < L) s += in[(int64_t)seg * L + base + i];
-    block_excl_scan(s, &tot);
-    if (threadIdx.x == 0) sums[(int64_t)seg * nchunk + blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_sums(uint32_t* __restrict__ sums, int nchunk)
-{
-    // one block per segment; nchunk may exceed the block size
-    __shared__ uint32_t tot;
-    const int seg = blockIdx.x;
-    uint32_t carry = 0;
-    for (int c0 = 0; c0 < nchunk; c0 += SCAN_THREADS) {
-        int c = c0 + threadIdx.x;
-        uint32_t v = c < nchunk ? sums[(int64_t)seg * nchunk + c] : 0u;
-        uint32_t ex = block_excl_scan(v, &tot);
-        if (c < nchunk) sums[(int64_t)seg * nchunk + c] = ex + carry;
-        carry += tot;
-        __syncthreads();
-    }
-}
-
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(uint32_t* __restrict__ data, int64_t L,
-                                                            const uint32_t* __restrict__ sums, int nchunk)
-{
-    __shared__ uint32_t tot;
-    const int seg = blockIdx.y;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-    uint32_t v[SCAN_ITEMS];
-    uint32_t s = 0;
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        v[i] = base + i < L ? data[(int64_t)seg * L + base + i] : 0u;
-        s += v[i];
-    }
-    uint32_t ex = block_excl_scan(s, &tot) + sums[(int64_t)seg * nchunk + blockIdx.x];
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        if (base + i < L) data[(int64_t)seg * L + base + i] = ex;
-        ex += v[i];
-    }
-}
-
-// ---- stable scatter --------------------------------------------------------
-// Items of a block: wave w owns keys [w*1024, (w+1)*1024) of the block's 4096,
-// visited in 16 rounds of 64 consecutive keys, so order within the block is
-// (wave, round, lane) = input order.  Each key is first placed at its stable
-// rank inside the block (digit-major) in LDS; the block then writes the LDS
-// array out in order, so consecutive threads write consecutive addresses of
-// one digit's run instead of 64 scattered words per instruction.
-__global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t seg_len, const int64_t* __restrict__ dev_count, int shift,
-    const uint32_t* __restrict__ goff, int nblk)
-{
-    __shared__ uint32_t woff[SORT_WAVES][256];
-    __shared__ uint32_t gdelta[256];     // global start of the digit minus its block-local start
-    __shared__ uint32_t wtot[SORT_WAVES];
-    __shared__ uint32_t LK[SORT_TILE];
-    __shared__ uint32_t LV[SORT_TILE];
-    const int seg = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
-    const int w = t >> 6, l = t & 63;
-    const int64_t n = seg_count(seg_len, dev_count);
-    const int64_t base = (int64_t)b * SORT_TILE;
-    if (base >= n) return;  // uniform per block
-    const int nvalid = (int)((n - base) < SORT_TILE ? (n - base) : SORT_TILE);
-    for (int i = t; i < SORT_WAVES * 256; i += SORT_THREADS) (&woff[0][0])[i] = 0;
-    __syncthreads();
-    const int64_t so = (int64_t)seg * seg_len;
-    const bool with_v = vout != nullptr;
-    uint32_t k[SORT_ITEMS], val[SORT_ITEMS];
-#pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
-        if (idx < n) {
-            k[r] = kin[so + idx];
-            val[r] = vin ? vin[so + idx] : (uint32_t)idx;
-            atomicAdd(&woff[w][(k[r] >> shift) & 255u], 1u);
-        } else {
-            k[r] = 0;
-            val[r] = 0;
-        }
-    }
-    __syncthreads();
-    {
-        // thread t owns digit t: block-local start of the digit (exclusive
-        // scan of the digit totals), then each wave's start inside it
-        uint32_t c[SORT_WAVES], tot = 0;
-#pragma unroll
-        for (int ww = 0; ww < SORT_WAVES; ++ww) {
-            c[ww] = woff[ww][t];
-            tot += c[ww];
-        }
-        const uint32_t inc = wave_scan_add_u32(tot);
-        if (l == 63) wtot[w] = inc;
-        __syncthreads();
-        uint32_t start = inc - tot;
-#pragma unroll
-        for (int ww = 0; ww < SORT_WAVES; ++ww)
-            if (ww < w) start += wtot[ww];
-        gdelta[t] = goff[((int64_t)seg * 256 + t) * nblk + b] - start;
-        uint32_t run = start;
-#pragma unroll
-        for (int ww = 0; ww < SORT_WAVES; ++ww) {
-            woff[ww][t] = run;
-            run += c[ww];
-        }
-    }
-    __syncthreads();
-    const uint64_t lt = lanemask_lt();
-#pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
-        bool active = idx < n;
-        uint32_t d = (k[r] >> shift) & 255u;
-        uint64_t m = ballot64(active);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            bool set = (d >> bit) & 1u;
-            uint64_t bb = ballot64(active && set);
-            m &= set ? bb : ~bb;
-        }
-        if (active) {
-            uint32_t rank = (uint32_t)__popcll(m & lt);
-            uint32_t pos = woff[w][d] + rank;       // < nvalid for a consistent histogram
-            if (pos < (uint32_t)nvalid) {
-                LK[pos] = k[r];
-                if (with_v) LV[pos] = val[r];
-            }
-            if (rank == 0) woff[w][d] += (uint32_t)__popcll(m);
-        }
-    }
-    __syncthreads();
-    for (int i = t; i < nvalid; i += SORT_THREADS) {
-        const uint32_t key = LK[i];
-        const uint32_t pos = gdelta[(key >> shift) & 255u] + (uint32_t)i;
-        if (pos < (uint64_t)n) {  // always true for a consistent histogram
-            if (kout) kout[so + pos] = key;
-            if (with_v) vout[so + pos] = LV[i];
-        }
-    }
-}
 
 // ---- coarse-bin key emission ---------------------------------------------
 // Each thread takes EMIT_ITEMS depth ranks (strided by the block size, so the
@@ -326,55 +116,6 @@ __global__ void __launch_bounds__(256) k_cell_finalize(const uint32_t* __restric
     if (i == n - 1 || (skeys[i + 1] >> rbits) != cell) ranges[cell].y = (uint32_t)(i + 1);
 }
 
-// ---- radix sort driver -------------------------------------------------------
-struct SortBufs {
-    uint32_t* hist;   // [nseg][256][nblk]
-    uint32_t* sums;   // [nseg][nchunk]
-};
-
-size_t sort_scratch_bytes(int64_t seg_len, int nseg) {
-    int64_t nblk = (seg_len + SORT_TILE - 1) / SORT_TILE;
-    int64_t L = 256 * nblk;
-    int64_t nchunk = (L + SCAN_TILE - 1) / SCAN_TILE;
-    return (size_t)nseg * (size_t)(L + nchunk + 64) * sizeof(uint32_t);
-}
-
-// Sorts nseg segments of seg_len keys (or one segment of *dev_count keys) by
-// bits [bit0, bit0 + 8*passes).  Buffers: ka/va hold the input; kb/vb are the
-// ping-pong partner.  Final keys/values go to kfinal/vfinal (either may be
-// null when not needed).  vin == null means values are the indices.
-tg_status radix_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va, uint32_t* kb,
-                     uint32_t* vb, uint32_t* kfinal, uint32_t* vfinal, int64_t seg_len, int nseg,
-                     const int64_t* dev_count, int bit0, int passes, void* scratch, hipStream_t s)
-{
-    const int nblk = (int)((seg_len + SORT_TILE - 1) / SORT_TILE);
-    if (nblk == 0) return TG_OK;
-    const int64_t L = 256LL * nblk;
-    const int nchunk = (int)((L + SCAN_TILE - 1) / SCAN_TILE);
-    uint32_t* hist = (uint32_t*)scratch;
-    uint32_t* sums = hist + (int64_t)nseg * L;
-    const uint32_t* ck = kin;
-    const uint32_t* cv = vin;
-    for (int p = 0; p < passes; ++p) {
-        const bool last = p == passes - 1;
-        uint32_t* ok = last ? kfinal : ((p & 1) ? kb : ka);
-        uint32_t* ov = last ? vfinal : ((p & 1) ? vb : va);
-        if (!last && !ok) return TG_ERR_INVALID_ARG;
-        const int shift = bit0 + 8 * p;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, seg_len, dev_count, shift,
-                           hist, nblk);
-        hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
-        hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(SCAN_THREADS), 0, s, sums, nchunk);
-        hipLaunchKernelGGL(k_scan_down, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, cv, ok,
-                           (last && !vfinal) ? nullptr : ov, seg_len, dev_count, shift, hist, nblk);
-        TG_CHECK_LAUNCH();
-        ck = ok;
-        cv = ov;
-    }
-    return TG_OK;
-}
-
 inline int bitlen(uint64_t x) {  // number of bits to represent x-1 values [0, x)
     int b = 0;
     while (b < 63 && (1ull << b) < x) ++b;
@@ -419,8 +160,8 @@ BinWs layout_ws(void* ws, int64_t N, int V, int64_t capacity) {
     size_t vn = (size_t)V * (size_t)N * 4;
     size_t a = take(vn), b = take(vn), c = take(vn), d = take(vn);
     size_t e = take((size_t)capacity * 4), f = take((size_t)capacity * 4);
-    size_t sc = sort_scratch_bytes(N, V);
-    size_t sc2 = sort_scratch_bytes(capacity, 1);
+    size_t sc = tg_sort_scratch_bytes(N, V);
+    size_t sc2 = tg_sort_scratch_bytes(capacity, 1);
     size_t g = take(sc > sc2 ? sc : sc2);
     char* base = (char*)ws;
     L.dk_a = (uint32_t*)(base + a);
@@ -479,7 +220,7 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
     TG_CHECK_LAUNCH();
     if (N == 0) return TG_OK;
     // (1) depth order per view: 4 passes over the 32-bit depth keys
-    st = radix_sort(sp->key, nullptr, L.dk_a, L.dv_a, L.dk_b, L.dv_b, nullptr, bins->order, N, V, nullptr, 0, 4,
+    st = tg_radix_sort(sp->key, nullptr, L.dk_a, L.dv_a, L.dk_b, L.dv_b, nullptr, bins->order, N, V, nullptr, 0, 4,
                     L.scratch, s);
     if (st != TG_OK) return st;
     // (2) emit (coarse bin | depth rank) keys
@@ -500,7 +241,7 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
     final_keys = (bp.passes & 1) ? L.pk_b : L.pk_a;
     other = (bp.passes & 1) ? L.pk_a : L.pk_b;
     (void)other;
-    st = radix_sort(L.pk_a, nullptr, L.pk_b, nullptr, L.pk_a, nullptr, final_keys, nullptr, bins->capacity, 1,
+    st = tg_radix_sort(L.pk_a, nullptr, L.pk_b, nullptr, L.pk_a, nullptr, final_keys, nullptr, bins->capacity, 1,
                     bins->n_pairs, 0, bp.passes, L.scratch, s);
     if (st != TG_OK) return st;
     // (4) ranges and ids
@@ -575,7 +316,7 @@ extern "C" tg_status tg_bin_expand(const tg_splats* sp, const tg_bins* bins, int
     tg_status st = plan_bins(cams, V, N > 0 ? N : 1, p, &bp);
     if (st != TG_OK) return st;
     const int64_t T = bp.gp.tile_off[V];
-    size_t need = align256((size_t)T * 4) * 2 + sort_scratch_bytes(T, 1) + 256;
+    size_t need = align256((size_t)T * 4) * 2 + tg_sort_scratch_bytes(T, 1) + 256;
     if (!ws) {
         *ws_bytes = need;
         return TG_OK;
@@ -590,10 +331,7 @@ extern "C" tg_status tg_bin_expand(const tg_splats* sp, const tg_bins* bins, int
                        (const uint2*)bins->cell_ranges, bins->overflow, N, V, bp.gp, bp.cshift, counts, nullptr,
                        nullptr, (int64_t)0, 0);
     hipMemcpyAsync(starts, counts, (size_t)T * 4, hipMemcpyDeviceToDevice, s);
-    const int nchunk = (int)((T + SCAN_TILE - 1) / SCAN_TILE);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, 1), dim3(SCAN_THREADS), 0, s, starts, T, scr, nchunk);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, s, scr, nchunk);
-    hipLaunchKernelGGL(k_scan_down, dim3(nchunk, 1), dim3(SCAN_THREADS), 0, s, starts, T, scr, nchunk);
+    tg_exclusive_scan_u32(starts, T, scr, s);
     hipLaunchKernelGGL(k_ranges_from_starts, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, starts, counts, T,
                        (uint2*)tile_ranges, capacity, n_out);
     TG_CHECK_LAUNCH();

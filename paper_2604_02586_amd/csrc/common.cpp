@@ -37,4 +37,9 @@ extern "C" void tg_default_params(tg_params* p) {
     p->views_min = 2;
     p->pix_total_min = 3;
     p->coarse_shift = 3;
+    p->reg_k = 8;
+    p->static_min_pix = 9;
+    p->static_frac = 0.9;
+    p->static_views = 2;
+    p->reserved = 0;
 }

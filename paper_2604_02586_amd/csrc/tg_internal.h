@@ -272,3 +272,15 @@ inline int64_t coarse_plan(const tg_camera* cams, int32_t V, int64_t N, const tg
     } while (0)
 
 static inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Stable LSD radix sort (sort.hip).  Sorts nseg segments of seg_len keys (or
+// one segment of *dev_count keys) by bits [bit0, bit0 + 8*passes).  ka/va
+// receive the first pass, kb/vb are the ping-pong partner, kfinal/vfinal the
+// last pass (either may be null when not needed); vin == null means values
+// are the indices.  scratch: tg_sort_scratch_bytes(seg_len, nseg) bytes.
+__attribute__((visibility("hidden"))) size_t tg_sort_scratch_bytes(int64_t seg_len, int nseg);
+__attribute__((visibility("hidden"))) tg_status tg_radix_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va, uint32_t* kb,
+                        uint32_t* vb, uint32_t* kfinal, uint32_t* vfinal, int64_t seg_len, int nseg,
+                        const int64_t* dev_count, int bit0, int passes, void* scratch, hipStream_t s);
+// In-place exclusive scan of L u32 values; scratch: one u32 per 4096 values.
+__attribute__((visibility("hidden"))) void tg_exclusive_scan_u32(uint32_t* data, int64_t L, uint32_t* scratch, hipStream_t s);

@@ -122,6 +122,31 @@ def test_batch_accumulate_validation(L):
     assert L.tg_splat_accumulate_batch(two, 2, ctypes.byref(p), None, None) == 7
 
 
+def test_regularize_validation(L):
+    from paper_2604_02586_amd import _lib
+    p = _lib.default_params()
+    assert p.reg_k == 8 and p.static_min_pix == 9 and p.static_frac == 0.9 and p.static_views == 2
+    nb = ctypes.c_size_t(0)
+    # workspace query needs no buffers
+    assert L.tg_regularize(None, None, None, None, 1000, 2, ctypes.byref(p), None, ctypes.byref(nb), None, None,
+                           None) == 0
+    assert nb.value > 1000 * 150
+    fake = ctypes.c_void_p(0x10000)
+    g = _lib.Gaussians(fake, fake, fake, fake, None, 0, 0, 0, 0)
+    small = ctypes.c_size_t(16)
+    assert L.tg_regularize(ctypes.byref(g), ctypes.byref(g), fake, fake, 1000, 2, ctypes.byref(p), fake,
+                           ctypes.byref(small), ctypes.byref(g), fake, None) == 3
+    big = ctypes.c_size_t(nb.value)
+    assert L.tg_regularize(None, ctypes.byref(g), fake, fake, 1000, 2, ctypes.byref(p), fake, ctypes.byref(big),
+                           ctypes.byref(g), fake, None) == 1
+    glog = _lib.Gaussians(fake, fake, fake, fake, None, 0, 1, 0, 0)
+    assert L.tg_regularize(ctypes.byref(glog), ctypes.byref(g), fake, fake, 1000, 2, ctypes.byref(p), fake,
+                           ctypes.byref(big), ctypes.byref(g), fake, None) == 7
+    p.reg_k = 9
+    assert L.tg_regularize(ctypes.byref(g), ctypes.byref(g), fake, fake, 1000, 2, ctypes.byref(p), fake,
+                           ctypes.byref(big), ctypes.byref(g), fake, None) == 1
+
+
 def test_workspace_query_and_cell_counts(L):
     from paper_2604_02586_amd import _lib
     p = _lib.default_params()
