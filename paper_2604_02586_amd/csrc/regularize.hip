@@ -6,15 +6,20 @@
 //                   and not static; the change against the first frame
 //                   (d_mu, Euler angles of R' R^T, d_S) of every solved
 //                   Gaussian; bounding box and count of the solved set.
-//   k_reg_grid      one thread: a uniform grid over the solved set (about two
-//                   solved Gaussians per cell, at most 2^21 cells).
+//   k_reg_grid      one thread: a cubic grid of 2^B cells per axis over the
+//                   solved set (about two solved Gaussians per finest cell,
+//                   B <= 7), seen at levels L = 0..B (cells of 2^L finest
+//                   cells per axis).
 //   k_reg_keys + radix sort + k_reg_cells
-//                   solved Gaussians sorted by grid cell; per-cell ranges and
-//                   the sorted positions as float4 (coalesced reads).
-//   k_reg_knn       per non-static Gaussian: exact K nearest solved
-//                   Gaussians by expanding shells of cells, FP64 distances,
-//                   ties by index; stops once no unvisited cell can hold a
-//                   closer one.
+//                   solved Gaussians sorted by the Morton code of their finest
+//                   cell, so every cell of every level is one contiguous run;
+//                   per-level cell ranges and the sorted positions as float4.
+//   k_reg_knn       per non-static Gaussian: exact K nearest solved Gaussians
+//                   by a best-first descent of the implicit octree formed by
+//                   the levels (FP64 distances, ties by index, boxes farther
+//                   than the current K-th neighbour pruned), so queries far
+//                   from every solved Gaussian (the occluded interior of a
+//                   scene, say) cost about as much as queries among them.
 //   k_reg_filter    per solved Gaussian: component-wise median of its
 //                   neighbours' changes (itself included).
 //   k_reg_apply     per Gaussian: static -> first frame; solved -> first
@@ -25,21 +30,36 @@
 namespace {
 
 constexpr int KMAX = TG_REG_K_MAX;
-constexpr int CELL_BITS = 21;
-constexpr uint32_t CELL_MAX = 1u << CELL_BITS;
-constexpr uint32_t KEY_NONE = CELL_MAX;   // non-solved: sorts after every cell
+constexpr int BMAX = 7;                   // finest grid: up to 128^3 cells
+constexpr uint32_t KEY_NONE = 1u << (3 * BMAX);   // non-solved: sorts after every cell
 constexpr int SORT_PASSES = 3;            // 22 key bits
+// cell ranges of all levels for B = BMAX: sum of 8^(BMAX - L), L = 0..BMAX
+constexpr uint64_t RANGES_MAX = ((1ull << (3 * (BMAX + 1))) - 1) / 7;
 
 enum : uint8_t { CLS_STATIC = 0, CLS_SOURCE = 1, CLS_TARGET = 2 };
 
 struct GridInfo {
     float lo[3];
     float inv_h;
-    double h;
-    int32_t dim[3];
+    double h;                 // finest cell size
+    int32_t B;                // 2^B finest cells per axis
     uint32_t n_src;
-    int32_t box[6];   // order-preserving integer images of min xyz, max xyz
+    int32_t box[6];           // order-preserving integer images of min xyz, max xyz
+    uint32_t lvl_off[BMAX + 2];   // first range entry of each level
 };
+
+// 10-bit coordinate -> every third bit (Morton interleave)
+__device__ __forceinline__ uint32_t part1by2(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x30000ffu;
+    x = (x | (x << 8)) & 0x300f00fu;
+    x = (x | (x << 4)) & 0x30c30c3u;
+    x = (x | (x << 2)) & 0x9249249u;
+    return x;
+}
+__device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
+}
 
 __device__ __forceinline__ int32_t f2o(float f) {
     const int32_t i = __builtin_bit_cast(int32_t, f);
@@ -118,7 +138,7 @@ struct RegArgs {
     uint32_t* keys;    // [N]
     const uint32_t* skeys;   // [N] sorted
     const uint32_t* svals;   // [N] Gaussian index of each sorted key
-    uint2* ranges;     // [CELL_MAX]
+    uint2* ranges;     // [RANGES_MAX] cell ranges of every level
     float4* spos;      // [N] sorted positions, index bits in w
     GridInfo* grid;
 };
@@ -189,39 +209,25 @@ __global__ void __launch_bounds__(256) k_reg_classify(RegArgs a) {
 }
 
 __global__ void k_reg_grid(GridInfo* gi) {
-    if (gi->n_src == 0) {
-        for (int i = 0; i < 3; ++i) {
-            gi->lo[i] = 0.f;
-            gi->dim[i] = 1;
-        }
-        gi->h = 1.0;
-        gi->inv_h = 1.0f;
-        return;
-    }
-    double lo[3], ext[3];
+    double lo[3], ext = 1e-6;
     for (int i = 0; i < 3; ++i) {
-        lo[i] = o2f(gi->box[i]);
-        ext[i] = fmax((double)o2f(gi->box[3 + i]) - lo[i], 1e-6);
+        lo[i] = gi->n_src ? (double)o2f(gi->box[i]) : 0.0;
+        if (gi->n_src) ext = fmax(ext, (double)o2f(gi->box[3 + i]) - lo[i]);
     }
-    const double vol = ext[0] * ext[1] * ext[2];
-    double h = cbrt(vol / fmax(1.0, 0.5 * gi->n_src));
-    h = fmax(h, fmax(ext[0], fmax(ext[1], ext[2])) / 1024.0);
-    int64_t d[3];
-    for (;;) {
-        int64_t prod = 1;
-        for (int i = 0; i < 3; ++i) {
-            d[i] = (int64_t)(ext[i] / h) + 1;
-            prod *= d[i];
-        }
-        if (prod <= (int64_t)CELL_MAX) break;
-        h *= 1.25;
-    }
-    for (int i = 0; i < 3; ++i) {
-        gi->lo[i] = (float)lo[i];
-        gi->dim[i] = (int32_t)d[i];
-    }
+    // about two solved Gaussians per finest cell
+    int B = 0;
+    while (B < BMAX && (double)(1ull << (3 * B)) * 2.0 < (double)gi->n_src) ++B;
+    const double h = ext / (double)(1 << B) * (1.0 + 1e-6);
+    for (int i = 0; i < 3; ++i) gi->lo[i] = (float)lo[i];
     gi->h = h;
     gi->inv_h = (float)(1.0 / h);
+    gi->B = B;
+    uint32_t off = 0;
+    for (int L = 0; L <= B; ++L) {
+        gi->lvl_off[L] = off;
+        off += 1u << (3 * (B - L));
+    }
+    gi->lvl_off[B + 1] = off;
 }
 
 __device__ __forceinline__ int cell_coord(float p, float lo, float inv_h, int dim) {
@@ -235,10 +241,11 @@ __global__ void __launch_bounds__(256) k_reg_keys(RegArgs a) {
     uint32_t key = KEY_NONE;
     if (a.cls[g] == CLS_SOURCE) {
         const GridInfo& gi = *a.grid;
-        const int cx = cell_coord(a.m0[3 * g], gi.lo[0], gi.inv_h, gi.dim[0]);
-        const int cy = cell_coord(a.m0[3 * g + 1], gi.lo[1], gi.inv_h, gi.dim[1]);
-        const int cz = cell_coord(a.m0[3 * g + 2], gi.lo[2], gi.inv_h, gi.dim[2]);
-        key = (uint32_t)((cz * gi.dim[1] + cy) * gi.dim[0] + cx);
+        const int dim = 1 << gi.B;
+        const int cx = cell_coord(a.m0[3 * g], gi.lo[0], gi.inv_h, dim);
+        const int cy = cell_coord(a.m0[3 * g + 1], gi.lo[1], gi.inv_h, dim);
+        const int cz = cell_coord(a.m0[3 * g + 2], gi.lo[2], gi.inv_h, dim);
+        key = morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
     }
     a.keys[g] = key;
 }
@@ -255,8 +262,14 @@ __global__ void __launch_bounds__(256) k_reg_cells(RegArgs a) {
     if (key >= KEY_NONE) return;
     const uint32_t g = a.svals[i];
     if (g >= (uint64_t)a.N) return;
-    if (i == 0 || a.skeys[i - 1] != key) a.ranges[key].x = (uint32_t)i;
-    if (i == a.N - 1 || a.skeys[i + 1] != key) a.ranges[key].y = (uint32_t)(i + 1);
+    const GridInfo& gi = *a.grid;
+    const uint32_t prev = i > 0 ? a.skeys[i - 1] : KEY_NONE;
+    const uint32_t next = i + 1 < a.N ? a.skeys[i + 1] : KEY_NONE;
+    for (int L = 0; L <= gi.B; ++L) {
+        const uint32_t c = key >> (3 * L);
+        if (prev >= KEY_NONE || (prev >> (3 * L)) != c) a.ranges[gi.lvl_off[L] + c].x = (uint32_t)i;
+        if (next >= KEY_NONE || (next >> (3 * L)) != c) a.ranges[gi.lvl_off[L] + c].y = (uint32_t)(i + 1);
+    }
     a.spos[i] = make_float4(a.m0[3 * g], a.m0[3 * g + 1], a.m0[3 * g + 2], __builtin_bit_cast(float, g));
 }
 
@@ -273,7 +286,39 @@ __device__ __forceinline__ void topk_insert(double* bd, uint32_t* bi, int& cnt, 
     bi[j] = id;
 }
 
-__global__ void __launch_bounds__(128) k_reg_knn(RegArgs a) {
+// Morton code -> one coordinate (every third bit)
+__device__ __forceinline__ uint32_t compact1by2(uint32_t x) {
+    x &= 0x9249249u;
+    x = (x ^ (x >> 2)) & 0x30c30c3u;
+    x = (x ^ (x >> 4)) & 0x300f00fu;
+    x = (x ^ (x >> 8)) & 0x30000ffu;
+    x = (x ^ (x >> 16)) & 0x3ffu;
+    return x;
+}
+
+// squared distance from p to the box of cell `code` at level L (FP64)
+__device__ __forceinline__ double box_dist2(const GridInfo& gi, int L, uint32_t code, const double p[3]) {
+    const double hL = gi.h * (double)(1 << L);
+    const uint32_t c[3] = {compact1by2(code), compact1by2(code >> 1), compact1by2(code >> 2)};
+    double d2 = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const double lo = (double)gi.lo[ax] + c[ax] * hL, hi = lo + hL;
+        const double d = p[ax] < lo ? lo - p[ax] : (p[ax] > hi ? p[ax] - hi : 0.0);
+        d2 += d * d;
+    }
+    return d2;
+}
+
+constexpr int KNN_THREADS = 128;
+constexpr int STACK = 64;      // >= 1 + 7 B entries for B <= 7
+constexpr uint32_t LEAF = 16;  // scan a cell's points directly at or below this count
+
+__global__ void __launch_bounds__(KNN_THREADS) k_reg_knn(RegArgs a) {
+    // Best-first descent of the implicit octree (cells of every level are
+    // Morton runs): a node is skipped when its box is farther than the
+    // current K-th neighbour, children are visited nearest first.  Boxes are
+    // widened by a margin because cells were assigned in FP32.
+    __shared__ uint32_t stk[KNN_THREADS * STACK];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.N) return;
     if (a.cls[g] == CLS_STATIC) {
@@ -286,51 +331,52 @@ __global__ void __launch_bounds__(128) k_reg_knn(RegArgs a) {
         a.ncnt[g] = 0;
         return;
     }
-    const float px = a.m0[3 * g], py = a.m0[3 * g + 1], pz = a.m0[3 * g + 2];
-    const int hx = cell_coord(px, gi.lo[0], gi.inv_h, gi.dim[0]);
-    const int hy = cell_coord(py, gi.lo[1], gi.inv_h, gi.dim[1]);
-    const int hz = cell_coord(pz, gi.lo[2], gi.inv_h, gi.dim[2]);
-    const int rmax = max(gi.dim[0], max(gi.dim[1], gi.dim[2]));
+    const double p[3] = {a.m0[3 * g], a.m0[3 * g + 1], a.m0[3 * g + 2]};
+    const double margin = 1e-3 * gi.h;
+    uint32_t* st = stk + threadIdx.x * STACK;
     double bd[KMAX];
     uint32_t bi[KMAX];
     int cnt = 0;
-    // cells were assigned in FP32 ((p - lo) / h up to ~1024 carries ~1e-4 of a
-    // cell of rounding), so faces are moved in by a margin
-    const double h = gi.h, margin = 1e-3 * h;
-    for (int r = 0; r <= rmax; ++r) {
-        const int z0 = max(hz - r, 0), z1 = min(hz + r, gi.dim[2] - 1);
-        const int y0 = max(hy - r, 0), y1 = min(hy + r, gi.dim[1] - 1);
-        const int x0 = max(hx - r, 0), x1 = min(hx + r, gi.dim[0] - 1);
-        // the cells at Chebyshev distance exactly r from the home cell
-        for (int z = z0; z <= z1; ++z)
-            for (int y = y0; y <= y1; ++y) {
-                const bool face = r == 0 || z == hz - r || z == hz + r || y == hy - r || y == hy + r;
-                const int xa = face ? x0 : hx - r, xb = face ? x1 : hx + r;
-                const int step = face ? 1 : 2 * r;
-                for (int x = xa; x <= xb; x += step) {
-                    if (x < 0 || x >= gi.dim[0]) continue;
-                    const uint2 rg = a.ranges[(z * gi.dim[1] + y) * gi.dim[0] + x];
-                    for (uint32_t i = rg.x; i < rg.y; ++i) {
-                        const float4 q = a.spos[i];
-                        const double dx = (double)q.x - px, dy = (double)q.y - py, dz = (double)q.z - pz;
-                        topk_insert(bd, bi, cnt, K, dx * dx + dy * dy + dz * dz, __builtin_bit_cast(uint32_t, q.w));
-                    }
-                }
-            }
+    int sp = 0;
+    st[sp++] = ((uint32_t)gi.B << 24);
+    while (sp > 0) {
+        const uint32_t node = st[--sp];
+        const int L = (int)(node >> 24);
+        const uint32_t code = node & 0xFFFFFFu;
+        const uint2 rg = a.ranges[gi.lvl_off[L] + code];
+        if (rg.y <= rg.x) continue;
         if (cnt == K) {
-            // distance from p to the nearest face of the visited block of
-            // cells, ignoring faces on the grid boundary (nothing beyond)
-            double bound = 1e300;
-            const float pp[3] = {px, py, pz};
-            const int hc[3] = {hx, hy, hz};
-            for (int ax = 0; ax < 3; ++ax) {
-                if (hc[ax] - r > 0) bound = fmin(bound, (double)pp[ax] - (gi.lo[ax] + (hc[ax] - r) * h));
-                if (hc[ax] + r < gi.dim[ax] - 1) bound = fmin(bound, (gi.lo[ax] + (hc[ax] + r + 1) * h) - pp[ax]);
-            }
-            bound -= margin;
-            if (bound > 0 && bd[K - 1] < bound * bound) break;
-            if (bound >= 1e299) break;   // the whole grid has been visited
+            const double dn = sqrt(box_dist2(gi, L, code, p)) - margin;
+            if (dn > 0.0 && dn * dn > bd[K - 1]) continue;
         }
+        if (L == 0 || rg.y - rg.x <= LEAF) {
+            for (uint32_t i = rg.x; i < rg.y; ++i) {
+                const float4 q = a.spos[i];
+                const double dx = (double)q.x - p[0], dy = (double)q.y - p[1], dz = (double)q.z - p[2];
+                topk_insert(bd, bi, cnt, K, dx * dx + dy * dy + dz * dz, __builtin_bit_cast(uint32_t, q.w));
+            }
+            continue;
+        }
+        // children, pushed farthest first so the nearest is visited next
+        double cd[8];
+        uint32_t cc[8];
+        int nc = 0;
+        const uint2* rc = a.ranges + gi.lvl_off[L - 1];
+        for (uint32_t k = 0; k < 8; ++k) {
+            const uint32_t ch = (code << 3) | k;
+            const uint2 r2 = rc[ch];
+            if (r2.y <= r2.x) continue;
+            const double d2 = box_dist2(gi, L - 1, ch, p);
+            int j = nc++;
+            while (j > 0 && cd[j - 1] < d2) {   // descending by distance
+                cd[j] = cd[j - 1];
+                cc[j] = cc[j - 1];
+                --j;
+            }
+            cd[j] = d2;
+            cc[j] = ch;
+        }
+        for (int k = 0; k < nc && sp < STACK; ++k) st[sp++] = ((uint32_t)(L - 1) << 24) | cc[k];
     }
     for (int k = 0; k < K; ++k) a.nbr[g * KMAX + k] = bi[k];
     a.ncnt[g] = (uint8_t)K;
@@ -423,7 +469,7 @@ RegLayout reg_layout(int64_t N) {
     L.vb = take((size_t)N * 4);
     L.kf = take((size_t)N * 4);
     L.vf = take((size_t)N * 4);
-    L.ranges = take((size_t)CELL_MAX * 8);
+    L.ranges = take((size_t)RANGES_MAX * 8);
     L.spos = take((size_t)N * 16);
     L.grid = take(sizeof(GridInfo));
     L.sort = take(tg_sort_scratch_bytes(N, 1));
@@ -494,10 +540,10 @@ extern "C" tg_status tg_regularize(const tg_gaussians* g_ref, const tg_gaussians
                                  (uint32_t*)(w + L.kb), (uint32_t*)(w + L.vb), (uint32_t*)(w + L.kf),
                                  (uint32_t*)(w + L.vf), N, 1, nullptr, 0, SORT_PASSES, w + L.sort, s);
     if (st != TG_OK) return st;
-    hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)((CELL_MAX + 255) / 256)), dim3(256), 0, s, a.ranges,
-                       (int64_t)CELL_MAX);
+    hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)((RANGES_MAX + 255) / 256)), dim3(256), 0, s, a.ranges,
+                       (int64_t)RANGES_MAX);
     hipLaunchKernelGGL(k_reg_cells, dim3(b256), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_reg_knn, dim3(b128), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(k_reg_knn, dim3(b128), dim3(KNN_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_reg_filter, dim3(b128), dim3(128), 0, s, a);
     hipLaunchKernelGGL(k_reg_apply, dim3(b128), dim3(128), 0, s, a);
     TG_CHECK_LAUNCH();
