@@ -104,7 +104,8 @@ __device__ __forceinline__ void sums_add(Sums& s, float wgt, float wx, float wy,
 // different work never hold each other's resources.  FM: frames per slot the
 // launch is compiled for (a slot may carry fewer).
 template <int FM, bool STATS>
-__global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FM == 1 ? 7 : 1, 8)))
+k_accumulate(BatchArgs a)
 {
     // 3.7 KB of LDS per wave: queue of filtered list entries (ids), column
     // offsets as floats, per-pixel transmittance and the atomics' transpose
@@ -259,52 +260,33 @@ __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
               const float uy = dyl + (float)(4 * g + rr);
               const float brow = cb * uy;
               const float hrow = cc * uy * uy;
-              // two pixels per step: their dependency chains interleave
+              // one pixel per step keeps the kernel at 72 registers (7 waves
+              // per SIMD); the pixel's chain is short enough for them to hide
               while (m) {
                 const int c1 = __builtin_ctz(m);
                 m &= m - 1;
-                const bool two = m != 0;
-                const int c2 = two ? (int)__builtin_ctz(m) : c1;
-                if (two) m &= m - 1;
-                const int j1 = 16 * rr + c1, j2 = 16 * rr + c2;
-                const int p1 = g * 64 + j1, p2i = g * 64 + j2;
-                const float T1 = T_[p1], T2 = T_[p2i];
-                const float ux1 = dxl + CF[c1], ux2 = dxl + CF[c2];
-                const float uy1 = uy, uy2 = uy;
+                const int j1 = 16 * rr + c1;
+                const int p1 = g * 64 + j1;
+                const float T1 = T_[p1];
+                const float ux1 = dxl + CF[c1];
+                const float uy1 = uy;
                 const float q1 = ux1 * (ca * ux1 + brow) + hrow;
-                const float q2 = ux2 * (ca * ux2 + brow) + hrow;
                 // alpha = min(alpha_max, o e^power), clamped with one v_med3
                 const float al1 = __builtin_amdgcn_fmed3f(op * __builtin_amdgcn_exp2f(q1), 0.0f, amax);
-                const float al2 = __builtin_amdgcn_fmed3f(op * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
                 // valid lanes: power <= 0 and alpha >= alpha_min
                 const uint64_t vm1 = ballot64(q1 <= 0.0f) & ballot64(al1 >= amin);
-                const uint64_t vm2 = two ? (ballot64(q2 <= 0.0f) & ballot64(al2 >= amin)) : 0ull;
                 float P1 = __builtin_amdgcn_inverse_ballot_w64(vm1) ? 1.0f - al1 : 1.0f;
-                float P2 = __builtin_amdgcn_inverse_ballot_w64(vm2) ? 1.0f - al2 : 1.0f;
-                wave_scan_mul_fused2(P1, P2);
+                P1 = wave_scan_mul_fused(P1);
                 const uint64_t tm1 = ballot64(T1 * P1 < tmin) & vm1;
-                const uint64_t tm2 = ballot64(T2 * P2 < tmin) & vm2;
                 const int kt1 = (int)__builtin_ctzll(tm1 | (1ull << 63));
-                const int kt2 = (int)__builtin_ctzll(tm2 | (1ull << 63));
                 const uint64_t cm1 = vm1 & (tm1 ? ((1ull << kt1) - 1ull) : ~0ull);
-                const uint64_t cm2 = vm2 & (tm2 ? ((1ull << kt2) - 1ull) : ~0ull);
                 const float Pk1 = tm1 ? (kt1 == 0 ? 1.0f : readlane_f(P1, kt1 - 1)) : readlane_f(P1, 63);
-                const float Pk2 = tm2 ? (kt2 == 0 ? 1.0f : readlane_f(P2, kt2 - 1)) : readlane_f(P2, 63);
-                if (lane0) {
-                    T_[p1] = T1 * Pk1;
-                    if (two) T_[p2i] = T2 * Pk2;
-                }
+                if (lane0) T_[p1] = T1 * Pk1;
                 if (tm1) dead |= 1ull << j1;
-                if (tm2) dead |= 1ull << j2;
                 if (STATS) {
                     n_eval += (uint64_t)(tm1 ? kt1 + 1 : nb);
                     n_contrib += (uint64_t)__popcll(cm1);
                     n_iter += 1;
-                    if (two) {
-                        n_eval += (uint64_t)(tm2 ? kt2 + 1 : nb);
-                        n_contrib += (uint64_t)__popcll(cm2);
-                        n_iter += 1;
-                    }
                 }
                 // statistics of Eq. 4 for the lanes that contribute, per frame
                 // whose track at this pixel is visible
@@ -327,27 +309,6 @@ __global__ void __launch_bounds__(64) k_accumulate(BatchArgs a)
                             if ((fl1 >> f) & 1u)
                                 sums_add(sm[f], wgt, wx, wy, wxx, wxy, wyy, tdx[f], tdy[f], (fl1 >> (8 + f)) & 1u,
                                          al1);
-                    }
-                }
-                const uint32_t fl2 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j2);
-                if (cm2 && (fl2 & VISM)) {
-                    float tdx[FM], tdy[FM];
-#pragma unroll
-                    for (int f = 0; f < FM; ++f) {
-                        tdx[f] = readlane_f(dxg[f][g], j2);
-                        tdy[f] = readlane_f(dyg[f][g], j2);
-                    }
-                    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
-                                 : "+v"(pex_reg) : "v"(P2));
-                    if (__builtin_amdgcn_inverse_ballot_w64(cm2)) {
-                        const float wgt = al2 * (T2 * pex_reg);
-                        const float wx = wgt * ux2, wy = wgt * uy2;
-                        const float wxx = wx * ux2, wxy = wx * uy2, wyy = wy * uy2;
-#pragma unroll
-                        for (int f = 0; f < FM; ++f)
-                            if ((fl2 >> f) & 1u)
-                                sums_add(sm[f], wgt, wx, wy, wxx, wxy, wyy, tdx[f], tdy[f], (fl2 >> (8 + f)) & 1u,
-                                         al2);
                     }
                 }
               }
