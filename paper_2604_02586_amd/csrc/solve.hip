@@ -187,10 +187,9 @@ struct TriArgs {
     int scale_mode;
 };
 
-__global__ void __launch_bounds__(128) k_triangulate(TriArgs a, CamPack cams, tg_params prm)
+// The full multi-view update of Gaussian g.
+__device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, const tg_params& prm, int64_t g)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.N) return;
     const float om0 = a.means_in[3 * g], om1 = a.means_in[3 * g + 1], om2 = a.means_in[3 * g + 2];
     const float oq0 = a.quats_in[4 * g], oq1 = a.quats_in[4 * g + 1], oq2 = a.quats_in[4 * g + 2],
                 oq3 = a.quats_in[4 * g + 3];
@@ -429,6 +428,60 @@ __global__ void __launch_bounds__(128) k_triangulate(TriArgs a, CamPack cams, tg
     if (a.status) a.status[g] = st;
 }
 
+// The totals that decide whether Gaussian g is a candidate at all (views
+// solved, accumulated alpha, pixels); a non-candidate is copied and done.
+__device__ __forceinline__ uint32_t tri_light(const TriArgs& a, const tg_params& prm, int64_t g) {
+    int nv = 0;
+    double sw = 0.0, nt = 0.0;
+    for (int v = 0; v < a.V; ++v) {
+        const int64_t o = (int64_t)v * a.N + g;
+        const ushort4 r = a.rect[o];
+        if (r.z > r.x && r.w > r.y) {
+            sw += (double)a.acc[o * TG_ACC_STRIDE + 0];
+            nt += (double)a.acc[o * TG_ACC_STRIDE + 12];
+        }
+        if (a.vflags[o] == 1) ++nv;
+    }
+    uint32_t st = 0;
+    if (nv < prm.views_min) st |= 4;
+    if (!(sw >= prm.wsum_total_min)) st |= 8;
+    if (nt < (double)prm.pix_total_min) st |= 16;
+    return st;
+}
+
+// A block first screens TRI_ITEMS x 256 Gaussians with the cheap totals and
+// compacts the candidates in LDS, then runs the full update on the compacted
+// list, so the register-heavy FP64 part runs in dense waves even when few
+// Gaussians qualify.
+constexpr int TRI_THREADS = 256;
+constexpr int TRI_ITEMS = 8;
+
+__global__ void __launch_bounds__(TRI_THREADS) k_triangulate(TriArgs a, CamPack cams, tg_params prm)
+{
+    __shared__ uint32_t cand[TRI_THREADS * TRI_ITEMS];
+    __shared__ uint32_t cn;
+    const int t = threadIdx.x;
+    if (t == 0) cn = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (TRI_THREADS * TRI_ITEMS);
+    for (int it = 0; it < TRI_ITEMS; ++it) {
+        const int64_t g = base + (int64_t)it * TRI_THREADS + t;
+        if (g >= a.N) break;
+        const uint32_t st = tri_light(a, prm, g);
+        if (st == 0) {
+            cand[atomicAdd(&cn, 1u)] = (uint32_t)(g - base);
+        } else {
+            for (int i = 0; i < 3; ++i) a.means_out[3 * g + i] = a.means_in[3 * g + i];
+            for (int i = 0; i < 4; ++i) a.quats_out[4 * g + i] = a.quats_in[4 * g + i];
+            for (int i = 0; i < 3; ++i) a.scales_out[3 * g + i] = a.scales_in[3 * g + i];
+            if (a.status) a.status[g] = st;
+        }
+    }
+    __syncthreads();
+    const uint32_t n = cn;
+    for (uint32_t i = t; i < n; i += TRI_THREADS) tri_one(a, cams, prm, base + cand[i]);
+}
+
 }  // namespace
 
 extern "C" tg_status tg_solve_views(const float* acc, const tg_splats* s, int64_t N, int32_t V, const tg_params* p,
@@ -478,7 +531,8 @@ extern "C" tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_ne
     a.scale_mode = g_in->scale_mode;
     CamPack cp;
     for (int v = 0; v < V; ++v) cp.cam[v] = cams[v];
-    hipLaunchKernelGGL(k_triangulate, dim3((unsigned)((N + 127) / 128)), dim3(128), 0, (hipStream_t)stream, a, cp,
+    hipLaunchKernelGGL(k_triangulate, dim3((unsigned)((N + TRI_THREADS * TRI_ITEMS - 1) / (TRI_THREADS * TRI_ITEMS))),
+                       dim3(TRI_THREADS), 0, (hipStream_t)stream, a, cp,
                        *p);
     TG_CHECK_LAUNCH();
     return TG_OK;
