@@ -95,6 +95,9 @@ __device__ __forceinline__ void sums_add(Sums& s, float wgt, float wx, float wy,
     s.ydy += wy * tdy;
     s.n += 1.0f;
     if (stat) {
+        // static pixels are rare: a real (wave-uniform) branch, kept from
+        // being turned into selects that would cost every pixel
+        asm volatile("");
         s.sn += 1.0f;
         s.sa += al;
     }
