@@ -27,23 +27,38 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __r
                                                              const int64_t* __restrict__ dev_count, int shift,
                                                              uint32_t* __restrict__ ghist, int nblk)
 {
-    __shared__ uint32_t h[256];
+    // one sub-histogram per wave (fewer LDS atomic collisions), keys loaded
+    // as uint4 where the block's range is whole and aligned
+    __shared__ uint32_t h[SORT_WAVES][256];
     const int seg = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
-    h[t] = 0;
+    const int w = t >> 6, l = t & 63;
+    for (int i = t; i < SORT_WAVES * 256; i += SORT_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
     const int64_t n = seg_count(seg_len, dev_count);
     const int64_t base = (int64_t)b * SORT_TILE;
     const uint32_t* kp = keys + (int64_t)seg * seg_len;
-    if (base < n) {
-        const int w = t >> 6, l = t & 63;
+    if (base + SORT_TILE <= n && (((uintptr_t)(kp + base)) & 15u) == 0) {
+        const uint4* k4 = (const uint4*)(kp + base);
+#pragma unroll
+        for (int r = 0; r < SORT_ITEMS / 4; ++r) {
+            const uint4 k = k4[r * SORT_THREADS + t];
+            atomicAdd(&h[w][(k.x >> shift) & 255u], 1u);
+            atomicAdd(&h[w][(k.y >> shift) & 255u], 1u);
+            atomicAdd(&h[w][(k.z >> shift) & 255u], 1u);
+            atomicAdd(&h[w][(k.w >> shift) & 255u], 1u);
+        }
+    } else if (base < n) {
 #pragma unroll 4
         for (int r = 0; r < SORT_ITEMS; ++r) {
             int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
-            if (idx < n) atomicAdd(&h[(kp[idx] >> shift) & 255u], 1u);
+            if (idx < n) atomicAdd(&h[w][(kp[idx] >> shift) & 255u], 1u);
         }
     }
     __syncthreads();
-    ghist[((int64_t)seg * 256 + t) * nblk + b] = h[t];
+    uint32_t c = 0;
+#pragma unroll
+    for (int ww = 0; ww < SORT_WAVES; ++ww) c += h[ww][t];
+    ghist[((int64_t)seg * 256 + t) * nblk + b] = c;
 }
 
 // ---- exclusive scan of a [nseg][L] u32 array (three kernels) ------------
