@@ -202,3 +202,41 @@ def render(means, quats, log_scales, logit_opacity, sh, cams, bg=(0.0, 0.0, 0.0)
             marg[torch.tensor(at)] = mg
         out = torch.stack(out, 0)
     return (out, marg) if return_marginal else out
+
+
+# ---------------------------------------------------------------------------
+# 3DGS objective (Sec. 4.6 refines "following the original 3DGS method"):
+# L = (1 - lambda) L1 + lambda (1 - SSIM), SSIM with an 11x11 Gaussian window
+# (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, zero padding, mean over pixels and
+# channels of every image.
+# ---------------------------------------------------------------------------
+SSIM_WIN, SSIM_SIGMA, SSIM_C1, SSIM_C2, DSSIM_LAMBDA = 11, 1.5, 0.01 ** 2, 0.03 ** 2, 0.2
+
+
+def gaussian_window(n=SSIM_WIN, sigma=SSIM_SIGMA):
+    x = torch.arange(n, dtype=torch.float64) - (n - 1) / 2
+    g = torch.exp(-x * x / (2 * sigma * sigma))
+    return g / g.sum()
+
+
+def ssim(img, tgt):
+    """Mean SSIM of images [..., H, W, C] (torch, differentiable, FP64)."""
+    return ssim_map(img, tgt).mean()
+
+
+def ssim_map(img, tgt):
+    """Per-pixel SSIM [B*C, 1, H, W] of images [..., H, W, C]."""
+    g = gaussian_window()
+    w2 = (g[:, None] * g[None, :])[None, None]                    # [1,1,11,11]
+    x = img.reshape(-1, *img.shape[-3:]).permute(0, 3, 1, 2).reshape(-1, 1, *img.shape[-3:-1])
+    y = tgt.reshape(-1, *tgt.shape[-3:]).permute(0, 3, 1, 2).reshape(-1, 1, *tgt.shape[-3:-1])
+    conv = lambda a: torch.nn.functional.conv2d(a, w2, padding=SSIM_WIN // 2)
+    mx, my = conv(x), conv(y)
+    sxx = conv(x * x) - mx * mx
+    syy = conv(y * y) - my * my
+    sxy = conv(x * y) - mx * my
+    return ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+
+
+def loss_3dgs(img, tgt, lam=DSSIM_LAMBDA):
+    return (1 - lam) * (img - tgt).abs().mean() + lam * (1 - ssim(img, tgt))

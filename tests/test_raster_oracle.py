@@ -140,3 +140,37 @@ def test_reference_gradient_by_finite_differences():
                 bad += 1
                 print(names[pi], k, fd, an)
     assert checked >= 40 and bad == 0, (bad, checked)
+
+
+def test_ssim_against_scipy_convolution():
+    """The reference SSIM (torch conv2d) against the same definition computed
+    with scipy's 2D convolution, and SSIM(x, x) = 1."""
+    from scipy.signal import convolve2d
+    rng = np.random.default_rng(11)
+    a = rng.uniform(0, 1, (2, 23, 31, 3))
+    b = np.clip(a + rng.normal(0, 0.1, a.shape), 0, 1)
+    g = raster_ref.gaussian_window().numpy()
+    w = np.outer(g, g)
+    vals = []
+    for i in range(2):
+        for c in range(3):
+            x, y = a[i, :, :, c], b[i, :, :, c]
+            cv = lambda z: convolve2d(z, w, mode="same", boundary="fill")
+            mx, my = cv(x), cv(y)
+            sxx, syy, sxy = cv(x * x) - mx * mx, cv(y * y) - my * my, cv(x * y) - mx * my
+            c1, c2 = raster_ref.SSIM_C1, raster_ref.SSIM_C2
+            vals.append(((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2)))
+    ref = np.mean(vals)
+    got = float(raster_ref.ssim(torch.tensor(a), torch.tensor(b)))
+    assert abs(got - ref) < 1e-12
+    assert abs(float(raster_ref.ssim(torch.tensor(a), torch.tensor(a))) - 1.0) < 1e-12
+
+
+def test_ssim_constant_images_closed_form():
+    """Interior pixels of two constant images a, b: SSIM = (2ab + C1)/(a^2 + b^2 + C1)."""
+    a, b = 0.3, 0.7
+    x = torch.full((1, 40, 40, 1), a, dtype=torch.float64)
+    y = torch.full((1, 40, 40, 1), b, dtype=torch.float64)
+    inner = raster_ref.ssim_map(x, y)[0, 0, 5:-5, 5:-5]
+    np.testing.assert_allclose(inner.numpy(), (2 * a * b + raster_ref.SSIM_C1) / (a * a + b * b + raster_ref.SSIM_C1),
+                               rtol=1e-12)
