@@ -226,15 +226,17 @@ def serving_bench(dev, n_frames=24, clients=4, rates=(2.0, 20.0), seed=12, n_tem
 
 def refine_bench(dev, iters=100, warmup=3):
     """Post-relocation refinement at the refinement workload's shape: 500k
-    Gaussians with degree-3 SH, 16 views at 1352x1014, L1 loss against
-    images rendered from the ground truth, Adam (lr 1e-3) from a perturbed
-    copy; one iteration = preprocess + binning + raster forward, L1,
+    Gaussians with degree-3 SH, 16 views at 1352x1014, against images rendered
+    from the ground truth, from a perturbed copy.  Two recipes: L1 + Adam
+    (lr 1e-3), and the 3DGS recipe (objective 0.8 L1 + 0.2 (1 - SSIM),
+    per-parameter rates with the decayed position rate).  One iteration =
+    preprocess + binning + raster forward, loss and its image gradient,
     raster backward + projection backward, Adam on every parameter."""
     import numpy as np
     import torch
 
     import synth
-    from paper_2604_02586_amd.raster import Adam, L1Loss, RasterContext, rasterize
+    from paper_2604_02586_amd.raster import Adam, L1Loss, Loss3DGS, RasterContext, lr_3dgs, rasterize, scene_extent
 
     t0 = time.perf_counter()
     wl = synth.make_refine_workload("refine")
@@ -246,33 +248,44 @@ def refine_bench(dev, iters=100, warmup=3):
     with torch.no_grad():
         target = rasterize(*gt, rc).clone()
     del gt
+    extent = scene_extent(rc.cams)
+    K = wl.init["sh"].shape[1]
 
     def fresh():
         return [torch.tensor(wl.init[k], device=dev, requires_grad=True) for k in keys]
 
-    def run(params, n):
-        opt = Adam(params, lr=1e-3)
+    def run(params, n, recipe):
+        opt = Adam(params, lr=1e-3 if recipe == "l1" else lr_3dgs(0, extent, K))
         losses = []
-        for _ in range(n):
+        for it in range(n):
             img = rasterize(*params, rc)
-            loss = L1Loss.apply(img, target)
+            if recipe == "l1":
+                loss = L1Loss.apply(img, target)
+            else:
+                opt.lr = lr_3dgs(it, extent, K)
+                loss = Loss3DGS.apply(img, target)
             opt.zero_grad()
             loss.backward()
             opt.step()
             losses.append(loss.detach())
         return losses
 
-    run(fresh(), warmup)
-    params = fresh()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    losses = run(params, iters)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t1
-    losses = [float(x) for x in losses]
-    return {"workload": f"refine: {N} Gaussians (SH degree 3) x {V} views x {W}x{H}, L1 + Adam lr 1e-3",
-            "iterations": iters, "ms_per_iteration": t * 1e3 / iters, "iterations_per_s": iters / t,
-            "loss_first": losses[0], "loss_last": losses[-1]}
+    out = {"workload": f"refine: {N} Gaussians (SH degree 3) x {V} views x {W}x{H}", "iterations": iters}
+    for recipe, label in (("l1", "L1 + Adam lr 1e-3"), ("3dgs", "3DGS objective and rates")):
+        run(fresh(), warmup, recipe)
+        params = fresh()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        losses = run(params, iters, recipe)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t1
+        losses = [float(x) for x in losses]
+        key = "" if recipe == "l1" else "_3dgs"
+        out.update({f"recipe{key}": label, f"ms_per_iteration{key}": t * 1e3 / iters,
+                    f"iterations_per_s{key}": iters / t, f"loss_first{key}": losses[0],
+                    f"loss_last{key}": losses[-1]})
+        log(f"  refine [{recipe}] {t * 1e3 / iters:.2f} ms/iteration, loss {losses[0]:.5f} -> {losses[-1]:.5f}")
+    return out
 
 
 def main():

@@ -10,7 +10,8 @@
  *                   -> tg_solve_views -> tg_triangulate
  * and the post-relocation refinement uses
  *     tg_preprocess -> tg_bin_sort -> tg_raster_fwd / tg_raster_bwd
- *                   -> tg_l1_loss_grad -> tg_adam_step.
+ *                   -> tg_l1_loss_grad (+ tg_ssim_loss_grad for the 3DGS
+ *                      objective) -> tg_adam_step / tg_adam_step_rows.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -384,9 +385,35 @@ tg_status tg_project_bwd(const tg_gaussians* g, const tg_splats* s, int64_t N, c
 tg_status tg_l1_loss_grad(const float* image, const float* target, int64_t n, float scale, float* grad,
                           float* loss_sum, void* stream);
 
+/*
+ * tg_ssim_loss_grad -- the structural-similarity term of the 3DGS objective
+ * the refinement optimises (Sec. 4.6: (1 - lambda) L1 + lambda (1 - SSIM),
+ * lambda = 0.2, as in 3DGS).  SSIM per pixel and channel over an 11x11
+ * Gaussian window (sigma 1.5, zero padding at the borders) with
+ * C1 = 0.01^2, C2 = 0.03^2.
+ * image, target: device [B,H,W,3].  Adds scale * d(sum of the SSIM map)/d image
+ * to grad (device [B,H,W,3]; so tg_l1_loss_grad, which writes grad, runs
+ * first, and the caller passes scale = -lambda / (B*H*W*3) for the objective
+ * above).  Adds the sum of the SSIM map (unscaled) to *ssim_sum (device
+ * float, nullable).  ws: three [B,H,W,3] float maps; query with ws == NULL.
+ * Errors: TG_ERR_INVALID_ARG for null buffers or negative sizes,
+ *         TG_ERR_WORKSPACE if *ws_bytes is smaller than required.
+ */
+tg_status tg_ssim_loss_grad(const float* image, const float* target, int32_t B, int32_t H, int32_t W, float scale,
+                            float* grad, float* ssim_sum, void* ws, size_t* ws_bytes, void* stream);
+
 /* Adam (bias-corrected, step >= 1), in place on param, m, v. */
 tg_status tg_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
                        float beta2, float eps, int32_t step, void* stream);
+
+/* Adam as above over n / row rows of row floats, with two learning rates:
+ * the first `head` floats of every row step with lr_head, the rest with
+ * lr_tail.  3DGS steps the DC SH coefficients (head = 3 of row = 3 (D+1)^2)
+ * 20x faster than the higher bands.  TG_ERR_INVALID_ARG unless
+ * 0 <= head <= row and n is a multiple of row. */
+tg_status tg_adam_step_rows(float* param, const float* grad, float* m, float* v, int64_t n, int32_t row,
+                            int32_t head, float lr_head, float lr_tail, float beta1, float beta2, float eps,
+                            int32_t step, void* stream);
 
 /* Linear index of tiles and coarse bins, for tests and tools: expands the
  * coarse lists into the per-tile depth-ordered lists.  tile_ranges [T,2]

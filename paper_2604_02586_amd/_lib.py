@@ -97,7 +97,9 @@ def lib():
         "tg_raster_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),
         "tg_project_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P], st),
         "tg_l1_loss_grad": ([P, P, c_i64, c_f, P, P, P], st),
+        "tg_ssim_loss_grad": ([P, P, c_i32, c_i32, c_i32, c_f, P, P, P, P, P], st),
         "tg_adam_step": ([P, P, P, P, c_i64, c_f, c_f, c_f, c_f, c_i32, P], st),
+        "tg_adam_step_rows": ([P, P, P, P, c_i64, c_i32, c_i32, c_f, c_f, c_f, c_f, c_f, c_i32, P], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -111,7 +113,8 @@ def exported_symbols():
     return [n for n in ("tg_abi_version", "tg_status_string", "tg_default_params", "tg_num_cells",
                         "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_splat_accumulate",
                         "tg_splat_accumulate_batch", "tg_regularize", "tg_solve_views", "tg_triangulate", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
-                        "tg_project_bwd", "tg_l1_loss_grad", "tg_adam_step")]
+                        "tg_project_bwd", "tg_l1_loss_grad", "tg_ssim_loss_grad", "tg_adam_step",
+                        "tg_adam_step_rows")]
 
 
 def check(fn, code):

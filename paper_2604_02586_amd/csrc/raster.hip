@@ -20,7 +20,7 @@
 //                   go to HBM with one set of atomics per (tile, Gaussian).
 //   tg_project_bwd  per Gaussian, over views: splat gradients -> mean,
 //                   quaternion, log-scale, logit-opacity, SH coefficients.
-//   tg_l1_loss_grad, tg_adam_step: elementwise.
+//   tg_l1_loss_grad, tg_adam_step, tg_adam_step_rows: elementwise.
 #include "tg_internal.h"
 
 namespace {
@@ -587,8 +587,12 @@ __global__ void __launch_bounds__(256) k_l1(const float* __restrict__ img, const
     if (threadIdx.x == 0 && loss) atomicAdd(loss, (red[0] + red[1] + red[2] + red[3]) * scale);
 }
 
+// Adam over rows of `row` floats: the first `head` floats of each row step
+// with lr_head, the rest with lr_tail (3DGS steps the DC colour coefficients
+// and the higher SH bands at different rates).
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+                       float* __restrict__ v, int64_t n, int row, int head, float lr_head, float lr_tail, float b1,
+                       float b2, float eps, float c1, float c2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
@@ -596,6 +600,7 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
+    const float lr = (int)(i % row) < head ? lr_head : lr_tail;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
@@ -723,14 +728,30 @@ extern "C" tg_status tg_l1_loss_grad(const float* image, const float* target, in
     return TG_OK;
 }
 
-extern "C" tg_status tg_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
-                                  float beta1, float beta2, float eps, int32_t step, void* stream)
+static tg_status adam_launch(float* param, const float* grad, float* m, float* v, int64_t n, int32_t row,
+                             int32_t head, float lr_head, float lr_tail, float beta1, float beta2, float eps,
+                             int32_t step, void* stream)
 {
-    if (!param || !grad || !m || !v || n < 0 || step < 1) return TG_ERR_INVALID_ARG;
+    if (!param || !grad || !m || !v || n < 0 || step < 1 || row < 1 || head < 0 || head > row)
+        return TG_ERR_INVALID_ARG;
+    if (n % row) return TG_ERR_INVALID_ARG;
     if (n == 0) return TG_OK;
     const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, param, grad, m, v,
-                       n, lr, beta1, beta2, eps, c1, c2);
+                       n, row, head, lr_head, lr_tail, beta1, beta2, eps, c1, c2);
     TG_CHECK_LAUNCH();
     return TG_OK;
+}
+
+extern "C" tg_status tg_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
+                                  float beta1, float beta2, float eps, int32_t step, void* stream)
+{
+    return adam_launch(param, grad, m, v, n, 1, 1, lr, lr, beta1, beta2, eps, step, stream);
+}
+
+extern "C" tg_status tg_adam_step_rows(float* param, const float* grad, float* m, float* v, int64_t n, int32_t row,
+                                       int32_t head, float lr_head, float lr_tail, float beta1, float beta2,
+                                       float eps, int32_t step, void* stream)
+{
+    return adam_launch(param, grad, m, v, n, row, head, lr_head, lr_tail, beta1, beta2, eps, step, stream);
 }

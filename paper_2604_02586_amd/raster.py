@@ -3,8 +3,12 @@
 `Rasterize` is a torch.autograd.Function whose forward runs tg_preprocess
 (SH colours, log-scales, logit opacities) -> tg_bin_sort -> tg_raster_fwd and
 whose backward runs tg_raster_bwd -> tg_project_bwd; `L1Loss` wraps
-tg_l1_loss_grad; `Adam` wraps tg_adam_step.  Torch holds the memory and the
-autograd graph; every arithmetic step runs in the HIP kernels.
+tg_l1_loss_grad; `Loss3DGS` (the 3DGS objective (1 - lambda) L1 +
+lambda (1 - SSIM)) wraps tg_l1_loss_grad + tg_ssim_loss_grad; `Adam` wraps
+tg_adam_step / tg_adam_step_rows.  `refine` runs either L1 + one learning rate
+or the 3DGS recipe (objective, per-parameter learning rates, exponentially
+decayed position rate).  Torch holds the memory and the autograd graph; every
+arithmetic step runs in the HIP kernels.
 """
 from __future__ import annotations
 
@@ -16,7 +20,10 @@ from . import _lib
 from .api import BinTensors, GaussianTensors, SplatTensors, _ptr, bin_sort, bin_sort_ws_bytes, preprocess, stream_ptr
 from ._lib import check, lib
 
-__all__ = ["RasterContext", "Rasterize", "L1Loss", "Adam", "rasterize", "refine"]
+__all__ = ["RasterContext", "Rasterize", "L1Loss", "Loss3DGS", "Adam", "rasterize", "refine", "lr_3dgs",
+           "scene_extent"]
+
+DSSIM_LAMBDA = 0.2
 
 
 class RasterContext:
@@ -112,16 +119,58 @@ class L1Loss(torch.autograd.Function):
         return grad * gl, None
 
 
+class Loss3DGS(torch.autograd.Function):
+    """(1 - lam) mean|image - target| + lam (1 - mean SSIM(image, target)) over
+    images [..., H, W, 3]; the gradient comes from tg_l1_loss_grad followed by
+    tg_ssim_loss_grad (which adds the SSIM term's share)."""
+
+    @staticmethod
+    def forward(ctx, image, target, lam=DSSIM_LAMBDA):
+        image, target = image.contiguous(), target.contiguous()
+        H, W = image.shape[-3], image.shape[-2]
+        if image.shape[-1] != 3 or target.shape != image.shape:
+            raise ValueError("images must be [..., H, W, 3] of one shape")
+        n = image.numel()
+        B = n // (H * W * 3) if n else 0
+        grad = torch.empty_like(image)
+        sums = torch.zeros(2, dtype=torch.float32, device=image.device)
+        st = stream_ptr()
+        check("tg_l1_loss_grad", lib().tg_l1_loss_grad(_ptr(image), _ptr(target), n, ctypes.c_float((1 - lam) / max(n, 1)),
+                                                       _ptr(grad), _ptr(sums), st))
+        wsb = ctypes.c_size_t(0)
+        check("tg_ssim_loss_grad", lib().tg_ssim_loss_grad(None, None, B, H, W, ctypes.c_float(0), None, None, None,
+                                                           ctypes.byref(wsb), st))
+        ws = torch.empty(max(wsb.value, 1), dtype=torch.uint8, device=image.device)
+        check("tg_ssim_loss_grad", lib().tg_ssim_loss_grad(_ptr(image), _ptr(target), B, H, W,
+                                                           ctypes.c_float(-lam / max(n, 1)), _ptr(grad),
+                                                           _ptr(sums[1:]), _ptr(ws), ctypes.byref(wsb), st))
+        ctx.save_for_backward(grad)
+        # sums = [(1 - lam) L1, sum of the SSIM map]
+        return sums[0] + lam * (1 - sums[1] / max(n, 1))
+
+    @staticmethod
+    def backward(ctx, gl):
+        (grad,) = ctx.saved_tensors
+        return grad * gl, None, None
+
+
 def rasterize(means, quats, log_scales, logit_opacity, sh, rc):
     return Rasterize.apply(means, quats, log_scales, logit_opacity, sh, rc)
 
 
 class Adam:
-    """Adam over a list of tensors; the update runs in tg_adam_step."""
+    """Adam over a list of tensors; the update runs in tg_adam_step.
+
+    lr: one rate, or one entry per tensor, each a float or a tuple
+    (lr_head, lr_tail, row, head) for tg_adam_step_rows (the first `head` of
+    every `row` floats step with lr_head).  `lr` may be reassigned between
+    steps (learning-rate schedules)."""
 
     def __init__(self, params, lr=1e-3, betas=(0.9, 0.999), eps=1e-15):
         self.params = list(params)
-        self.lr = lr if isinstance(lr, (list, tuple)) else [lr] * len(self.params)
+        self.lr = list(lr) if isinstance(lr, (list, tuple)) else [lr] * len(self.params)
+        if len(self.lr) != len(self.params):
+            raise ValueError("one learning rate per tensor")
         self.b1, self.b2 = betas
         self.eps = eps
         self.m = [torch.zeros_like(p) for p in self.params]
@@ -130,27 +179,71 @@ class Adam:
 
     def step(self):
         self.t += 1
+        f = ctypes.c_float
         for p, m, v, lr in zip(self.params, self.m, self.v, self.lr):
             if p.grad is None:
                 continue
             g = p.grad.contiguous()
-            check("tg_adam_step", lib().tg_adam_step(_ptr(p.data), _ptr(g), _ptr(m), _ptr(v), p.numel(),
-                                                     ctypes.c_float(lr), ctypes.c_float(self.b1),
-                                                     ctypes.c_float(self.b2), ctypes.c_float(self.eps), self.t,
-                                                     stream_ptr()))
+            if isinstance(lr, tuple):
+                lr_head, lr_tail, row, head = lr
+                check("tg_adam_step_rows", lib().tg_adam_step_rows(
+                    _ptr(p.data), _ptr(g), _ptr(m), _ptr(v), p.numel(), row, head, f(lr_head), f(lr_tail),
+                    f(self.b1), f(self.b2), f(self.eps), self.t, stream_ptr()))
+            else:
+                check("tg_adam_step", lib().tg_adam_step(_ptr(p.data), _ptr(g), _ptr(m), _ptr(v), p.numel(), f(lr),
+                                                         f(self.b1), f(self.b2), f(self.eps), self.t, stream_ptr()))
 
     def zero_grad(self):
         for p in self.params:
             p.grad = None
 
 
-def refine(params, rc: RasterContext, targets, iters=100, lr=1e-3, log_every=0):
-    """L1 + Adam refinement of (means, quats, log_scales, logit_opacity, sh)."""
-    opt = Adam(params, lr=lr)
+def scene_extent(cams):
+    """3DGS's spatial learning-rate scale: 1.1 x the largest distance of a
+    camera centre from the mean camera centre."""
+    import numpy as np
+    centres = np.stack([-np.asarray(c.R, np.float64).reshape(3, 3).T @ np.asarray(c.t, np.float64) for c in cams])
+    d = np.linalg.norm(centres - centres.mean(0), axis=1).max()
+    return 1.1 * float(d)
+
+
+# 3DGS learning rates: position (scaled by the scene extent, decayed
+# exponentially from init to final over max_steps), DC colour, higher SH bands
+# (DC / 20), opacity, scale, rotation
+LR_3DGS = dict(position_init=1.6e-4, position_final=1.6e-6, position_max_steps=30000, feature=2.5e-3,
+               feature_rest_div=20.0, opacity=0.05, scaling=5e-3, rotation=1e-3)
+
+
+def lr_3dgs(step, extent, sh_coeffs, cfg=LR_3DGS):
+    """Per-tensor rates for (means, quats, log_scales, logit_opacity, sh) at
+    optimiser step `step` (0-based)."""
+    import math
+    t = min(max(step / cfg["position_max_steps"], 0.0), 1.0)
+    pos = math.exp((1 - t) * math.log(cfg["position_init"]) + t * math.log(cfg["position_final"])) * extent
+    f = cfg["feature"]
+    sh = (f, f / cfg["feature_rest_div"], 3 * sh_coeffs, 3)
+    return [pos, cfg["rotation"], cfg["scaling"], cfg["opacity"], sh]
+
+
+def refine(params, rc: RasterContext, targets, iters=100, lr=1e-3, log_every=0, recipe="l1", extent=None):
+    """Refinement of (means, quats, log_scales, logit_opacity, sh) against
+    targets [V,H,W,3].  recipe "l1": L1 + Adam at one rate `lr`; recipe
+    "3dgs": the 3DGS objective and per-parameter rates (`lr` unused; extent
+    defaults to scene_extent of the context's cameras)."""
+    if recipe not in ("l1", "3dgs"):
+        raise ValueError(f"unknown recipe {recipe!r}")
+    if recipe == "3dgs":
+        extent = scene_extent(rc.cams) if extent is None else extent
+        K = params[4].shape[1]
+        opt = Adam(params, lr=lr_3dgs(0, extent, K))
+    else:
+        opt = Adam(params, lr=lr)
     losses = []
     for it in range(iters):
+        if recipe == "3dgs":
+            opt.lr = lr_3dgs(it, extent, K)
         img = rasterize(*params, rc)
-        loss = L1Loss.apply(img, targets)
+        loss = Loss3DGS.apply(img, targets) if recipe == "3dgs" else L1Loss.apply(img, targets)
         opt.zero_grad()
         loss.backward()
         opt.step()
