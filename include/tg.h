@@ -188,9 +188,10 @@ tg_status tg_preprocess(const tg_gaussians* g, int64_t N, const tg_camera* cams,
  *
  * Step 1: per view, a device LSD radix sort of the N depth keys (ties by
  * Gaussian id) gives bins->order.  Step 2: every non-culled Gaussian emits a
- * key (coarse bin | depth rank) for each coarse bin (2^coarse_shift tiles a
- * side) its tile rectangle meets; a device radix sort of those keys gives,
- * per bin, the Gaussians in depth order.  The renderer reads a tile's list as
+ * key (coarse bin | Gaussian id) for each coarse bin (2^coarse_shift tiles a
+ * side) its tile rectangle meets, in (view, depth rank) order; a stable device
+ * radix sort of those keys over the bin bits gives, per bin, the Gaussians in
+ * depth order.  The renderer reads a tile's list as
  * the entries of its bin whose rectangle contains the tile, which is exactly
  * the depth-ordered per-tile list.
  *
@@ -199,7 +200,7 @@ tg_status tg_preprocess(const tg_gaussians* g, int64_t N, const tg_camera* cams,
  * device count exceeds it, *bins->overflow is set, no list is written and the
  * later stages of the frame do nothing (the caller re-sizes and re-runs).
  * Errors: TG_ERR_WORKSPACE if *ws_bytes is smaller than required;
- *         TG_ERR_UNSUPPORTED if bin and rank bits exceed 32 at every
+ *         TG_ERR_UNSUPPORTED if bin and id bits exceed 32 at every
  *         coarse size.
  */
 tg_status tg_bin_sort(const tg_splats* s, int64_t N, const tg_camera* cams, int32_t V,

@@ -3,12 +3,16 @@
 //
 // Design for CDNA4: instead of sorting one 64-bit (tile | depth) key per
 // (tile, Gaussian) pair -- about 16M pairs per 1080p view at 1M Gaussians --
-// we (1) radix-sort the N depth keys of each view once, giving every Gaussian
-// a depth rank, then (2) emit one 32-bit key (coarse bin | depth rank) per
-// (coarse bin, Gaussian) pair, with coarse bins of 8x8 tiles, and radix-sort
-// those (about 2M pairs per view).  The rasteriser streams its coarse bin's
-// list in depth order and keeps the entries whose tile rectangle contains its
-// tile, which is exactly the per-tile depth-ordered list.
+// we (1) radix-sort the N depth keys of each view once, then (2) emit one
+// 32-bit key (coarse bin | Gaussian id) per (coarse bin, Gaussian) pair, with
+// coarse bins of 8x8 tiles, written in (view, depth rank) order: a count
+// pass, a scan of the per-block counts, and a write pass that places every
+// block's pairs in rank order.  (3) A stable radix sort over the coarse-bin
+// bits alone (two 8-bit passes for up to 65536 bins) then leaves each bin's
+// ids in depth order, ties by id, so the low bits never need sorting.  The
+// rasteriser streams its coarse bin's list in depth order and keeps the
+// entries whose tile rectangle contains its tile, which is exactly the
+// per-tile depth-ordered list.
 //
 // The radix sort (sort.hip) is LSD with 8-bit digits and stable ranks.
 #include "tg_internal.h"
@@ -16,62 +20,135 @@
 namespace {
 
 // ---- coarse-bin key emission ---------------------------------------------
-// Each thread takes EMIT_ITEMS depth ranks (strided by the block size, so the
-// order/rect reads stay coalesced), the block reserves its output range with
-// one atomic on the pair counter, and each thread writes its keys into its
-// own sub-range.  Key order is irrelevant here: the keys are sorted next.
+// A block takes EMIT_RANKS consecutive depth ranks of one view.  Global
+// loads and stores are item-major (rank = block base + item * 256 + thread,
+// coalesced); the write pass transposes through LDS so that thread t owns the
+// EMIT_ITEMS consecutive ranks [8t, 8t + 8), making rank order (thread, item)
+// order and one block-wide exclusive scan enough to place every pair.
 constexpr int EMIT_ITEMS = 8;
+constexpr int EMIT_RANKS = 256 * EMIT_ITEMS;
+constexpr int EMIT_STAGE = EMIT_RANKS * 3;   // keys staged in the write pass's 24 KB of LDS
 
-__global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ order, const ushort4* __restrict__ rect,
-                                              int64_t N, int V, GridPack gp, int cshift, int rbits,
-                                              uint32_t* __restrict__ keys, int64_t capacity,
-                                              unsigned long long* __restrict__ n_pairs, int32_t* __restrict__ overflow)
-{
-    __shared__ unsigned long long gbase;
-    __shared__ uint32_t wsum[4];
-    const int v = blockIdx.y;
+// Coarse-bin rectangle of Gaussian g's tile rectangle (empty when culled).
+__device__ __forceinline__ ushort4 coarse_rect(const ushort4* __restrict__ rect, int64_t vN, uint32_t g, int64_t N,
+                                               int cshift, uint32_t& cnt) {
+    const ushort4 r = g < (uint64_t)N ? rect[vN + g] : make_ushort4(0, 0, 0, 0);
+    if (!(r.z > r.x && r.w > r.y)) return make_ushort4(0, 0, 0, 0);
+    const ushort4 c = make_ushort4((unsigned short)(r.x >> cshift), (unsigned short)(r.y >> cshift),
+                                   (unsigned short)(((r.z - 1) >> cshift) + 1),
+                                   (unsigned short)(((r.w - 1) >> cshift) + 1));
+    cnt += (uint32_t)((c.z - c.x) * (c.w - c.y));
+    return c;
+}
+
+// Block sum and exclusive prefix of one u32 per thread (256 threads).
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t* wsum, uint32_t& total) {
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const int64_t base = (int64_t)blockIdx.x * (256 * EMIT_ITEMS);
-    ushort4 cr[EMIT_ITEMS];
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int it = 0; it < EMIT_ITEMS; ++it) {
-        const int64_t k = base + it * 256 + t;
-        ushort4 c = make_ushort4(0, 0, 0, 0);
-        if (k < N) {
-            const uint32_t g = order[(int64_t)v * N + k];
-            const ushort4 r = g < (uint64_t)N ? rect[(int64_t)v * N + g] : make_ushort4(0, 0, 0, 0);
-            if (r.z > r.x && r.w > r.y) {
-                c = make_ushort4((unsigned short)(r.x >> cshift), (unsigned short)(r.y >> cshift),
-                                 (unsigned short)(((r.z - 1) >> cshift) + 1), (unsigned short)(((r.w - 1) >> cshift) + 1));
-                cnt += (uint32_t)((c.z - c.x) * (c.w - c.y));
-            }
-        }
-        cr[it] = c;
-    }
-    const uint32_t inc = wave_scan_add_u32(cnt);
+    const uint32_t inc = wave_scan_add_u32(x);
     if (l == 63) wsum[w] = inc;
     __syncthreads();
-    if (t == 0) {
-        uint32_t s = 0;
-        for (int i = 0; i < 4; ++i) { uint32_t c = wsum[i]; wsum[i] = s; s += c; }
-        gbase = s ? atomicAdd(n_pairs, (unsigned long long)s) : 0ull;
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t c = wsum[i];
+        before += i < w ? c : 0u;
+        total += c;
+    }
+    return before + inc - x;
+}
+
+// Count pass: gathers each rank's tile rectangle (the one random access of
+// the emission), stores its coarse rectangle in rank order for the write
+// pass, and records the block's pair count.
+__global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__ order, const ushort4* __restrict__ rect,
+                                                    int64_t N, int cshift, int nblk, ushort4* __restrict__ crs,
+                                                    uint32_t* __restrict__ counts,
+                                                    unsigned long long* __restrict__ n_pairs)
+{
+    __shared__ uint32_t wsum[4];
+    const int v = blockIdx.y;
+    const int64_t vN = (int64_t)v * N;
+    const int64_t base = (int64_t)blockIdx.x * EMIT_RANKS + threadIdx.x;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < EMIT_ITEMS; ++i) {
+        const int64_t k = base + i * 256;
+        if (k < N) crs[vN + k] = coarse_rect(rect, vN, order[vN + k], N, cshift, cnt);
+    }
+    uint32_t total;
+    (void)block_excl_scan_u32(cnt, wsum, total);
+    if (threadIdx.x == 0) {
+        counts[(int64_t)v * nblk + blockIdx.x] = total;
+        if (total) atomicAdd(n_pairs, (unsigned long long)total);
+    }
+}
+
+// Write pass: the same ranks, coarse rectangles read back in rank order.
+__global__ void __launch_bounds__(256) k_emit_write(const uint32_t* __restrict__ order, const ushort4* __restrict__ crs,
+                                                    int64_t N, GridPack gp, int rbits, int nblk,
+                                                    const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
+                                                    int64_t capacity, const int32_t* __restrict__ overflow)
+{
+    // 24 KB: ids then coarse rectangles, rank-major; reused to stage keys
+    __shared__ uint4 lds[EMIT_RANKS * 12 / 16];
+    __shared__ uint32_t wsum[4];
+    uint4* sg4 = lds;
+    ushort4* sc = (ushort4*)(lds + EMIT_RANKS / 4);
+    uint32_t* stage = (uint32_t*)lds;
+    if (*overflow) return;   // block-uniform: the caller re-sizes and retries
+    const int v = blockIdx.y, t = threadIdx.x;
+    const int64_t vN = (int64_t)v * N;
+    const int64_t base = (int64_t)blockIdx.x * EMIT_RANKS;
+    uint32_t* sg = (uint32_t*)sg4;
+#pragma unroll
+    for (int i = 0; i < EMIT_ITEMS; ++i) {
+        const int j = i * 256 + t;
+        const bool in = base + j < N;
+        sg[j] = in ? order[vN + base + j] : 0u;
+        sc[j] = in ? crs[vN + base + j] : make_ushort4(0, 0, 0, 0);
     }
     __syncthreads();
-    if (cnt == 0) return;
-    unsigned long long pos = gbase + wsum[w] + inc - cnt;
-    if (pos + cnt > (unsigned long long)capacity) {
-        *overflow = 1;
-        return;
+    uint32_t gid[EMIT_ITEMS];
+    ushort4 cr[EMIT_ITEMS];
+    {
+        const uint4 a = sg4[2 * t], b = sg4[2 * t + 1];
+        gid[0] = a.x; gid[1] = a.y; gid[2] = a.z; gid[3] = a.w;
+        gid[4] = b.x; gid[5] = b.y; gid[6] = b.z; gid[7] = b.w;
     }
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < EMIT_ITEMS; ++i) {
+        cr[i] = sc[EMIT_ITEMS * t + i];
+        cnt += (uint32_t)((cr[i].z - cr[i].x) * (cr[i].w - cr[i].y));
+    }
+    uint32_t total;
+    const uint32_t before = block_excl_scan_u32(cnt, wsum, total);
+    const uint64_t off = (uint64_t)offsets[(int64_t)v * nblk + blockIdx.x];
+    if (off + total > (uint64_t)capacity) return;   // unreachable without overflow
     const int cw = gp.cx[v];
     const uint32_t cbase = (uint32_t)gp.cell_off[v];
+    if (total <= EMIT_STAGE) {
+        // stage the block's keys in LDS (its ids and rectangles are in
+        // registers now), then write them out contiguously
+        __syncthreads();
+        uint32_t pos = before;
 #pragma unroll
-    for (int it = 0; it < EMIT_ITEMS; ++it) {
-        const ushort4 c = cr[it];
-        const uint32_t k = (uint32_t)(base + it * 256 + t);
+        for (int i = 0; i < EMIT_ITEMS; ++i) {
+            const ushort4 c = cr[i];
+            for (int y = c.y; y < c.w; ++y)
+                for (int x = c.x; x < c.z; ++x) stage[pos++] = ((cbase + (uint32_t)(y * cw + x)) << rbits) | gid[i];
+        }
+        __syncthreads();
+        for (uint32_t j = t; j < total; j += 256) keys[off + j] = stage[j];
+        return;
+    }
+    uint64_t pos = off + before;
+#pragma unroll
+    for (int i = 0; i < EMIT_ITEMS; ++i) {
+        const ushort4 c = cr[i];
         for (int y = c.y; y < c.w; ++y)
-            for (int x = c.x; x < c.z; ++x) keys[pos++] = ((cbase + (uint32_t)(y * cw + x)) << rbits) | k;
+            for (int x = c.x; x < c.z; ++x) keys[pos++] = ((cbase + (uint32_t)(y * cw + x)) << rbits) | gid[i];
     }
 }
 
@@ -87,33 +164,39 @@ __global__ void k_check_overflow(const unsigned long long* n_pairs, int64_t capa
     if (*n_pairs > (unsigned long long)capacity) *overflow = 1;
 }
 
-__device__ __forceinline__ int view_of_cell(const GridPack& gp, int V, uint32_t cell) {
-    int lo = 0, hi = V - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if ((uint32_t)gp.cell_off[mid] <= cell) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
+// Ids and bin ranges from the sorted keys; each thread takes four
+// consecutive keys (one 16-byte load from the 256-byte aligned workspace).
 __global__ void __launch_bounds__(256) k_cell_finalize(const uint32_t* __restrict__ skeys,
                                                        const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                       int rbits, const uint32_t* __restrict__ order, int64_t N,
-                                                       GridPack gp, int V, uint32_t* __restrict__ cell_ids,
+                                                       int rbits, int64_t N, uint32_t* __restrict__ cell_ids,
                                                        uint2* __restrict__ ranges, int64_t ncell)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     int64_t n = *n_pairs;
     if (n > capacity) n = 0;
-    if (i >= n) return;
-    const uint32_t key = skeys[i];
-    const uint32_t cell = key >> rbits;
-    const uint32_t rank = key & ((1u << rbits) - 1u);
-    if (cell >= (uint64_t)ncell || rank >= (uint64_t)N) return;  // consistent keys never hit this
-    const int v = view_of_cell(gp, V, cell);
-    cell_ids[i] = order[(int64_t)v * N + rank];
-    if (i == 0 || (skeys[i - 1] >> rbits) != cell) ranges[cell].x = (uint32_t)i;
-    if (i == n - 1 || (skeys[i + 1] >> rbits) != cell) ranges[cell].y = (uint32_t)(i + 1);
+    if (i0 >= n) return;
+    uint32_t k[6];   // k[0] = key i0 - 1, k[1..4] = keys i0..i0+3, k[5] = key i0 + 4
+    if (i0 + 4 <= n) {
+        const uint4 q = *(const uint4*)(skeys + i0);
+        k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[1 + j] = i0 + j < n ? skeys[i0 + j] : 0u;
+    }
+    k[0] = i0 > 0 ? skeys[i0 - 1] : 0u;
+    k[5] = i0 + 4 < n ? skeys[i0 + 4] : 0u;
+    const uint32_t mask = (1u << rbits) - 1u;
+#pragma unroll
+    for (int j = 1; j <= 4; ++j) {
+        const int64_t i = i0 + j - 1;
+        if (i >= n) break;
+        const uint32_t cell = k[j] >> rbits;
+        const uint32_t id = k[j] & mask;
+        if (cell >= (uint64_t)ncell || id >= (uint64_t)N) continue;  // consistent keys never hit this
+        cell_ids[i] = id;
+        if (i == 0 || (k[j - 1] >> rbits) != cell) ranges[cell].x = (uint32_t)i;
+        if (i == n - 1 || (k[j + 1] >> rbits) != cell) ranges[cell].y = (uint32_t)(i + 1);
+    }
 }
 
 inline int bitlen(uint64_t x) {  // number of bits to represent x-1 values [0, x)
@@ -139,7 +222,7 @@ tg_status plan_bins(const tg_camera* cams, int V, int64_t N, const tg_params* p,
         if (cs > 12) return TG_ERR_UNSUPPORTED;
     }
     bp->cshift = cs;
-    bp->passes = (bp->rbits + bp->cbits + 7) / 8;
+    bp->passes = (bp->cbits + 7) / 8;   // the id bits are already in order
     return TG_OK;
 }
 
@@ -147,6 +230,7 @@ tg_status plan_bins(const tg_camera* cams, int V, int64_t N, const tg_params* p,
 struct BinWs {
     uint32_t *dk_a, *dv_a, *dk_b, *dv_b;   // depth sort ping-pong [V*N]
     uint32_t *pk_a, *pk_b;                  // pair keys [capacity]
+    uint32_t* counts;                       // per emission block pair counts [V*nblk]
     void* scratch;
     size_t bytes;
 };
@@ -158,8 +242,12 @@ BinWs layout_ws(void* ws, int64_t N, int V, int64_t capacity) {
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
     size_t vn = (size_t)V * (size_t)N * 4;
+    // dk_a and dv_a are adjacent: after the depth sort the emission reuses
+    // them as one [V*N] array of 8-byte coarse rectangles
     size_t a = take(vn), b = take(vn), c = take(vn), d = take(vn);
     size_t e = take((size_t)capacity * 4), f = take((size_t)capacity * 4);
+    const int64_t ncount = (int64_t)V * ((N + EMIT_RANKS - 1) / EMIT_RANKS);
+    size_t h = take((size_t)ncount * 4);
     size_t sc = tg_sort_scratch_bytes(N, V);
     size_t sc2 = tg_sort_scratch_bytes(capacity, 1);
     size_t g = take(sc > sc2 ? sc : sc2);
@@ -170,6 +258,7 @@ BinWs layout_ws(void* ws, int64_t N, int V, int64_t capacity) {
     L.dv_b = (uint32_t*)(base + d);
     L.pk_a = (uint32_t*)(base + e);
     L.pk_b = (uint32_t*)(base + f);
+    L.counts = (uint32_t*)(base + h);
     L.scratch = base + g;
     L.bytes = o;
     return L;
@@ -223,31 +312,30 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
     st = tg_radix_sort(sp->key, nullptr, L.dk_a, L.dv_a, L.dk_b, L.dv_b, nullptr, bins->order, N, V, nullptr, 0, 4,
                     L.scratch, s);
     if (st != TG_OK) return st;
-    // (2) emit (coarse bin | depth rank) keys
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((N + 256 * EMIT_ITEMS - 1) / (256 * EMIT_ITEMS)), V), dim3(256), 0, s,
-                       bins->order,
-                       (const ushort4*)sp->rect, N, V, bp.gp, bp.cshift, bp.rbits, L.pk_a, bins->capacity,
-                       (unsigned long long*)bins->n_pairs, bins->overflow);
+    // (2) emit (coarse bin | Gaussian id) keys in (view, depth rank) order
+    const int nblk = (int)((N + EMIT_RANKS - 1) / EMIT_RANKS);
+    // coarse rectangles in rank order reuse the depth sort's first ping-pong
+    // pair (8 B per (view, Gaussian) over two contiguous 4 B arrays)
+    ushort4* crs = (ushort4*)L.dk_a;
+    hipLaunchKernelGGL(k_emit_count, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order, (const ushort4*)sp->rect, N,
+                       bp.cshift, nblk, crs, L.counts, (unsigned long long*)bins->n_pairs);
     hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,
                        bins->capacity, bins->overflow);
+    // with no overflow the total fits the capacity (< 2^32), so u32 offsets
+    tg_exclusive_scan_u32(L.counts, (int64_t)V * nblk, (uint32_t*)L.scratch, s);
+    hipLaunchKernelGGL(k_emit_write, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order, (const ushort4*)crs, N,
+                       bp.gp, bp.rbits, nblk, L.counts, L.pk_a, bins->capacity, bins->overflow);
     TG_CHECK_LAUNCH();
     if (bins->capacity == 0) return TG_OK;
-    // (3) sort pair keys over their used bits; final keys land in pk_b or pk_a
-    uint32_t* final_keys = L.pk_b;
-    uint32_t* other = L.pk_a;
-    // ping-pong: pass p writes (p odd ? kb : ka) except the last -> kfinal.
-    // Input lives in pk_a, so use ka = pk_b, kb = pk_a, final = whichever the
-    // last pass would otherwise overwrite safely.
-    final_keys = (bp.passes & 1) ? L.pk_b : L.pk_a;
-    other = (bp.passes & 1) ? L.pk_a : L.pk_b;
-    (void)other;
+    // (3) stable sort of the pair keys over the coarse-bin bits
+    uint32_t* final_keys = (bp.passes & 1) ? L.pk_b : L.pk_a;
     st = tg_radix_sort(L.pk_a, nullptr, L.pk_b, nullptr, L.pk_a, nullptr, final_keys, nullptr, bins->capacity, 1,
-                    bins->n_pairs, 0, bp.passes, L.scratch, s);
+                       bins->n_pairs, bp.rbits, bp.passes, L.scratch, s);
     if (st != TG_OK) return st;
     // (4) ranges and ids
-    hipLaunchKernelGGL(k_cell_finalize, dim3((unsigned)((bins->capacity + 255) / 256)), dim3(256), 0, s, final_keys,
-                       bins->n_pairs, bins->capacity, bp.rbits, bins->order, N, bp.gp, V, bins->cell_ids,
-                       (uint2*)bins->cell_ranges, bp.ncell);
+    hipLaunchKernelGGL(k_cell_finalize, dim3((unsigned)((bins->capacity + 1023) / 1024)), dim3(256), 0, s, final_keys,
+                       bins->n_pairs, bins->capacity, bp.rbits, N, bins->cell_ids, (uint2*)bins->cell_ranges,
+                       bp.ncell);
     TG_CHECK_LAUNCH();
     return TG_OK;
 }

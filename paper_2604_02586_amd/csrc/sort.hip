@@ -23,6 +23,28 @@ __device__ __forceinline__ int64_t seg_count(int64_t seg_len, const int64_t* dev
     return n > seg_len ? 0 : n;
 }
 
+// Adds one key's digit to the wave's sub-histogram.  FEW: the digit takes
+// few distinct values (the top digit of depth keys or of the bin bits), so
+// equal digits are first counted across the wave and the lowest lane of each
+// group adds the count (one LDS atomic per distinct digit instead of a chain
+// of colliding ones).
+template <bool FEW>
+__device__ __forceinline__ void hist_add(uint32_t* h, uint32_t d, bool active) {
+    if (!FEW) {
+        if (active) atomicAdd(&h[d], 1u);
+        return;
+    }
+    uint64_t left = ballot64(active);
+    while (left) {
+        const int lead = __ffsll((unsigned long long)left) - 1;
+        const uint32_t d0 = (uint32_t)__shfl((int)d, lead, 64);
+        const uint64_t same = ballot64(active && d == d0);
+        if ((int)(threadIdx.x & 63) == lead) atomicAdd(&h[d0], (uint32_t)__popcll(same));
+        left &= ~same;
+    }
+}
+
+template <bool FEW>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __restrict__ keys, int64_t seg_len,
                                                              const int64_t* __restrict__ dev_count, int shift,
                                                              uint32_t* __restrict__ ghist, int nblk)
@@ -42,16 +64,17 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __r
 #pragma unroll
         for (int r = 0; r < SORT_ITEMS / 4; ++r) {
             const uint4 k = k4[r * SORT_THREADS + t];
-            atomicAdd(&h[w][(k.x >> shift) & 255u], 1u);
-            atomicAdd(&h[w][(k.y >> shift) & 255u], 1u);
-            atomicAdd(&h[w][(k.z >> shift) & 255u], 1u);
-            atomicAdd(&h[w][(k.w >> shift) & 255u], 1u);
+            hist_add<FEW>(h[w], (k.x >> shift) & 255u, true);
+            hist_add<FEW>(h[w], (k.y >> shift) & 255u, true);
+            hist_add<FEW>(h[w], (k.z >> shift) & 255u, true);
+            hist_add<FEW>(h[w], (k.w >> shift) & 255u, true);
         }
     } else if (base < n) {
 #pragma unroll 4
         for (int r = 0; r < SORT_ITEMS; ++r) {
             int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
-            if (idx < n) atomicAdd(&h[w][(kp[idx] >> shift) & 255u], 1u);
+            const bool in = idx < n;
+            hist_add<FEW>(h[w], in ? (kp[idx] >> shift) & 255u : 0u, in);
         }
     }
     __syncthreads();
@@ -269,8 +292,14 @@ tg_status tg_radix_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, 
         uint32_t* ov = last ? vfinal : ((p & 1) ? vb : va);
         if (!last && !ok) return TG_ERR_INVALID_ARG;
         const int shift = bit0 + 8 * p;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, seg_len, dev_count, shift,
-                           hist, nblk);
+        // the top digit of a sort (the high exponent bits of depth keys, or
+        // the high bits of the bin numbers) takes few distinct values
+        if (last)
+            hipLaunchKernelGGL(k_radix_hist<true>, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, seg_len,
+                               dev_count, shift, hist, nblk);
+        else
+            hipLaunchKernelGGL(k_radix_hist<false>, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, seg_len,
+                               dev_count, shift, hist, nblk);
         hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
         hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(SCAN_THREADS), 0, s, sums, nchunk);
         hipLaunchKernelGGL(k_scan_down, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
