@@ -7,17 +7,18 @@
 // reduction:
 //
 //  * one wave64 owns one 16x16 tile; its 256 pixels are wave-uniform scalars
-//    (the pixel's transmittance, track and flags live in 4 VGPRs per quantity
-//    and are read with v_readlane), visited with s_ff1 over an alive mask so
-//    finished pixels cost nothing;
+//    (the transmittance in LDS, the flags in 4 VGPRs read with v_readlane,
+//    the track fetched with a scalar load when the pixel contributes),
+//    visited with s_ff1 over an alive mask so finished pixels cost nothing;
 //  * the 64 lanes hold 64 consecutive Gaussians of the tile's depth-ordered
 //    list; for a pixel, every lane evaluates its Gaussian's alpha, and the
 //    transmittance in front of each lane is an exclusive product scan across
 //    the wave (6 DPP row_shr/row_bcast steps), so termination is a ballot and
 //    first-set-bit;
-//  * each lane keeps its Gaussian's 15 running sums in registers over all
-//    pixels of the tile, then adds them to HBM with one set of FP32 atomics
-//    per (tile, Gaussian) -- no shuffle reduction, no LDS merge.
+//  * each lane keeps its Gaussian's running sums in registers over all
+//    pixels of the tile (per-row partial sums folded into the y terms at the
+//    end of each row), then adds the 15-entry record to HBM with one set of
+//    FP32 atomics per (tile, Gaussian) -- no shuffle reduction, no LDS merge.
 //
 // The tile's list is read from its coarse bin (8x8 tiles) in depth order and
 // filtered by the tile rectangle with a ballot/popcount compaction into a
@@ -36,6 +37,7 @@
 namespace {
 
 constexpr int QCAP = 128;
+constexpr int SA_RECS = 16;   // records per round of the flush
 constexpr float LOG2E = 1.4426950408889634f;
 
 // One slot of a launch: a Gaussian set (splats + bins of one frame set)
@@ -66,34 +68,37 @@ struct BatchArgs {
     unsigned long long* stats;
 };
 
-// Running sums of one frame for the lane's Gaussian (Eq. 4 record order).
+// Running sums of one frame for the lane's Gaussian.  With u = (ux, uy) the
+// pixel's offset from the splat centre, the record of Eq. 4 needs sums of w,
+// w u, w u u^T, w d, w u d^T.  Within a pixel row uy is constant, so the
+// per-pixel work keeps only sums over the row's pixels (R0 = sum w,
+// R1 = sum w c, RDX/RDY = sum w d), folded into the uy terms once per row.
+// The x offsets are kept as ux = ax + c with c a small integer column offset
+// from a per-lane anchor ax (|ax| <= 1/2 when the centre's column lies in the
+// tile), so sum w ux^2 = C2 + 2 ax C1 + ax^2 W adds terms of one sign or of
+// bounded ratio, never a large cancellation.
 struct Sums {
-    float w, ux, uy, xx, xy, yy, dx, dy, xdx, xdy, ydx, ydy, n, sn, sa;
+    float W, C1, C2, N, DX, DY, CDX, CDY, UY, XY, YY, YDX, YDY, sn, sa;   // tile totals
+    float R0, R1, RDX, RDY;                                               // current row
 };
 
 __device__ __forceinline__ void sums_zero(Sums& s) {
-    s.w = s.ux = s.uy = s.xx = s.xy = s.yy = 0.f;
-    s.dx = s.dy = s.xdx = s.xdy = s.ydx = s.ydy = 0.f;
-    s.n = s.sn = s.sa = 0.f;
+    s.W = s.C1 = s.C2 = s.N = s.DX = s.DY = s.CDX = s.CDY = 0.f;
+    s.UY = s.XY = s.YY = s.YDX = s.YDY = s.sn = s.sa = 0.f;
+    s.R0 = s.R1 = s.RDX = s.RDY = 0.f;
 }
 
-// Adds one pixel's weighted record: w, w u, w u u^T (shared by the frames)
-// and the frame's track d.
-__device__ __forceinline__ void sums_add(Sums& s, float wgt, float wx, float wy, float wxx, float wxy, float wyy,
-                                         float tdx, float tdy, bool stat, float al) {
-    s.w += wgt;
-    s.ux += wx;
-    s.uy += wy;
-    s.xx += wxx;
-    s.xy += wxy;
-    s.yy += wyy;
-    s.dx += wgt * tdx;
-    s.dy += wgt * tdy;
-    s.xdx += wx * tdx;
-    s.xdy += wx * tdy;
-    s.ydx += wy * tdx;
-    s.ydy += wy * tdy;
-    s.n += 1.0f;
+// One pixel: weight w, w c (c = column offset from the anchor), track d.
+__device__ __forceinline__ void sums_add(Sums& s, float wgt, float wc, float cpp, float tdx, float tdy, bool stat,
+                                         float al) {
+    s.R0 += wgt;
+    s.R1 += wc;
+    s.C2 = fmaf(wc, cpp, s.C2);
+    s.RDX = fmaf(wgt, tdx, s.RDX);
+    s.RDY = fmaf(wgt, tdy, s.RDY);
+    s.CDX = fmaf(wc, tdx, s.CDX);
+    s.CDY = fmaf(wc, tdy, s.CDY);
+    s.N += 1.0f;
     if (stat) {
         // static pixels are rare: a real (wave-uniform) branch, kept from
         // being turned into selects that would cost every pixel
@@ -103,6 +108,20 @@ __device__ __forceinline__ void sums_add(Sums& s, float wgt, float wx, float wy,
     }
 }
 
+// End of a pixel row at vertical offset uy.
+__device__ __forceinline__ void sums_fold_row(Sums& s, float uy, float ax) {
+    s.W += s.R0;
+    s.C1 += s.R1;
+    s.DX += s.RDX;
+    s.DY += s.RDY;
+    s.UY = fmaf(uy, s.R0, s.UY);
+    s.XY = fmaf(uy, fmaf(ax, s.R0, s.R1), s.XY);
+    s.YY = fmaf(uy * uy, s.R0, s.YY);
+    s.YDX = fmaf(uy, s.RDX, s.YDX);
+    s.YDY = fmaf(uy, s.RDY, s.YDY);
+    s.R0 = s.R1 = s.RDX = s.RDY = 0.f;
+}
+
 // One wave (64 threads) per workgroup and per 16x16 tile, so tiles of very
 // different work never hold each other's resources.  FM: frames per slot the
 // launch is compiled for (a slot may carry fewer).
@@ -110,13 +129,13 @@ template <int FM, bool STATS>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FM == 1 ? 7 : 1, 8)))
 k_accumulate(BatchArgs a)
 {
-    // 3.7 KB of LDS per wave: queue of filtered list entries (ids), column
-    // offsets as floats, per-pixel transmittance and the atomics' transpose
-    // buffer
+    // 5.7 KB of LDS per wave (7 waves per SIMD fit): queue of filtered list
+    // entries (ids), per-pixel records (transmittance, and for one frame the
+    // track; a row of them is held in registers while the row is visited)
+    // and the atomics' transpose buffer
     __shared__ uint32_t qi[QCAP];
-    __shared__ float CF[16];        // column offsets 0..15 as floats
-    __shared__ float T_[256];
-    __shared__ float SA[32 * 17];   // 32 records in flight to the atomics
+    __shared__ float4 PR[256];      // T, track x, track y, unused
+    __shared__ float SA[SA_RECS * 17];
     // XCD-aware remap: hardware places workgroup b on XCD (b mod 8); give
     // each XCD a contiguous range of tiles (its L2 then holds those bins).
     const int64_t b = blockIdx.x;
@@ -149,14 +168,15 @@ k_accumulate(BatchArgs a)
     const int px0 = tx * TG_TILE, py0 = ty * TG_TILE;
     const int64_t row_base = (int64_t)v * H;
     const int lane = threadIdx.x;
-    if (lane < 16) CF[lane] = (float)lane;
 
     // pixel state: pixel j = g*64 + lane -> (px0 + (j&15), py0 + (j>>4));
     // flags of pixel j: bit f = track visible in frame f, bit 8+f = static
     // in frame f
     uint64_t alive[4];
     uint32_t flg[4];
-    float dxg[FM][4], dyg[FM][4];   // track of pixel g*64 + lane per frame
+    // tracks of pixel g*64 + lane per frame (in registers for several frames,
+    // in the LDS records for one)
+    float dxg[FM == 1 ? 1 : FM][4], dyg[FM == 1 ? 1 : FM][4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int j = g * 64 + lane;
@@ -181,10 +201,14 @@ k_accumulate(BatchArgs a)
                 fl |= (vv ? 1u : 0u) << f;
                 fl |= (s2 < a.static2 ? 1u : 0u) << (8 + f);
             }
-            dxg[f][g] = ddx;
-            dyg[f][g] = ddy;
+            if constexpr (FM == 1) {
+                PR[j] = make_float4(1.0f, ddx, ddy, 0.0f);
+            } else {
+                dxg[f][g] = ddx;
+                dyg[f][g] = ddy;
+            }
         }
-        T_[j] = 1.0f;
+        if constexpr (FM > 1) PR[j].x = 1.0f;
         flg[g] = fl;
         alive[g] = ballot64(in);
     }
@@ -242,6 +266,14 @@ k_accumulate(BatchArgs a)
             cc = -0.5f * LOG2E * r1.x;
             op = r1.y;
         }
+        // alpha = o 2^q = 2^(q + log2 o): the opacity rides in the row term,
+        // and "power <= 0" becomes q + log2 o <= log2 o (-inf for the empty
+        // lanes, whose alpha is 0)
+        const float lop = __builtin_amdgcn_logf(op);
+        // column anchor: ux = ax + (column - o_x), o_x the column nearest the
+        // centre, clamped to the tile
+        const float o_x = fminf(fmaxf(rintf(-dxl), 0.0f), 15.0f);
+        const float ax = dxl + o_x;
         if (lane + 64 < qn) {
             const uint32_t g2 = qi[lane + 64];
             qi[lane] = g2;
@@ -255,65 +287,106 @@ k_accumulate(BatchArgs a)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             uint64_t dead = 0;
+            // one frame: the group's visibility and static flags as
+            // wave-uniform masks (one scalar bit test per pixel)
+            uint64_t visg = 0, statg = 0;
+            if constexpr (FM == 1) {
+                visg = ballot64((flg[g] & 1u) != 0u);
+                statg = ballot64((flg[g] & 0x100u) != 0u);
+            }
             for (int rr = 0; rr < 4; ++rr) {
               uint32_t m = (uint32_t)(alive[g] >> (16 * rr)) & 0xFFFFu;
               if (m == 0u) continue;
               // the row's share of the quadratic form, common to its pixels:
-              // q = ux (ca ux + cb uy) + cc uy^2
+              // q = ux (ca ux + cb uy) + cc uy^2 (+ log2 o)
               const float uy = dyl + (float)(4 * g + rr);
               const float brow = cb * uy;
-              const float hrow = cc * uy * uy;
-              // one pixel per step keeps the kernel at 72 registers (7 waves
-              // per SIMD); the pixel's chain is short enough for them to hide
+              const float hrow = fmaf(cc * uy, uy, lop);
+              bool rowhit = false;
+              // the row's pixel records live in lanes 0..15 (copied to every
+              // 16-lane group) for the row: each step reads its pixel with
+              // v_readlane and writes the new transmittance back with one
+              // select, with no LDS traffic or address arithmetic per step
+              const int rbase = (4 * g + rr) * 16;
+              const float4 prow = PR[rbase + (lane & 15)];
+              float Trow = prow.x;
+              const float Xrow = prow.y, Yrow = prow.z;
               while (m) {
                 const int c1 = __builtin_ctz(m);
                 m &= m - 1;
                 const int j1 = 16 * rr + c1;
-                const int p1 = g * 64 + j1;
-                const float T1 = T_[p1];
-                const float ux1 = dxl + CF[c1];
-                const float uy1 = uy;
+                const float T1 = readlane_f(Trow, c1);
+                const float cf1 = (float)c1;
+                const float ux1 = dxl + cf1;
                 const float q1 = ux1 * (ca * ux1 + brow) + hrow;
                 // alpha = min(alpha_max, o e^power), clamped with one v_med3
-                const float al1 = __builtin_amdgcn_fmed3f(op * __builtin_amdgcn_exp2f(q1), 0.0f, amax);
+                const float al1 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(q1), 0.0f, amax);
                 // valid lanes: power <= 0 and alpha >= alpha_min
-                const uint64_t vm1 = ballot64(q1 <= 0.0f) & ballot64(al1 >= amin);
+                const uint64_t vm1 = ballot64(q1 <= lop) & ballot64(al1 >= amin);
                 float P1 = __builtin_amdgcn_inverse_ballot_w64(vm1) ? 1.0f - al1 : 1.0f;
                 P1 = wave_scan_mul_fused(P1);
                 const uint64_t tm1 = ballot64(T1 * P1 < tmin) & vm1;
-                const int kt1 = (int)__builtin_ctzll(tm1 | (1ull << 63));
-                const uint64_t cm1 = vm1 & (tm1 ? ((1ull << kt1) - 1ull) : ~0ull);
-                const float Pk1 = tm1 ? (kt1 == 0 ? 1.0f : readlane_f(P1, kt1 - 1)) : readlane_f(P1, 63);
-                if (lane0) T_[p1] = T1 * Pk1;
-                if (tm1) dead |= 1ull << j1;
+                // contributing lanes and the product of (1 - alpha) over them;
+                // termination inside the batch is the rare case
+                uint64_t cm1 = vm1;
+                float Pk1;
+                if (__builtin_expect(tm1 != 0ull, 0)) {
+                    const int kt1 = (int)__builtin_ctzll(tm1);
+                    cm1 = vm1 & ((1ull << kt1) - 1ull);
+                    Pk1 = kt1 == 0 ? 1.0f : readlane_f(P1, kt1 - 1);
+                    dead |= 1ull << j1;
+                    if (STATS) n_eval += (uint64_t)(kt1 + 1);
+                } else {
+                    Pk1 = readlane_f(P1, 63);
+                    if (STATS) n_eval += (uint64_t)nb;
+                }
+                const float Tn = Trow * Pk1;   // lane c1 holds T1
+                Trow = __builtin_amdgcn_inverse_ballot_w64(1ull << c1) ? Tn : Trow;
                 if (STATS) {
-                    n_eval += (uint64_t)(tm1 ? kt1 + 1 : nb);
                     n_contrib += (uint64_t)__popcll(cm1);
                     n_iter += 1;
                 }
                 // statistics of Eq. 4 for the lanes that contribute, per frame
                 // whose track at this pixel is visible
-                const uint32_t fl1 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j1);
-                if (cm1 && (fl1 & VISM)) {
-                    float tdx[FM], tdy[FM];
-#pragma unroll
-                    for (int f = 0; f < FM; ++f) {
-                        tdx[f] = readlane_f(dxg[f][g], j1);
-                        tdy[f] = readlane_f(dyg[f][g], j1);
-                    }
+                uint32_t fl1 = 0;
+                bool any;
+                if constexpr (FM == 1) {
+                    any = (visg >> j1) & 1ull;
+                } else {
+                    fl1 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j1);
+                    any = (fl1 & VISM) != 0u;
+                }
+                if (cm1 && any) {
                     asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
                                  : "+v"(pex_reg) : "v"(P1));
-                    if (__builtin_amdgcn_inverse_ballot_w64(cm1)) {
-                        const float wgt = al1 * (T1 * pex_reg);
-                        const float wx = wgt * ux1, wy = wgt * uy1;
-                        const float wxx = wx * ux1, wxy = wx * uy1, wyy = wy * uy1;
+                    rowhit = true;
+                    float2 td[FM];
+                    if constexpr (FM == 1) {
+                        td[0] = make_float2(readlane_f(Xrow, c1), readlane_f(Yrow, c1));
+                    } else {
 #pragma unroll
                         for (int f = 0; f < FM; ++f)
-                            if ((fl1 >> f) & 1u)
-                                sums_add(sm[f], wgt, wx, wy, wxx, wxy, wyy, tdx[f], tdy[f], (fl1 >> (8 + f)) & 1u,
-                                         al1);
+                            td[f] = make_float2(readlane_f(dxg[f][g], j1), readlane_f(dyg[f][g], j1));
+                    }
+                    if (__builtin_amdgcn_inverse_ballot_w64(cm1)) {
+                        const float wgt = al1 * (T1 * pex_reg);
+                        const float cpp = cf1 - o_x;   // exact: small integers
+                        const float wc = wgt * cpp;
+                        if constexpr (FM == 1) {
+                            sums_add(sm[0], wgt, wc, cpp, td[0].x, td[0].y, (statg >> j1) & 1ull, al1);
+                        } else {
+#pragma unroll
+                            for (int f = 0; f < FM; ++f)
+                                if ((fl1 >> f) & 1u)
+                                    sums_add(sm[f], wgt, wc, cpp, td[f].x, td[f].y, (fl1 >> (8 + f)) & 1u, al1);
+                        }
                     }
                 }
+              }
+              if (lane < 16) PR[rbase + lane].x = Trow;
+              if (rowhit) {
+#pragma unroll
+                for (int f = 0; f < FM; ++f) sums_fold_row(sm[f], uy, ax);
               }
             }
             alive[g] &= ~dead;
@@ -329,30 +402,33 @@ k_accumulate(BatchArgs a)
             const Sums& s = sm[f];
             float* const accf = S.acc[f];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (32 * h >= nb) break;
-                const int rl = lane - 32 * h;
-                if (rl >= 0 && rl < 32) {
+            for (int h = 0; h < 64 / SA_RECS; ++h) {
+                if (SA_RECS * h >= nb) break;
+                const int rl = lane - SA_RECS * h;
+                if (rl >= 0 && rl < SA_RECS) {
+                    // Eq. 4 record order: w, w ux, w uy, w ux^2, w ux uy,
+                    // w uy^2, w dx, w dy, w ux dx, w ux dy, w uy dx, w uy dy,
+                    // pixel count, static count, static alpha
                     float* r = SA + rl * 17;
-                    r[0] = s.w;
-                    r[1] = s.ux;
-                    r[2] = s.uy;
-                    r[3] = s.xx;
-                    r[4] = s.xy;
-                    r[5] = s.yy;
-                    r[6] = s.dx;
-                    r[7] = s.dy;
-                    r[8] = s.xdx;
-                    r[9] = s.xdy;
-                    r[10] = s.ydx;
-                    r[11] = s.ydy;
-                    r[12] = s.n;
+                    r[0] = s.W;
+                    r[1] = fmaf(ax, s.W, s.C1);
+                    r[2] = s.UY;
+                    r[3] = fmaf(ax, fmaf(ax, s.W, 2.0f * s.C1), s.C2);
+                    r[4] = s.XY;
+                    r[5] = s.YY;
+                    r[6] = s.DX;
+                    r[7] = s.DY;
+                    r[8] = fmaf(ax, s.DX, s.CDX);
+                    r[9] = fmaf(ax, s.DY, s.CDY);
+                    r[10] = s.YDX;
+                    r[11] = s.YDY;
+                    r[12] = s.N;
                     r[13] = s.sn;
                     r[14] = s.sa;
                     r[15] = __builtin_bit_cast(float, gid);
                 }
                 __syncthreads();
-                const int rec_n = min(32, nb - 32 * h);
+                const int rec_n = min(SA_RECS, nb - SA_RECS * h);
                 const int k = lane & 15;
                 for (int q = 0; 4 * q < rec_n; ++q) {
                     const int gl = 4 * q + (lane >> 4);
@@ -370,7 +446,7 @@ k_accumulate(BatchArgs a)
         for (int g = 0; g < 4; ++g) {
             const int j = g * 64 + lane;
             const int px = px0 + (j & 15), py = py0 + (j >> 4);
-            if (px < W && py < H) S.t_final[(row_base + py) * W + px] = T_[j];
+            if (px < W && py < H) S.t_final[(row_base + py) * W + px] = PR[j].x;
         }
     }
     if (STATS && lane == 0) {
