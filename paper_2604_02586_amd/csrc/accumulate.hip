@@ -286,7 +286,6 @@ k_accumulate(BatchArgs a)
 
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            uint64_t dead = 0;
             // one frame: the group's visibility and static flags as
             // wave-uniform masks (one scalar bit test per pixel)
             uint64_t visg = 0, statg = 0;
@@ -302,6 +301,10 @@ k_accumulate(BatchArgs a)
               const float uy = dyl + (float)(4 * g + rr);
               const float brow = cb * uy;
               const float hrow = fmaf(cc * uy, uy, lop);
+              // as a polynomial in the anchored column offset c'' = ux - ax:
+              // q = (ca c'' + bq) c'' + cq, cq being q at the anchor column
+              const float bq = fmaf(2.0f * ca, ax, brow);
+              const float cq = fmaf(ax, fmaf(ca, ax, brow), hrow);
               bool rowhit = false;
               // the row's pixel records live in lanes 0..15 (copied to every
               // 16-lane group) for the row: each step reads its pixel with
@@ -316,25 +319,33 @@ k_accumulate(BatchArgs a)
                 m &= m - 1;
                 const int j1 = 16 * rr + c1;
                 const float T1 = readlane_f(Trow, c1);
-                const float cf1 = (float)c1;
-                const float ux1 = dxl + cf1;
-                const float q1 = ux1 * (ca * ux1 + brow) + hrow;
+                const float cpp = (float)c1 - o_x;   // exact: small integers
+                const float q1 = fmaf(fmaf(ca, cpp, bq), cpp, cq);
                 // alpha = min(alpha_max, o e^power), clamped with one v_med3
                 const float al1 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(q1), 0.0f, amax);
                 // valid lanes: power <= 0 and alpha >= alpha_min
                 const uint64_t vm1 = ballot64(q1 <= lop) & ballot64(al1 >= amin);
+                // no Gaussian of the batch reaches the pixel: nothing changes
+                if (vm1 == 0ull) {
+                    if (STATS) {
+                        n_eval += (uint64_t)nb;
+                        n_iter += 1;
+                    }
+                    continue;
+                }
                 float P1 = __builtin_amdgcn_inverse_ballot_w64(vm1) ? 1.0f - al1 : 1.0f;
                 P1 = wave_scan_mul_fused(P1);
                 const uint64_t tm1 = ballot64(T1 * P1 < tmin) & vm1;
                 // contributing lanes and the product of (1 - alpha) over them;
                 // termination inside the batch is the rare case
+                // A pixel that terminates stores its transmittance negated:
+                // the row's dead pixels are then one ballot at the row's end.
                 uint64_t cm1 = vm1;
                 float Pk1;
                 if (__builtin_expect(tm1 != 0ull, 0)) {
                     const int kt1 = (int)__builtin_ctzll(tm1);
                     cm1 = vm1 & ((1ull << kt1) - 1ull);
-                    Pk1 = kt1 == 0 ? 1.0f : readlane_f(P1, kt1 - 1);
-                    dead |= 1ull << j1;
+                    Pk1 = -(kt1 == 0 ? 1.0f : readlane_f(P1, kt1 - 1));
                     if (STATS) n_eval += (uint64_t)(kt1 + 1);
                 } else {
                     Pk1 = readlane_f(P1, 63);
@@ -356,7 +367,7 @@ k_accumulate(BatchArgs a)
                     fl1 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j1);
                     any = (fl1 & VISM) != 0u;
                 }
-                if (cm1 && any) {
+                if (any && cm1 != 0ull) {
                     asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
                                  : "+v"(pex_reg) : "v"(P1));
                     rowhit = true;
@@ -370,7 +381,6 @@ k_accumulate(BatchArgs a)
                     }
                     if (__builtin_amdgcn_inverse_ballot_w64(cm1)) {
                         const float wgt = al1 * (T1 * pex_reg);
-                        const float cpp = cf1 - o_x;   // exact: small integers
                         const float wc = wgt * cpp;
                         if constexpr (FM == 1) {
                             sums_add(sm[0], wgt, wc, cpp, td[0].x, td[0].y, (statg >> j1) & 1ull, al1);
@@ -384,12 +394,12 @@ k_accumulate(BatchArgs a)
                 }
               }
               if (lane < 16) PR[rbase + lane].x = Trow;
+              alive[g] &= ~((ballot64(Trow < 0.0f) & 0xFFFFull) << (16 * rr));
               if (rowhit) {
 #pragma unroll
                 for (int f = 0; f < FM; ++f) sums_fold_row(sm[f], uy, ax);
               }
             }
-            alive[g] &= ~dead;
         }
         // Flush through LDS: each lane's record is transposed so that one
         // atomic instruction adds 4 records (16 lanes each, one record per
@@ -446,7 +456,8 @@ k_accumulate(BatchArgs a)
         for (int g = 0; g < 4; ++g) {
             const int j = g * 64 + lane;
             const int px = px0 + (j & 15), py = py0 + (j >> 4);
-            if (px < W && py < H) S.t_final[(row_base + py) * W + px] = PR[j].x;
+            // (terminated pixels hold their transmittance negated)
+            if (px < W && py < H) S.t_final[(row_base + py) * W + px] = fabsf(PR[j].x);
         }
     }
     if (STATS && lane == 0) {
