@@ -305,7 +305,6 @@ k_accumulate(BatchArgs a)
               // q = (ca c'' + bq) c'' + cq, cq being q at the anchor column
               const float bq = fmaf(2.0f * ca, ax, brow);
               const float cq = fmaf(ax, fmaf(ca, ax, brow), hrow);
-              bool rowhit = false;
               // the row's pixel records live in lanes 0..15 (copied to every
               // 16-lane group) for the row: each step reads its pixel with
               // v_readlane and writes the new transmittance back with one
@@ -341,60 +340,60 @@ k_accumulate(BatchArgs a)
                 // A pixel that terminates stores its transmittance negated:
                 // the row's dead pixels are then one ballot at the row's end.
                 uint64_t cm1 = vm1;
-                float Pk1;
+                float Pk1 = readlane_f(P1, 63);
                 if (__builtin_expect(tm1 != 0ull, 0)) {
                     const int kt1 = (int)__builtin_ctzll(tm1);
                     cm1 = vm1 & ((1ull << kt1) - 1ull);
                     Pk1 = -(kt1 == 0 ? 1.0f : readlane_f(P1, kt1 - 1));
-                    if (STATS) n_eval += (uint64_t)(kt1 + 1);
-                } else {
-                    Pk1 = readlane_f(P1, 63);
-                    if (STATS) n_eval += (uint64_t)nb;
+                    if (STATS) n_eval += (uint64_t)(kt1 + 1 - nb);
                 }
                 const float Tn = Trow * Pk1;   // lane c1 holds T1
                 Trow = __builtin_amdgcn_inverse_ballot_w64(1ull << c1) ? Tn : Trow;
                 if (STATS) {
+                    n_eval += (uint64_t)nb;
                     n_contrib += (uint64_t)__popcll(cm1);
                     n_iter += 1;
                 }
                 // statistics of Eq. 4 for the lanes that contribute, per frame
-                // whose track at this pixel is visible
+                // whose track at this pixel is visible: one exec mask, no
+                // separate tests (the wave-wide reads come first)
                 uint32_t fl1 = 0;
-                bool any;
+                uint64_t gate;
                 if constexpr (FM == 1) {
-                    any = (visg >> j1) & 1ull;
+                    gate = ((visg >> j1) & 1ull) ? cm1 : 0ull;
                 } else {
                     fl1 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j1);
-                    any = (fl1 & VISM) != 0u;
+                    gate = (fl1 & VISM) ? cm1 : 0ull;
                 }
-                if (any && cm1 != 0ull) {
-                    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
-                                 : "+v"(pex_reg) : "v"(P1));
-                    rowhit = true;
-                    float2 td[FM];
+                asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
+                             : "+v"(pex_reg) : "v"(P1));
+                float2 td[FM];
+                if constexpr (FM == 1) {
+                    td[0] = make_float2(readlane_f(Xrow, c1), readlane_f(Yrow, c1));
+                } else {
+#pragma unroll
+                    for (int f = 0; f < FM; ++f)
+                        td[f] = make_float2(readlane_f(dxg[f][g], j1), readlane_f(dyg[f][g], j1));
+                }
+                if (__builtin_amdgcn_inverse_ballot_w64(gate)) {
+                    const float wgt = al1 * (T1 * pex_reg);
+                    const float wc = wgt * cpp;
                     if constexpr (FM == 1) {
-                        td[0] = make_float2(readlane_f(Xrow, c1), readlane_f(Yrow, c1));
+                        sums_add(sm[0], wgt, wc, cpp, td[0].x, td[0].y, (statg >> j1) & 1ull, al1);
                     } else {
 #pragma unroll
                         for (int f = 0; f < FM; ++f)
-                            td[f] = make_float2(readlane_f(dxg[f][g], j1), readlane_f(dyg[f][g], j1));
-                    }
-                    if (__builtin_amdgcn_inverse_ballot_w64(cm1)) {
-                        const float wgt = al1 * (T1 * pex_reg);
-                        const float wc = wgt * cpp;
-                        if constexpr (FM == 1) {
-                            sums_add(sm[0], wgt, wc, cpp, td[0].x, td[0].y, (statg >> j1) & 1ull, al1);
-                        } else {
-#pragma unroll
-                            for (int f = 0; f < FM; ++f)
-                                if ((fl1 >> f) & 1u)
-                                    sums_add(sm[f], wgt, wc, cpp, td[f].x, td[f].y, (fl1 >> (8 + f)) & 1u, al1);
-                        }
+                            if ((fl1 >> f) & 1u)
+                                sums_add(sm[f], wgt, wc, cpp, td[f].x, td[f].y, (fl1 >> (8 + f)) & 1u, al1);
                     }
                 }
               }
               if (lane < 16) PR[rbase + lane].x = Trow;
               alive[g] &= ~((ballot64(Trow < 0.0f) & 0xFFFFull) << (16 * rr));
+              // fold the row's partial sums unless no lane gathered any
+              bool rowhit = false;
+#pragma unroll
+              for (int f = 0; f < FM; ++f) rowhit |= ballot64(sm[f].R0 != 0.0f) != 0ull;
               if (rowhit) {
 #pragma unroll
                 for (int f = 0; f < FM; ++f) sums_fold_row(sm[f], uy, ax);
