@@ -15,6 +15,8 @@
 // per-tile depth-ordered list.
 //
 // The radix sort (sort.hip) is LSD with 8-bit digits and stable ranks.
+#include <algorithm>
+
 #include "tg_internal.h"
 
 namespace {
@@ -28,6 +30,8 @@ namespace {
 constexpr int EMIT_ITEMS = 8;
 constexpr int EMIT_RANKS = 256 * EMIT_ITEMS;
 constexpr int EMIT_STAGE = EMIT_RANKS * 3;   // keys staged in the write pass's 24 KB of LDS
+constexpr int DIRECT_BINS = 256;   // coarse bins per view for the direct placement
+constexpr int DIRECT_WIN = 4096;   // pairs per LDS window of the direct placement
 
 // Coarse-bin rectangle of Gaussian g's tile rectangle (empty when culled).
 __device__ __forceinline__ ushort4 coarse_rect(const ushort4* __restrict__ rect, int64_t vN, uint32_t g, int64_t N,
@@ -60,28 +64,193 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t* ws
 
 // Count pass: gathers each rank's tile rectangle (the one random access of
 // the emission), stores its coarse rectangle in rank order for the write
-// pass, and records the block's pair count.
+// pass, and records the block's pair count -- or, for the direct placement
+// (HIST), the block's pair count per coarse bin of its view, as the column
+// hist[bin][block] of a bin-major matrix.
+template <bool HIST>
 __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__ order, const ushort4* __restrict__ rect,
-                                                    int64_t N, int cshift, int nblk, ushort4* __restrict__ crs,
-                                                    uint32_t* __restrict__ counts,
+                                                    int64_t N, int cshift, int nblk, GridPack gp,
+                                                    ushort4* __restrict__ crs, uint32_t* __restrict__ counts,
                                                     unsigned long long* __restrict__ n_pairs)
 {
     __shared__ uint32_t wsum[4];
-    const int v = blockIdx.y;
+    __shared__ uint32_t hist[HIST ? DIRECT_BINS : 1];
+    const int v = blockIdx.y, t = threadIdx.x;
     const int64_t vN = (int64_t)v * N;
-    const int64_t base = (int64_t)blockIdx.x * EMIT_RANKS + threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * EMIT_RANKS + t;
+    const int cw = gp.cx[v], nbv = gp.cx[v] * gp.cy[v];
+    if (HIST) {
+        for (int c = t; c < nbv; c += 256) hist[c] = 0;
+        __syncthreads();
+    }
     uint32_t cnt = 0;
 #pragma unroll
     for (int i = 0; i < EMIT_ITEMS; ++i) {
         const int64_t k = base + i * 256;
-        if (k < N) crs[vN + k] = coarse_rect(rect, vN, order[vN + k], N, cshift, cnt);
+        if (k < N) {
+            const ushort4 c = coarse_rect(rect, vN, order[vN + k], N, cshift, cnt);
+            crs[vN + k] = c;
+            if (HIST)
+                for (int y = c.y; y < c.w; ++y)
+                    for (int x = c.x; x < c.z; ++x) atomicAdd(&hist[y * cw + x], 1u);
+        }
     }
     uint32_t total;
     (void)block_excl_scan_u32(cnt, wsum, total);
-    if (threadIdx.x == 0) {
+    if (HIST) {
+        for (int c = t; c < nbv; c += 256)
+            counts[(int64_t)(gp.cell_off[v] + c) * nblk + blockIdx.x] = hist[c];
+    } else if (t == 0) {
         counts[(int64_t)v * nblk + blockIdx.x] = total;
-        if (total) atomicAdd(n_pairs, (unsigned long long)total);
     }
+    if (t == 0 && total) atomicAdd(n_pairs, (unsigned long long)total);
+}
+
+// Direct placement: the block's pairs, already in (view, depth rank) order,
+// are sorted by coarse bin inside the block (stable, in LDS, a window of
+// DIRECT_WIN pairs at a time) and written straight to their final places in
+// cell_ids: offsets[bin][block] (the scanned count matrix) is where the
+// block's run of each bin starts.  This replaces a global radix sort of the
+// pair keys.  Within a window, wave w ranks items [w*1024, w*1024+1024) in
+// rounds of 64 consecutive items by ballot matching on the bin (stable), the
+// window is placed bin-major in LDS and then written out as contiguous runs.
+__global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__ order, const ushort4* __restrict__ crs,
+                                                    int64_t N, GridPack gp, int nblk,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    uint32_t* __restrict__ cell_ids,
+                                                    const int32_t* __restrict__ overflow)
+{
+    // 24 KB: the rank-major transpose of ids and rectangles, then the
+    // window's ids (16 KB) and bins (4 KB)
+    __shared__ uint4 lds[EMIT_RANKS * 12 / 16];
+    __shared__ uint32_t sid[DIRECT_WIN];        // window sorted by bin
+    __shared__ uint8_t sbin[DIRECT_WIN];
+    __shared__ uint32_t cnt[4][DIRECT_BINS];    // per wave and bin
+    __shared__ uint32_t boff[DIRECT_BINS];      // global start of the block's next pair per bin
+    __shared__ uint32_t gofs[DIRECT_BINS];      // global position minus window position, per bin
+    __shared__ uint32_t wsum[4];
+    if (*overflow) return;   // block-uniform: the caller re-sizes and retries
+    const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int64_t vN = (int64_t)v * N;
+    const int64_t rbase = (int64_t)blockIdx.x * EMIT_RANKS;
+    uint32_t* sg = (uint32_t*)lds;
+    ushort4* sc = (ushort4*)(lds + EMIT_RANKS / 4);
+#pragma unroll
+    for (int i = 0; i < EMIT_ITEMS; ++i) {
+        const int j = i * 256 + t;
+        const bool in = rbase + j < N;
+        sg[j] = in ? order[vN + rbase + j] : 0u;
+        sc[j] = in ? crs[vN + rbase + j] : make_ushort4(0, 0, 0, 0);
+    }
+    const int cw = gp.cx[v], nbv = gp.cx[v] * gp.cy[v];
+    for (int c = t; c < nbv; c += 256)
+        boff[c] = offsets[(int64_t)(gp.cell_off[v] + c) * nblk + blockIdx.x];
+    __syncthreads();
+    uint32_t gid[EMIT_ITEMS];
+    ushort4 cr[EMIT_ITEMS];
+    {
+        const uint4 a = lds[2 * t], b = lds[2 * t + 1];
+        gid[0] = a.x; gid[1] = a.y; gid[2] = a.z; gid[3] = a.w;
+        gid[4] = b.x; gid[5] = b.y; gid[6] = b.z; gid[7] = b.w;
+    }
+    uint32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < EMIT_ITEMS; ++i) {
+        cr[i] = sc[EMIT_ITEMS * t + i];
+        mine += (uint32_t)((cr[i].z - cr[i].x) * (cr[i].w - cr[i].y));
+    }
+    uint32_t total;
+    const uint32_t before = block_excl_scan_u32(mine, wsum, total);
+    uint32_t* wid = (uint32_t*)lds;                          // [DIRECT_WIN]
+    uint8_t* wbin = (uint8_t*)(lds + DIRECT_WIN / 4);        // [DIRECT_WIN]
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t w0 = 0; w0 < total; w0 += DIRECT_WIN) {
+        __syncthreads();   // registers hold this thread's data; LDS is free
+        {
+            uint32_t pidx = before;
+#pragma unroll
+            for (int i = 0; i < EMIT_ITEMS; ++i) {
+                const ushort4 c = cr[i];
+                for (int y = c.y; y < c.w; ++y)
+                    for (int x = c.x; x < c.z; ++x, ++pidx)
+                        if (pidx >= w0 && pidx < w0 + DIRECT_WIN) {
+                            wid[pidx - w0] = gid[i];
+                            wbin[pidx - w0] = (uint8_t)(y * cw + x);
+                        }
+            }
+        }
+        for (int k = t; k < 4 * DIRECT_BINS; k += 256) (&cnt[0][0])[k] = 0;
+        __syncthreads();
+        const uint32_t nwin = total - w0 < DIRECT_WIN ? total - w0 : DIRECT_WIN;
+        uint32_t lrank[DIRECT_WIN / 256];
+#pragma unroll
+        for (int r = 0; r < DIRECT_WIN / 256; ++r) {
+            const uint32_t idx = (uint32_t)(w * (DIRECT_WIN / 4) + r * 64 + lane);
+            const bool act = idx < nwin;
+            const uint32_t d = act ? wbin[idx] : 0u;
+            uint64_t m = ballot64(act);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool set = (d >> bit) & 1u;
+                const uint64_t bb = ballot64(act && set);
+                m &= set ? bb : ~bb;
+            }
+            const uint32_t rk = (uint32_t)__popcll(m & lt);
+            const uint32_t b0 = act ? cnt[w][d] : 0u;
+            lrank[r] = b0 + rk;
+            if (act && rk == 0) cnt[w][d] = b0 + (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        {
+            // thread t owns bin t: window-local start (exclusive scan over
+            // bins), the waves' starts inside it, and the global offset
+            const int c = t;
+            uint32_t cw4[4], tot = 0;
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) {
+                cw4[ww] = cnt[ww][c];
+                tot += cw4[ww];
+            }
+            uint32_t all;
+            const uint32_t start = block_excl_scan_u32(tot, wsum, all);
+            uint32_t run = start;
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) {
+                cnt[ww][c] = run;
+                run += cw4[ww];
+            }
+            if (c < nbv) {
+                gofs[c] = boff[c] - start;
+                boff[c] += tot;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < DIRECT_WIN / 256; ++r) {
+            const uint32_t idx = (uint32_t)(w * (DIRECT_WIN / 4) + r * 64 + lane);
+            if (idx < nwin) {
+                const uint32_t d = wbin[idx];
+                const uint32_t sp = cnt[w][d] + lrank[r];
+                sid[sp] = wid[idx];
+                sbin[sp] = (uint8_t)d;
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = t; i < nwin; i += 256) cell_ids[gofs[sbin[i]] + i] = sid[i];
+    }
+}
+
+// Bin ranges of the direct placement from the scanned count matrix: bin c
+// starts where its first block's run starts.
+__global__ void k_bin_ranges(const uint32_t* __restrict__ offsets, int nblk, int64_t ncell,
+                             const int64_t* __restrict__ n_pairs, int64_t capacity, uint2* __restrict__ ranges)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = *n_pairs;
+    if (c >= ncell || n > capacity) return;
+    const uint32_t start = offsets[c * nblk];
+    const uint32_t end = c + 1 < ncell ? offsets[(c + 1) * nblk] : (uint32_t)n;
+    ranges[c] = make_uint2(start, end);
 }
 
 // Write pass: the same ranks, coarse rectangles read back in rank order.
@@ -312,13 +481,37 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
     st = tg_radix_sort(sp->key, nullptr, L.dk_a, L.dv_a, L.dk_b, L.dv_b, nullptr, bins->order, N, V, nullptr, 0, 4,
                     L.scratch, s);
     if (st != TG_OK) return st;
-    // (2) emit (coarse bin | Gaussian id) keys in (view, depth rank) order
+    // (2) emit the (coarse bin, Gaussian) pairs in (view, depth rank) order
     const int nblk = (int)((N + EMIT_RANKS - 1) / EMIT_RANKS);
     // coarse rectangles in rank order reuse the depth sort's first ping-pong
     // pair (8 B per (view, Gaussian) over two contiguous 4 B arrays)
     ushort4* crs = (ushort4*)L.dk_a;
-    hipLaunchKernelGGL(k_emit_count, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order, (const ushort4*)sp->rect, N,
-                       bp.cshift, nblk, crs, L.counts, (unsigned long long*)bins->n_pairs);
+    int max_bins = 0;
+    for (int v = 0; v < V; ++v) max_bins = std::max(max_bins, bp.gp.cx[v] * bp.gp.cy[v]);
+    const int64_t nmat = bp.ncell * (int64_t)nblk;
+    if (max_bins <= DIRECT_BINS && nmat <= bins->capacity && nmat <= ((int64_t)1 << 26)) {
+        // direct placement: per-(bin, block) counts, one scan, then each
+        // block sorts its pairs by bin in LDS and writes the final lists
+        uint32_t* mat = L.pk_a;   // [ncell][nblk], free on this path
+        hipLaunchKernelGGL(k_emit_count<true>, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order,
+                           (const ushort4*)sp->rect, N, bp.cshift, nblk, bp.gp, crs, mat,
+                           (unsigned long long*)bins->n_pairs);
+        hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,
+                           bins->capacity, bins->overflow);
+        // with no overflow the total fits the capacity (< 2^32): u32 offsets
+        tg_exclusive_scan_u32(mat, nmat, (uint32_t*)L.scratch, s);
+        hipLaunchKernelGGL(k_emit_place, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order, (const ushort4*)crs,
+                           N, bp.gp, nblk, mat, bins->cell_ids, bins->overflow);
+        hipLaunchKernelGGL(k_bin_ranges, dim3((unsigned)((bp.ncell + 255) / 256)), dim3(256), 0, s, mat, nblk,
+                           bp.ncell, bins->n_pairs, bins->capacity, (uint2*)bins->cell_ranges);
+        TG_CHECK_LAUNCH();
+        return TG_OK;
+    }
+    // general path: keys (coarse bin | Gaussian id) written in rank order,
+    // then a stable radix sort over the bin bits
+    hipLaunchKernelGGL(k_emit_count<false>, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order,
+                       (const ushort4*)sp->rect, N, bp.cshift, nblk, bp.gp, crs, L.counts,
+                       (unsigned long long*)bins->n_pairs);
     hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,
                        bins->capacity, bins->overflow);
     // with no overflow the total fits the capacity (< 2^32), so u32 offsets
