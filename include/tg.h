@@ -291,10 +291,13 @@ tg_status tg_splat_accumulate_batch(const tg_acc_slot* slots, int32_t n_slots, c
  * det_min, or 4 det(C)/tr(C)^2 below iso_min with C = Suu/Sw - (Su/Sw)(Su/Sw)^T
  * the weighted covariance of the pixel offsets (bits 2-16 may combine).  Unsolved entries get zero mu'/Sigma'.
  * mu2d_new [V,N,2], cov2d_new [V,N,3] float32, vflags [V,N] uint8: device.
+ * wn: device [V,N,2] float32 or NULL: receives each record's accumulated
+ * alpha (slot 0) and pixel count (slot 12), the compact totals that
+ * tg_triangulate reads (8-byte aligned).
  */
 tg_status tg_solve_views(const float* acc, const tg_splats* s, int64_t N, int32_t V,
                          const tg_params* p, float* mu2d_new, float* cov2d_new,
-                         uint8_t* vflags, void* stream);
+                         uint8_t* vflags, float* wn, void* stream);
 
 /*
  * tg_triangulate -- multi-view update of each Gaussian (Sec. 4.4) in FP64.
@@ -313,10 +316,12 @@ tg_status tg_solve_views(const float* acc, const tg_splats* s, int64_t N, int32_
  * 8 low total alpha, 16 few total pixels, 32 non-positive eigenvalue or
  * singular covariance system, 64 degenerate DLT, 128 behind a camera.
  * Everything not updated is copied from g_in.  g_out may alias g_in (in-place
- * update).  cams: host [V]; V <= TG_MAX_VIEWS.
+ * update).  cams: host [V]; V <= TG_MAX_VIEWS.  wn: device [V,N,2] from
+ * tg_solve_views (accumulated alpha and pixel count per view, summed here
+ * into the per-Gaussian totals).
  */
 tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_new, const uint8_t* vflags,
-                         const float* acc, const tg_splats* s, const tg_gaussians* g_in,
+                         const float* wn, const tg_splats* s, const tg_gaussians* g_in,
                          int64_t N, const tg_camera* cams, int32_t V, const tg_params* p,
                          tg_gaussians* g_out, uint32_t* status, void* stream);
 

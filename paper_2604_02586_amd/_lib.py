@@ -90,7 +90,7 @@ def lib():
         "tg_splat_accumulate": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P, P], st),
         "tg_splat_accumulate_batch": ([P, c_i32, P, P, P], st),
         "tg_regularize": ([P, P, P, P, c_i64, c_i32, P, P, P, P, P, P], st),
-        "tg_solve_views": ([P, P, c_i64, c_i32, P, P, P, P, P], st),
+        "tg_solve_views": ([P, P, c_i64, c_i32, P, P, P, P, P, P], st),
         "tg_triangulate": ([P, P, P, P, P, P, c_i64, P, c_i32, P, P, P, P], st),
         "tg_bin_expand": ([P, P, c_i64, P, c_i32, P, P, P, c_i64, P, P, P, P], st),
         "tg_raster_fwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),

@@ -211,18 +211,21 @@ def regularize(g_ref: GaussianTensors, g_upd: GaussianTensors, status, acc, para
                                                ctypes.byref(go), _ptr(reg_status), stream_ptr(stream)))
 
 
-def solve_views(acc, s: SplatTensors, n, V, params, mu_new, cov_new, vflags, stream=None):
+def solve_views(acc, s: SplatTensors, n, V, params, mu_new, cov_new, vflags, wn=None, stream=None):
+    """wn: optional [V,N,2] float32 output of the compact totals (alpha, pixels)."""
     sc = s.c()
     check("tg_solve_views", lib().tg_solve_views(_ptr(acc), ctypes.byref(sc), n, V, ctypes.byref(params),
-                                                 _ptr(mu_new), _ptr(cov_new), _ptr(vflags), stream_ptr(stream)))
+                                                 _ptr(mu_new), _ptr(cov_new), _ptr(vflags),
+                                                 _ptr(wn) if wn is not None else None, stream_ptr(stream)))
 
 
-def triangulate(mu_new, cov_new, vflags, acc, s: SplatTensors, g_in: GaussianTensors, cams, params,
+def triangulate(mu_new, cov_new, vflags, wn, s: SplatTensors, g_in: GaussianTensors, cams, params,
                 g_out: GaussianTensors, status, stream=None):
+    """wn: [V,N,2] totals written by solve_views."""
     cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
     sc, gi, go = s.c(), g_in.c(), g_out.c()
     check("tg_triangulate", lib().tg_triangulate(
-        _ptr(mu_new), _ptr(cov_new), _ptr(vflags), _ptr(acc), ctypes.byref(sc), ctypes.byref(gi), g_in.n, cams,
+        _ptr(mu_new), _ptr(cov_new), _ptr(vflags), _ptr(wn), ctypes.byref(sc), ctypes.byref(gi), g_in.n, cams,
         len(cams), ctypes.byref(params), ctypes.byref(go), _ptr(status), stream_ptr(stream)))
 
 
@@ -279,6 +282,7 @@ class MotionTransfer:
         self.mu_new = torch.empty(*VN, 2, dtype=torch.float32, device=self.device)
         self.cov_new = torch.empty(*VN, 3, dtype=torch.float32, device=self.device)
         self.vflags = torch.empty(*VN, dtype=torch.uint8, device=self.device)
+        self.wn = torch.empty(*VN, 2, dtype=torch.float32, device=self.device)
         self.status = torch.empty(self.N, dtype=torch.int32, device=self.device)
         self.t_final = None
         self.stats = torch.zeros(4, dtype=torch.int64, device=self.device)
@@ -311,10 +315,11 @@ class MotionTransfer:
                          self.t_final if t_final else None, self.stats if stats else None)
 
     def solve(self):
-        solve_views(self.acc, self.splats, self.N, self.V, self.params, self.mu_new, self.cov_new, self.vflags)
+        solve_views(self.acc, self.splats, self.N, self.V, self.params, self.mu_new, self.cov_new, self.vflags,
+                    self.wn)
 
     def triangulate(self, g_in: GaussianTensors, g_out: GaussianTensors):
-        triangulate(self.mu_new, self.cov_new, self.vflags, self.acc, self.splats, g_in, self.cams_host,
+        triangulate(self.mu_new, self.cov_new, self.vflags, self.wn, self.splats, g_in, self.cams_host,
                     self.params, g_out, self.status)
 
     def run(self, g: GaussianTensors, disp, vis=None, g_out: GaussianTensors | None = None, check_overflow=True,

@@ -15,7 +15,8 @@ namespace {
 __global__ void __launch_bounds__(256) k_solve_views(const float4* __restrict__ acc, const float4* __restrict__ rec,
                                                      const float* __restrict__ cov2d, const ushort4* __restrict__ rect,
                                                      int64_t VN, tg_params prm, float2* __restrict__ mu_new,
-                                                     float* __restrict__ cov_new, uint8_t* __restrict__ flags)
+                                                     float* __restrict__ cov_new, uint8_t* __restrict__ flags,
+                                                     float2* __restrict__ wn)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= VN) return;
@@ -75,6 +76,9 @@ __global__ void __launch_bounds__(256) k_solve_views(const float4* __restrict__ 
         co[2] = (float)(m10 * A10 + m11 * A11);
     }
     mu_new[i] = mo;
+    // accumulated alpha and pixel count, compact for the triangulation's
+    // per-Gaussian totals (8 B instead of a 64-byte record per view)
+    if (wn) wn[i] = make_float2(a0.x, a3.x);
     cov_new[3 * i] = co[0];
     cov_new[3 * i + 1] = co[1];
     cov_new[3 * i + 2] = co[2];
@@ -173,8 +177,7 @@ struct TriArgs {
     const float2* mu_new;
     const float* cov_new;
     const uint8_t* vflags;
-    const float* acc;
-    const ushort4* rect;
+    const float2* wn;
     const float* means_in;
     const float* quats_in;
     const float* scales_in;
@@ -207,11 +210,10 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
     double sw = 0.0, nt = 0.0;
     for (int v = 0; v < a.V; ++v) {
         const int64_t o = (int64_t)v * a.N + g;
-        const ushort4 r = a.rect[o];
-        if (r.z > r.x && r.w > r.y) {
-            sw += (double)a.acc[o * TG_ACC_STRIDE + 0];
-            nt += (double)a.acc[o * TG_ACC_STRIDE + 12];
-        }
+        // culled views accumulate nothing, so their totals are zero
+        const float2 t = a.wn[o];
+        sw += (double)t.x;
+        nt += (double)t.y;
         if (a.vflags[o] != 1) continue;
         ++nv;
         const tg_camera& c = cams.cam[v];
@@ -435,11 +437,9 @@ __device__ __forceinline__ uint32_t tri_light(const TriArgs& a, const tg_params&
     double sw = 0.0, nt = 0.0;
     for (int v = 0; v < a.V; ++v) {
         const int64_t o = (int64_t)v * a.N + g;
-        const ushort4 r = a.rect[o];
-        if (r.z > r.x && r.w > r.y) {
-            sw += (double)a.acc[o * TG_ACC_STRIDE + 0];
-            nt += (double)a.acc[o * TG_ACC_STRIDE + 12];
-        }
+        const float2 t = a.wn[o];
+        sw += (double)t.x;
+        nt += (double)t.y;
         if (a.vflags[o] == 1) ++nv;
     }
     uint32_t st = 0;
@@ -485,40 +485,40 @@ __global__ void __launch_bounds__(TRI_THREADS) k_triangulate(TriArgs a, CamPack 
 }  // namespace
 
 extern "C" tg_status tg_solve_views(const float* acc, const tg_splats* s, int64_t N, int32_t V, const tg_params* p,
-                                    float* mu2d_new, float* cov2d_new, uint8_t* vflags, void* stream)
+                                    float* mu2d_new, float* cov2d_new, uint8_t* vflags, float* wn, void* stream)
 {
     if (!acc || !s || !p || !mu2d_new || !cov2d_new || !vflags || N < 0 || V < 1) return TG_ERR_INVALID_ARG;
     if (!s->rec || !s->cov2d || !s->rect) return TG_ERR_INVALID_ARG;
-    if (!aligned16(acc) || !aligned16(s->rec) || ((uintptr_t)mu2d_new & 7u)) return TG_ERR_ALIGNMENT;
+    if (!aligned16(acc) || !aligned16(s->rec) || ((uintptr_t)mu2d_new & 7u) || ((uintptr_t)wn & 7u))
+        return TG_ERR_ALIGNMENT;
     const int64_t VN = (int64_t)V * N;
     if (VN == 0) return TG_OK;
     hipLaunchKernelGGL(k_solve_views, dim3((unsigned)((VN + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                        (const float4*)acc, (const float4*)s->rec, s->cov2d, (const ushort4*)s->rect, VN, *p,
-                       (float2*)mu2d_new, cov2d_new, vflags);
+                       (float2*)mu2d_new, cov2d_new, vflags, (float2*)wn);
     TG_CHECK_LAUNCH();
     return TG_OK;
 }
 
 extern "C" tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_new, const uint8_t* vflags,
-                                    const float* acc, const tg_splats* s, const tg_gaussians* g_in, int64_t N,
+                                    const float* wn, const tg_splats* s, const tg_gaussians* g_in, int64_t N,
                                     const tg_camera* cams, int32_t V, const tg_params* p, tg_gaussians* g_out,
                                     uint32_t* status, void* stream)
 {
-    if (!mu2d_new || !cov2d_new || !vflags || !acc || !s || !g_in || !cams || !p || !g_out || N < 0 || V < 1)
+    if (!mu2d_new || !cov2d_new || !vflags || !wn || !s || !g_in || !cams || !p || !g_out || N < 0 || V < 1)
         return TG_ERR_INVALID_ARG;
     if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
-    if (!s->rect || !g_in->means || !g_in->quats || !g_in->scales || !g_out->means || !g_out->quats ||
+    if (!g_in->means || !g_in->quats || !g_in->scales || !g_out->means || !g_out->quats ||
         !g_out->scales)
         return TG_ERR_INVALID_ARG;
     if (g_in->scale_mode < 0 || g_in->scale_mode > 1) return TG_ERR_INVALID_ARG;
-    if (((uintptr_t)mu2d_new & 7u)) return TG_ERR_ALIGNMENT;
+    if (((uintptr_t)mu2d_new & 7u) || ((uintptr_t)wn & 7u)) return TG_ERR_ALIGNMENT;
     if (N == 0) return TG_OK;
     TriArgs a;
     a.mu_new = (const float2*)mu2d_new;
     a.cov_new = cov2d_new;
     a.vflags = vflags;
-    a.acc = acc;
-    a.rect = (const ushort4*)s->rect;
+    a.wn = (const float2*)wn;
     a.means_in = g_in->means;
     a.quats_in = g_in->quats;
     a.scales_in = g_in->scales;

@@ -41,9 +41,9 @@ class BudgetError(RuntimeError):
 def frame_bytes(n, V, H, W):
     """Device bytes of one in-flight frame: tracks (8 B) and visibility
     (1 B) per pixel; accumulators (64 B), new 2D mean/covariance and flags
-    (21 B) per (view, Gaussian); output mean/quaternion/scale and status
-    (44 B) per Gaussian."""
-    return V * H * W * 9 + V * n * (64 + 21) + n * 44
+    (21 B) and the compact totals (8 B) per (view, Gaussian); output
+    mean/quaternion/scale and status (44 B) per Gaussian."""
+    return V * H * W * 9 + V * n * (64 + 21 + 8) + n * 44
 
 
 def resident_bytes(n, V, n_cells, capacity, ws_bytes):
@@ -362,13 +362,14 @@ class Server:
                     mu = torch.empty(*VN, 2, dtype=torch.float32, device=self.device)
                     cov = torch.empty(*VN, 3, dtype=torch.float32, device=self.device)
                     vfl = torch.empty(*VN, dtype=torch.uint8, device=self.device)
+                    wn = torch.empty(*VN, 2, dtype=torch.float32, device=self.device)
                     st = torch.empty(r.N, dtype=torch.int32, device=self.device)
                     g = r.g
                     out = api.GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.quats),
                                               torch.empty_like(g.scales), g.opacity, g.sh, g.sh_degree,
                                               g.scale_mode, g.opacity_mode)
-                    api.solve_views(acc, r.splats, r.N, r.V, self.params, mu, cov, vfl)
-                    api.triangulate(mu, cov, vfl, acc, r.splats, g, r.cams, self.params, out, st)
+                    api.solve_views(acc, r.splats, r.N, r.V, self.params, mu, cov, vfl, wn)
+                    api.triangulate(mu, cov, vfl, wn, r.splats, g, r.cams, self.params, out, st)
                     f.result = (out, st, acc, mu, cov, vfl) if self.keep_intermediate else (out, st)
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(self.compute)
