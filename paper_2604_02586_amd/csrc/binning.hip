@@ -31,7 +31,7 @@ constexpr int EMIT_ITEMS = 8;
 constexpr int EMIT_RANKS = 256 * EMIT_ITEMS;
 constexpr int EMIT_STAGE = EMIT_RANKS * 3;   // keys staged in the write pass's 24 KB of LDS
 constexpr int DIRECT_BINS = 256;   // coarse bins per view for the direct placement
-constexpr int DIRECT_WIN = 4096;   // pairs per LDS window of the direct placement
+constexpr int DIRECT_WIN = 2048;   // pairs per LDS window of the direct placement
 
 // Coarse-bin rectangle of Gaussian g's tile rectangle (empty when culled).
 __device__ __forceinline__ ushort4 coarse_rect(const ushort4* __restrict__ rect, int64_t vN, uint32_t g, int64_t N,
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
     __shared__ uint4 lds[EMIT_RANKS * 12 / 16];
     __shared__ uint32_t sid[DIRECT_WIN];        // window sorted by bin
     __shared__ uint8_t sbin[DIRECT_WIN];
-    __shared__ uint32_t cnt[4][DIRECT_BINS];    // per wave and bin
+    __shared__ uint16_t cnt[4][DIRECT_BINS];    // per wave and bin (< DIRECT_WIN)
     __shared__ uint32_t boff[DIRECT_BINS];      // global start of the block's next pair per bin
     __shared__ uint32_t gofs[DIRECT_BINS];      // global position minus window position, per bin
     __shared__ uint32_t wsum[4];
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
             const uint32_t rk = (uint32_t)__popcll(m & lt);
             const uint32_t b0 = act ? cnt[w][d] : 0u;
             lrank[r] = b0 + rk;
-            if (act && rk == 0) cnt[w][d] = b0 + (uint32_t)__popcll(m);
+            if (act && rk == 0) cnt[w][d] = (uint16_t)(b0 + (uint32_t)__popcll(m));
         }
         __syncthreads();
         {
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
             uint32_t run = start;
 #pragma unroll
             for (int ww = 0; ww < 4; ++ww) {
-                cnt[ww][c] = run;
+                cnt[ww][c] = (uint16_t)run;
                 run += cw4[ww];
             }
             if (c < nbv) {
