@@ -244,7 +244,6 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
         }
         qn -= nb;
         const float ca = -0.5f * LOG2E * A, cb = -LOG2E * B, cc = -0.5f * LOG2E * C;
-        const uint32_t my_idx = bstart + (uint32_t)lane;
 
         float g_mx = 0.f, g_my = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f;
         const float fx0 = (float)px0;
@@ -265,10 +264,15 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 // sums are exact in FP32), so alpha is bit-identical
                 const float ux = (fx0 + CFt[j & 15]) - mx, uy = (fy0 + RFt[j >> 4]) - my;
                 const float p2 = ux * (ca * ux + cb * uy) + cc * uy * uy;
-                const float e2 = op * __builtin_amdgcn_exp2f(p2);
+                const float ex = __builtin_amdgcn_exp2f(p2);
+                const float e2 = op * ex;
                 const float al = __builtin_amdgcn_fmed3f(e2, 0.0f, amax);
-                const uint64_t vm = ballot64(p2 <= 0.0f) & ballot64(al >= amin) & ballot64(my_idx < (uint32_t)np) &
-                                    ballot64(lane < nb);
+                // lanes past the batch (opacity 0) fail alpha >= alpha_min;
+                // the lanes the forward processed for this pixel are the
+                // first np - bstart of the batch
+                const uint32_t nfw = (uint32_t)np - bstart;
+                const uint64_t fwm = nfw >= 64u ? ~0ull : ((1ull << nfw) - 1ull);
+                const uint64_t vm = ballot64(p2 <= 0.0f) & ballot64(al >= amin) & fwm;
                 const bool valid = __builtin_amdgcn_inverse_ballot_w64(vm);
                 float P = valid ? 1.0f - al : 1.0f;
                 P = wave_scan_mul_fused(P);
@@ -277,13 +281,15 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 const float Ti = rt.w * pex_reg;
                 const float wgt = valid ? al * Ti : 0.0f;
                 const float w0 = c0 * wgt, w1 = c1 * wgt, w2 = c2 * wgt;
-                const float F0 = wave_scan_add_fused(w0);
-                const float F1 = wave_scan_add_fused(w1);
-                const float F2 = wave_scan_add_fused(w2);
+                float F0 = w0, F1 = w1, F2 = w2;
+                wave_scan_add_fused3(F0, F1, F2);
                 if (valid) {
                     // colour behind lane i (incl. background): C - front - own
                     const float S0 = rt.x - F0, S1 = rt.y - F1, S2 = rt.z - F2;
-                    const float inv1m = 1.0f / (1.0f - al);
+                    // 1 - alpha >= 0.01 (alpha is clamped at 0.99): the
+                    // hardware reciprocal's ulp error is far below the
+                    // gradient's FP32 accumulation error
+                    const float inv1m = __builtin_amdgcn_rcpf(1.0f - al);
                     const float dal = gf.x * (c0 * Ti - S0 * inv1m) + gf.y * (c1 * Ti - S1 * inv1m) +
                                       gf.z * (c2 * Ti - S2 * inv1m);
                     g_r += gf.x * wgt;
@@ -291,7 +297,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                     g_b += gf.z * wgt;
                     if (e2 < amax) {  // not clamped: alpha = o e^power
                         const float dpow = dal * al;
-                        g_o += dal * (al / op);
+                        g_o += dal * ex;   // d alpha / d o = e^power when not clamped
                         g_mx += dpow * (A * ux + B * uy);
                         g_my += dpow * (C * uy + B * ux);
                         g_A += dpow * (-0.5f * ux * ux);
