@@ -162,7 +162,10 @@ __device__ __forceinline__ float rect_min_form(float a, float b, float c, float 
                                                float y0, float y1) {
     if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.0f;
     const float dx0 = x0 - mx, dx1 = x1 - mx, dy0 = y0 - my, dy1 = y1 - my;
-    const float ia = 1.0f / a, ic = 1.0f / c;
+    // the hardware reciprocal (about 1 ulp) only moves each edge minimiser
+    // slightly along its segment, where the form is flat to second order;
+    // the caller's margin covers it
+    const float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
     float best;
     {
         const float dy = fminf(dy1, fmaxf(dy0, -b * dx0 * ic));
