@@ -37,7 +37,7 @@
 namespace {
 
 constexpr int QCAP = 128;
-constexpr int SA_RECS = 16;   // records per round of the flush
+constexpr int SA_RECS = 8;    // records per round of the flush
 constexpr float LOG2E = 1.4426950408889634f;
 
 // One slot of a launch: a Gaussian set (splats + bins of one frame set)
@@ -129,11 +129,12 @@ template <int FM, bool STATS>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FM == 1 ? 7 : 1, 8)))
 k_accumulate(BatchArgs a)
 {
-    // 5.7 KB of LDS per wave (7 waves per SIMD fit): queue of filtered list
-    // entries (ids), per-pixel records (transmittance, and for one frame the
+    // 5.7 KB of LDS per wave (7 waves per SIMD fit): queues of candidate
+    // and filtered list entries (ids), per-pixel records (transmittance, and for one frame the
     // track; a row of them is held in registers while the row is visited)
     // and the atomics' transpose buffer
     __shared__ uint32_t qi[QCAP];
+    __shared__ uint32_t cq[QCAP];   // candidates passing the rectangle test
     __shared__ float4 PR[256];      // T, track x, track y, unused
     __shared__ float SA[SA_RECS * 17];
     // XCD-aware remap: hardware places workgroup b on XCD (b mod 8); give
@@ -219,7 +220,7 @@ k_accumulate(BatchArgs a)
     const bool lane0 = lane == 0;
     constexpr uint32_t VISM = (1u << FM) - 1u;
     float pex_reg = 1.0f;   // lane 0 is never written by the wave shift below
-    int qn = 0;
+    int qn = 0, cn = 0;
     uint32_t pos = rg.x;
     // pixel-centre extent of the tile (conservative for the ellipse test)
     const float ex0 = (float)px0, ex1 = (float)(px0 + TG_TILE - 1);
@@ -233,23 +234,39 @@ k_accumulate(BatchArgs a)
         // culling: q >= 2 ln(o / alpha_min) everywhere on the tile means
         // alpha < alpha_min at every pixel, so the Gaussian neither adds nor
         // attenuates (a margin keeps it conservative under FP32 rounding).
-        while (qn < 64 && pos < rg.y) {
-            const uint32_t gid = nid;
-            const uint32_t i = pos + lane;
-            pos += 64;
-            nid = (pos + lane < rg.y) ? cell_ids[pos + lane] : 0xFFFFFFFFu;
-            bool hit = false;
-            if (i < rg.y && gid < (uint64_t)N) {
-                const ushort4 r = rect[vN + gid];
-                hit = tx >= r.x && tx < r.z && ty >= r.y && ty < r.w;
-                if (hit)
-                    hit = splat_reaches_tile(rec[2 * (vN + gid)], rec[2 * (vN + gid) + 1], log_amin, amin, ex0,
-                                             ex1, ey0, ey1);
+        // Two stages keep the lanes busy: the rectangle test streams the
+        // list (a few percent of a coarse bin's entries meet one tile) into
+        // a candidate queue, and the exact test runs on 64 candidates at a
+        // time.  Both queues keep list order.
+        while (qn < 64 && (pos < rg.y || cn > 0)) {
+            while (cn < 64 && pos < rg.y) {
+                const uint32_t gid = nid;
+                const uint32_t i = pos + lane;
+                pos += 64;
+                nid = (pos + lane < rg.y) ? cell_ids[pos + lane] : 0xFFFFFFFFu;
+                bool hit = false;
+                if (i < rg.y && gid < (uint64_t)N) {
+                    const ushort4 r = rect[vN + gid];
+                    hit = tx >= r.x && tx < r.z && ty >= r.y && ty < r.w;
+                }
+                const uint64_t m = ballot64(hit);
+                if (hit) cq[cn + __popcll(m & ltmask)] = gid;
+                cn += __popcll(m);
+                if (STATS) n_refill += 1;
             }
-            const uint64_t m = ballot64(hit);
-            if (hit) qi[qn + __popcll(m & ltmask)] = gid;
+            const int nc = cn < 64 ? cn : 64;
+            bool ok = false;
+            uint32_t cg = 0;
+            if (lane < nc) {
+                cg = cq[lane];
+                ok = splat_reaches_tile(rec[2 * (vN + cg)], rec[2 * (vN + cg) + 1], log_amin, amin, ex0, ex1, ey0,
+                                        ey1);
+            }
+            const uint64_t m = ballot64(ok);
+            if (ok) qi[qn + __popcll(m & ltmask)] = cg;
             qn += __popcll(m);
-            if (STATS) n_refill += 1;
+            if (lane + 64 < cn) cq[lane] = cq[lane + 64];
+            cn -= nc;
         }
         if (qn == 0) break;
         const int nb = qn < 64 ? qn : 64;
