@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
                                                     float* __restrict__ t_final, int32_t* __restrict__ n_proc)
 {
     __shared__ Entry E[256];
+    __shared__ uint32_t C[512];    // candidates passing the rectangle test
     __shared__ uint32_t wcount[4];
     if (*a.overflow) return;
     const int64_t b = blockIdx.x;
@@ -75,32 +76,58 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
     bool done = !inside;
     int32_t nproc = -1;
     uint32_t idx = 0;  // filtered index of the current batch start
-    for (uint32_t pos = rg.x; pos < rg.y; pos += 256) {
-        // cooperative filter of 256 list entries
-        const uint32_t i = pos + t;
-        bool hit = false;
-        uint32_t gid = 0;
-        if (i < rg.y) {
-            gid = a.cell_ids[i];
-            if (gid < (uint64_t)a.N) {
-                const ushort4 r = a.rect[vN + gid];
-                hit = tc.tx >= r.x && tc.tx < r.z && tc.ty >= r.y && tc.ty < r.w;
-                if (hit)
-                    hit = splat_reaches_tile(a.rec[2 * (vN + gid)], a.rec[2 * (vN + gid) + 1], log_amin,
-                                             a.alpha_min, ex0, ex1, ey0, ey1);
-            }
-        }
-        const uint64_t m = ballot64(hit);
+    uint32_t pos = rg.x;
+    uint32_t cn = 0;   // candidates waiting in C (block-uniform)
+    // Two filtering stages, in list order: the rectangle test streams 256
+    // list entries per round into the candidate queue C, and the exact
+    // culling test runs on 256 candidates at a time (one per thread).
+    auto block_compact = [&](bool keep, uint32_t& before, uint32_t& total) {
+        const uint64_t m = ballot64(keep);
         if (lane == 0) wcount[w] = (uint32_t)__popcll(m);
         __syncthreads();
-        uint32_t before = 0, nhit = 0;
+        before = 0;
+        total = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (k < w) before += wcount[k];
-            nhit += wcount[k];
+            total += wcount[k];
         }
-        if (hit) {
-            const uint32_t slot = before + (uint32_t)__popcll(m & ltmask);
+        before += (uint32_t)__popcll(m & ltmask);
+        __syncthreads();
+    };
+    while (pos < rg.y || cn > 0) {
+        while (cn < 256 && pos < rg.y) {
+            const uint32_t i = pos + t;
+            pos += 256;
+            bool hit = false;
+            uint32_t gid = 0;
+            if (i < rg.y) {
+                gid = a.cell_ids[i];
+                if (gid < (uint64_t)a.N) {
+                    const ushort4 r = a.rect[vN + gid];
+                    hit = tc.tx >= r.x && tc.tx < r.z && tc.ty >= r.y && tc.ty < r.w;
+                }
+            }
+            uint32_t before, nhit;
+            block_compact(hit, before, nhit);
+            if (hit) C[cn + before] = gid;
+            cn += nhit;
+            __syncthreads();
+        }
+        const uint32_t nc = cn < 256 ? cn : 256;
+        bool ok = false;
+        uint32_t gid = 0;
+        if ((uint32_t)t < nc) {
+            gid = C[t];
+            ok = splat_reaches_tile(a.rec[2 * (vN + gid)], a.rec[2 * (vN + gid) + 1], log_amin, a.alpha_min, ex0,
+                                    ex1, ey0, ey1);
+        }
+        const uint32_t moved = (uint32_t)t + 256 < cn ? C[t + 256] : 0u;
+        uint32_t slot, nhit;
+        block_compact(ok, slot, nhit);
+        if ((uint32_t)t + 256 < cn) C[t] = moved;
+        cn -= nc;
+        if (ok) {
             const float4 r0 = a.rec[2 * (vN + gid)];
             const float4 r1 = a.rec[2 * (vN + gid) + 1];
             const float* c = a.colors + 3 * (vN + gid);
@@ -150,6 +177,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                                                    const int32_t* __restrict__ n_proc, float* __restrict__ grad2d)
 {
     __shared__ uint32_t qi[QCAP];
+    __shared__ uint32_t cq[QCAP];   // candidates passing the rectangle test
     // per pixel: the colour still to come (final colour minus the front
     // already composited) with the running transmittance, and dL/dC
     __shared__ float4 RT[256];   // remaining colour (r, g, b), T
@@ -195,29 +223,44 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
     }
     float pex_reg = 1.0f;
     const bool lane0 = lane == 0;
-    int qn = 0;
+    int qn = 0, cn = 0;
     uint32_t pos = rg.x;
     uint32_t bstart = 0;  // filtered index of the batch's first entry
 
     while ((alive[0] | alive[1] | alive[2] | alive[3]) != 0ull) {
-        while (qn < 64 && pos < rg.y) {
-            const uint32_t i = pos + lane;
-            pos += 64;
-            bool hit = false;
-            uint32_t gid = 0;
-            if (i < rg.y) {
-                gid = a.cell_ids[i];
-                if (gid < (uint64_t)a.N) {
-                    const ushort4 r = a.rect[vN + gid];
-                    hit = tc.tx >= r.x && tc.tx < r.z && tc.ty >= r.y && tc.ty < r.w;
-                    if (hit)
-                        hit = splat_reaches_tile(a.rec[2 * (vN + gid)], a.rec[2 * (vN + gid) + 1], log_amin, amin,
-                                                 ex0, ex1, ey0, ey1);
+        // two stages, as in the forward's order: the rectangle test streams
+        // the list into a candidate queue, the exact culling test runs on 64
+        // candidates at a time (both queues keep list order)
+        while (qn < 64 && (pos < rg.y || cn > 0)) {
+            while (cn < 64 && pos < rg.y) {
+                const uint32_t i = pos + lane;
+                pos += 64;
+                bool hit = false;
+                uint32_t gid = 0;
+                if (i < rg.y) {
+                    gid = a.cell_ids[i];
+                    if (gid < (uint64_t)a.N) {
+                        const ushort4 r = a.rect[vN + gid];
+                        hit = tc.tx >= r.x && tc.tx < r.z && tc.ty >= r.y && tc.ty < r.w;
+                    }
                 }
+                const uint64_t m = ballot64(hit);
+                if (hit) cq[cn + __popcll(m & ltmask)] = gid;
+                cn += __popcll(m);
             }
-            const uint64_t m = ballot64(hit);
-            if (hit) qi[qn + __popcll(m & ltmask)] = gid;
+            const int nc = cn < 64 ? cn : 64;
+            bool ok = false;
+            uint32_t cg = 0;
+            if (lane < nc) {
+                cg = cq[lane];
+                ok = splat_reaches_tile(a.rec[2 * (vN + cg)], a.rec[2 * (vN + cg) + 1], log_amin, amin, ex0, ex1,
+                                        ey0, ey1);
+            }
+            const uint64_t m = ballot64(ok);
+            if (ok) qi[qn + __popcll(m & ltmask)] = cg;
             qn += __popcll(m);
+            if (lane + 64 < cn) cq[lane] = cq[lane + 64];
+            cn -= nc;
         }
         if (qn == 0) break;
         const int nb = qn < 64 ? qn : 64;
