@@ -225,8 +225,6 @@ k_accumulate(BatchArgs a)
     // pixel-centre extent of the tile (conservative for the ellipse test)
     const float ex0 = (float)px0, ex1 = (float)(px0 + TG_TILE - 1);
     const float ey0 = (float)py0, ey1 = (float)(py0 + TG_TILE - 1);
-    // prefetched ids of the next 64 list entries
-    uint32_t nid = (pos + lane < rg.y) ? cell_ids[pos + lane] : 0xFFFFFFFFu;
 
     while ((alive[0] | alive[1] | alive[2] | alive[3]) != 0ull) {
         // Refill: list entries whose rectangle contains this tile and whose
@@ -239,20 +237,35 @@ k_accumulate(BatchArgs a)
         // a candidate queue, and the exact test runs on 64 candidates at a
         // time.  Both queues keep list order.
         while (qn < 64 && (pos < rg.y || cn > 0)) {
-            while (cn < 64 && pos < rg.y) {
-                const uint32_t gid = nid;
-                const uint32_t i = pos + lane;
-                pos += 64;
-                nid = (pos + lane < rg.y) ? cell_ids[pos + lane] : 0xFFFFFFFFu;
-                bool hit = false;
-                if (i < rg.y && gid < (uint64_t)N) {
-                    const ushort4 r = rect[vN + gid];
-                    hit = tx >= r.x && tx < r.z && ty >= r.y && ty < r.w;
+            if (cn < 64 && pos < rg.y) {
+                // a two-deep pipeline: the ids two rounds ahead and the
+                // rectangles one round ahead are in flight while a round is
+                // tested (entries fetched past the stopping point are read
+                // again by the next refill)
+                auto id_at = [&](uint32_t p) -> uint32_t {
+                    const uint32_t g = p + lane < rg.y ? cell_ids[p + lane] : 0xFFFFFFFFu;
+                    return g < (uint64_t)N ? g : 0xFFFFFFFFu;
+                };
+                auto rect_of = [&](uint32_t g) -> ushort4 {
+                    return g != 0xFFFFFFFFu ? rect[vN + g] : make_ushort4(0, 0, 0, 0);
+                };
+                uint32_t id0 = id_at(pos);
+                ushort4 r0 = rect_of(id0);
+                uint32_t id1 = id_at(pos + 64);
+                while (true) {
+                    const ushort4 r1 = rect_of(id1);
+                    const uint32_t id2 = id_at(pos + 128);
+                    const bool hit = tx >= r0.x && tx < r0.z && ty >= r0.y && ty < r0.w;
+                    const uint64_t m = ballot64(hit);
+                    if (hit) cq[cn + __popcll(m & ltmask)] = id0;
+                    cn += __popcll(m);
+                    pos += 64;
+                    if (STATS) n_refill += 1;
+                    if (!(cn < 64 && pos < rg.y)) break;
+                    id0 = id1;
+                    r0 = r1;
+                    id1 = id2;
                 }
-                const uint64_t m = ballot64(hit);
-                if (hit) cq[cn + __popcll(m & ltmask)] = gid;
-                cn += __popcll(m);
-                if (STATS) n_refill += 1;
             }
             const int nc = cn < 64 ? cn : 64;
             bool ok = false;
