@@ -96,23 +96,34 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
         __syncthreads();
     };
     while (pos < rg.y || cn > 0) {
-        while (cn < 256 && pos < rg.y) {
-            const uint32_t i = pos + t;
-            pos += 256;
-            bool hit = false;
-            uint32_t gid = 0;
-            if (i < rg.y) {
-                gid = a.cell_ids[i];
-                if (gid < (uint64_t)a.N) {
-                    const ushort4 r = a.rect[vN + gid];
-                    hit = tc.tx >= r.x && tc.tx < r.z && tc.ty >= r.y && tc.ty < r.w;
-                }
+        if (cn < 256 && pos < rg.y) {
+            // pipelined: the next round's ids and rectangles are in flight
+            // while a round is tested
+            auto id_at = [&](uint32_t p) -> uint32_t {
+                const uint32_t g = p + t < rg.y ? a.cell_ids[p + t] : 0xFFFFFFFFu;
+                return g < (uint64_t)a.N ? g : 0xFFFFFFFFu;
+            };
+            auto rect_of = [&](uint32_t g) -> ushort4 {
+                return g != 0xFFFFFFFFu ? a.rect[vN + g] : make_ushort4(0, 0, 0, 0);
+            };
+            uint32_t id0 = id_at(pos);
+            ushort4 r0 = rect_of(id0);
+            uint32_t id1 = id_at(pos + 256);
+            while (true) {
+                const ushort4 r1 = rect_of(id1);
+                const uint32_t id2 = id_at(pos + 512);
+                const bool hit = tc.tx >= r0.x && tc.tx < r0.z && tc.ty >= r0.y && tc.ty < r0.w;
+                uint32_t before, nhit;
+                block_compact(hit, before, nhit);
+                if (hit) C[cn + before] = id0;
+                cn += nhit;
+                pos += 256;
+                __syncthreads();
+                if (!(cn < 256 && pos < rg.y)) break;
+                id0 = id1;
+                r0 = r1;
+                id1 = id2;
             }
-            uint32_t before, nhit;
-            block_compact(hit, before, nhit);
-            if (hit) C[cn + before] = gid;
-            cn += nhit;
-            __syncthreads();
         }
         const uint32_t nc = cn < 256 ? cn : 256;
         bool ok = false;
@@ -232,21 +243,31 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
         // the list into a candidate queue, the exact culling test runs on 64
         // candidates at a time (both queues keep list order)
         while (qn < 64 && (pos < rg.y || cn > 0)) {
-            while (cn < 64 && pos < rg.y) {
-                const uint32_t i = pos + lane;
-                pos += 64;
-                bool hit = false;
-                uint32_t gid = 0;
-                if (i < rg.y) {
-                    gid = a.cell_ids[i];
-                    if (gid < (uint64_t)a.N) {
-                        const ushort4 r = a.rect[vN + gid];
-                        hit = tc.tx >= r.x && tc.tx < r.z && tc.ty >= r.y && tc.ty < r.w;
-                    }
+            if (cn < 64 && pos < rg.y) {
+                // pipelined two rounds deep, as in the accumulation
+                auto id_at = [&](uint32_t p) -> uint32_t {
+                    const uint32_t g = p + lane < rg.y ? a.cell_ids[p + lane] : 0xFFFFFFFFu;
+                    return g < (uint64_t)a.N ? g : 0xFFFFFFFFu;
+                };
+                auto rect_of = [&](uint32_t g) -> ushort4 {
+                    return g != 0xFFFFFFFFu ? a.rect[vN + g] : make_ushort4(0, 0, 0, 0);
+                };
+                uint32_t id0 = id_at(pos);
+                ushort4 r0 = rect_of(id0);
+                uint32_t id1 = id_at(pos + 64);
+                while (true) {
+                    const ushort4 r1 = rect_of(id1);
+                    const uint32_t id2 = id_at(pos + 128);
+                    const bool hit = tc.tx >= r0.x && tc.tx < r0.z && tc.ty >= r0.y && tc.ty < r0.w;
+                    const uint64_t m = ballot64(hit);
+                    if (hit) cq[cn + __popcll(m & ltmask)] = id0;
+                    cn += __popcll(m);
+                    pos += 64;
+                    if (!(cn < 64 && pos < rg.y)) break;
+                    id0 = id1;
+                    r0 = r1;
+                    id1 = id2;
                 }
-                const uint64_t m = ballot64(hit);
-                if (hit) cq[cn + __popcll(m & ltmask)] = gid;
-                cn += __popcll(m);
             }
             const int nc = cn < 64 ? cn : 64;
             bool ok = false;
