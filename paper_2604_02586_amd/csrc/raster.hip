@@ -309,7 +309,9 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
         qn -= nb;
         const float ca = -0.5f * LOG2E * A, cb = -LOG2E * B, cc = -0.5f * LOG2E * C;
 
-        float g_mx = 0.f, g_my = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f;
+        // per lane: sums over pixels of dpow u (s_x, s_y) and dpow u u^T
+        // (s_xx, s_xy, s_yy), and the opacity and colour gradients
+        float s_x = 0.f, s_y = 0.f, s_xx = 0.f, s_xy = 0.f, s_yy = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f;
         const float fx0 = (float)px0;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -337,6 +339,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 const uint32_t nfw = (uint32_t)np - bstart;
                 const uint64_t fwm = nfw >= 64u ? ~0ull : ((1ull << nfw) - 1ull);
                 const uint64_t vm = ballot64(p2 <= 0.0f) & ballot64(al >= amin) & fwm;
+                if (vm == 0ull) continue;   // no lane reaches the pixel: nothing changes
                 const bool valid = __builtin_amdgcn_inverse_ballot_w64(vm);
                 float P = valid ? 1.0f - al : 1.0f;
                 P = wave_scan_mul_fused(P);
@@ -360,13 +363,17 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                     g_g += gf.y * wgt;
                     g_b += gf.z * wgt;
                     if (e2 < amax) {  // not clamped: alpha = o e^power
+                        // d power = dL/dalpha * alpha; the centre and conic
+                        // gradients are linear in the moments of u = p - mu
+                        // weighted by it, combined with the conic at the end
                         const float dpow = dal * al;
                         g_o += dal * ex;   // d alpha / d o = e^power when not clamped
-                        g_mx += dpow * (A * ux + B * uy);
-                        g_my += dpow * (C * uy + B * ux);
-                        g_A += dpow * (-0.5f * ux * ux);
-                        g_B += dpow * (-ux * uy);
-                        g_C += dpow * (-0.5f * uy * uy);
+                        const float tx = dpow * ux, ty = dpow * uy;
+                        s_x += tx;
+                        s_y += ty;
+                        s_xx += tx * ux;
+                        s_xy += tx * uy;
+                        s_yy += ty * uy;
                     }
                 }
                 // advance this pixel's transmittance and remaining colour
@@ -379,11 +386,12 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
         }
         if (lane < nb) {
             float* dst = grad2d + (vN + gid) * 9;
-            unsafeAtomicAdd(dst + 0, g_mx);
-            unsafeAtomicAdd(dst + 1, g_my);
-            unsafeAtomicAdd(dst + 2, g_A);
-            unsafeAtomicAdd(dst + 3, g_B);
-            unsafeAtomicAdd(dst + 4, g_C);
+            // power = -1/2 (A ux^2 + C uy^2) - B ux uy with u = p - mu
+            unsafeAtomicAdd(dst + 0, A * s_x + B * s_y);
+            unsafeAtomicAdd(dst + 1, C * s_y + B * s_x);
+            unsafeAtomicAdd(dst + 2, -0.5f * s_xx);
+            unsafeAtomicAdd(dst + 3, -s_xy);
+            unsafeAtomicAdd(dst + 4, -0.5f * s_yy);
             unsafeAtomicAdd(dst + 5, g_o);
             unsafeAtomicAdd(dst + 6, g_r);
             unsafeAtomicAdd(dst + 7, g_g);
