@@ -14,12 +14,19 @@
 //                   solved Gaussians sorted by the Morton code of their finest
 //                   cell, so every cell of every level is one contiguous run;
 //                   per-level cell ranges and the sorted positions as float4.
+//   k_reg_qkeys + radix sort, k_reg_wkeys + radix sort
+//                   the queries (all non-static Gaussians) in Morton order of
+//                   their grid cell, so a wave's queries are neighbours; the
+//                   waves with queries far from every solved Gaussian (the
+//                   longest searches) launched first.
 //   k_reg_knn       per non-static Gaussian: exact K nearest solved Gaussians
-//                   by a best-first descent of the implicit octree formed by
-//                   the levels (FP64 distances, ties by index, boxes farther
-//                   than the current K-th neighbour pruned), so queries far
+//                   (FP64 distances, ties by index); a wave answers 64
+//                   neighbouring queries with one best-first descent of the
+//                   implicit octree formed by the levels, pruning boxes
+//                   farther from the queries' bounding box than the wave's
+//                   largest current K-th neighbour distance, so queries far
 //                   from every solved Gaussian (the occluded interior of a
-//                   scene, say) cost about as much as queries among them.
+//                   scene, say) share one traversal instead of diverging.
 //   k_reg_filter    per solved Gaussian: component-wise median of its
 //                   neighbours' changes (itself included).
 //   k_reg_apply     per Gaussian: static -> first frame; solved -> first
@@ -139,6 +146,8 @@ struct RegArgs {
     const uint32_t* skeys;   // [N] sorted
     const uint32_t* svals;   // [N] Gaussian index of each sorted key
     uint2* ranges;     // [RANGES_MAX] cell ranges of every level
+    const uint32_t* qorder;  // [N] Gaussians in the neighbour search's order
+    const uint32_t* worder;  // [ceil(N / 64)] groups of 64 queries in launch order
     float4* spos;      // [N] sorted positions, index bits in w
     GridInfo* grid;
 };
@@ -250,6 +259,54 @@ __global__ void __launch_bounds__(256) k_reg_keys(RegArgs a) {
     a.keys[g] = key;
 }
 
+// Query order for the neighbour search: every non-static Gaussian by the
+// Morton code of the finest cell it falls in (clamped to the grid), so the
+// 64 queries of a wave are spatial neighbours and walk the same octree nodes.
+// Static Gaussians sort last.
+__global__ void __launch_bounds__(256) k_reg_qkeys(RegArgs a) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.N) return;
+    uint32_t key = KEY_NONE;
+    const GridInfo& gi = *a.grid;
+    if (a.cls[g] != CLS_STATIC && gi.n_src > 0) {
+        const int dim = 1 << gi.B;
+        const int cx = cell_coord(a.m0[3 * g], gi.lo[0], gi.inv_h, dim);
+        const int cy = cell_coord(a.m0[3 * g + 1], gi.lo[1], gi.inv_h, dim);
+        const int cz = cell_coord(a.m0[3 * g + 2], gi.lo[2], gi.inv_h, dim);
+        key = morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
+    }
+    a.keys[g] = key;
+}
+
+// Launch order of the neighbour search's waves (groups of 64 consecutive
+// queries): by the level of the smallest cell around a query that holds K
+// solved Gaussians, the largest over the group, largest first (stable).
+// Queries far from every solved Gaussian have the longest searches; starting
+// their waves first keeps them off the end of the launch.
+__global__ void __launch_bounds__(256) k_reg_wkeys(RegArgs a, int64_t n_groups) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_groups) return;
+    const GridInfo& gi = *a.grid;
+    const uint32_t K = (uint32_t)a.K < gi.n_src ? (uint32_t)a.K : gi.n_src;
+    const int dim = 1 << gi.B;
+    int deepest = -1;
+    for (int64_t i = w * 64; i < a.N && i < (w + 1) * 64; ++i) {
+        const int64_t g = a.qorder[i];
+        if (a.cls[g] == CLS_STATIC || K == 0) continue;
+        const int cx = cell_coord(a.m0[3 * g], gi.lo[0], gi.inv_h, dim);
+        const int cy = cell_coord(a.m0[3 * g + 1], gi.lo[1], gi.inv_h, dim);
+        const int cz = cell_coord(a.m0[3 * g + 2], gi.lo[2], gi.inv_h, dim);
+        const uint32_t code = morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
+        int L = 0;
+        for (; L < gi.B; ++L) {
+            const uint2 r = a.ranges[gi.lvl_off[L] + (code >> (3 * L))];
+            if (r.y - r.x >= K) break;
+        }
+        deepest = L > deepest ? L : deepest;
+    }
+    a.keys[w] = deepest < 0 ? 0xFFu : (uint32_t)(BMAX - deepest);
+}
+
 __global__ void __launch_bounds__(256) k_fill_ranges(uint2* r, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) r[i] = make_uint2(0u, 0u);
@@ -273,19 +330,6 @@ __global__ void __launch_bounds__(256) k_reg_cells(RegArgs a) {
     a.spos[i] = make_float4(a.m0[3 * g], a.m0[3 * g + 1], a.m0[3 * g + 2], __builtin_bit_cast(float, g));
 }
 
-// insert (d2, id) into the sorted top list (ascending by d2, then id)
-__device__ __forceinline__ void topk_insert(double* bd, uint32_t* bi, int& cnt, int K, double d2, uint32_t id) {
-    if (cnt == K && !(d2 < bd[K - 1] || (d2 == bd[K - 1] && id < bi[K - 1]))) return;
-    int j = cnt < K ? cnt++ : K - 1;
-    while (j > 0 && (d2 < bd[j - 1] || (d2 == bd[j - 1] && id < bi[j - 1]))) {
-        bd[j] = bd[j - 1];
-        bi[j] = bi[j - 1];
-        --j;
-    }
-    bd[j] = d2;
-    bi[j] = id;
-}
-
 // Morton code -> one coordinate (every third bit)
 __device__ __forceinline__ uint32_t compact1by2(uint32_t x) {
     x &= 0x9249249u;
@@ -296,90 +340,257 @@ __device__ __forceinline__ uint32_t compact1by2(uint32_t x) {
     return x;
 }
 
-// squared distance from p to the box of cell `code` at level L (FP64)
-__device__ __forceinline__ double box_dist2(const GridInfo& gi, int L, uint32_t code, const double p[3]) {
-    const double hL = gi.h * (double)(1 << L);
+// squared distance between the box of cell `code` at level L (finest cells
+// of size h from the corner lo) and the box [qlo, qhi] (FP64)
+__device__ __forceinline__ double box_box_dist2(const double lo[3], double h, int L, uint32_t code,
+                                                const double qlo[3], const double qhi[3]) {
+    const double hL = h * (double)(1 << L);
     const uint32_t c[3] = {compact1by2(code), compact1by2(code >> 1), compact1by2(code >> 2)};
     double d2 = 0.0;
     for (int ax = 0; ax < 3; ++ax) {
-        const double lo = (double)gi.lo[ax] + c[ax] * hL, hi = lo + hL;
-        const double d = p[ax] < lo ? lo - p[ax] : (p[ax] > hi ? p[ax] - hi : 0.0);
+        const double blo = lo[ax] + c[ax] * hL, bhi = blo + hL;
+        const double d = fmax(0.0, fmax(blo - qhi[ax], qlo[ax] - bhi));
         d2 += d * d;
     }
     return d2;
 }
 
-constexpr int KNN_THREADS = 128;
-constexpr int STACK = 64;      // >= 1 + 7 B entries for B <= 7
-constexpr uint32_t LEAF = 16;  // scan a cell's points directly at or below this count
+// (d, i) before (e, j): by distance, ties by index
+__device__ __forceinline__ bool nb_before(double d, uint32_t i, double e, uint32_t j) {
+    return d < e || (d == e && i < j);
+}
 
-__global__ void __launch_bounds__(KNN_THREADS) k_reg_knn(RegArgs a) {
-    // Best-first descent of the implicit octree (cells of every level are
-    // Morton runs): a node is skipped when its box is farther than the
-    // current K-th neighbour, children are visited nearest first.  Boxes are
-    // widened by a margin because cells were assigned in FP32.
-    __shared__ uint32_t stk[KNN_THREADS * STACK];
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.N) return;
-    if (a.cls[g] == CLS_STATIC) {
-        a.ncnt[g] = 0;
-        return;
+// sorted insert into the KMAX best (d, i) so far; fully unrolled, so the
+// lists stay in registers
+__device__ __forceinline__ void nb_insert(double (&bd)[KMAX], uint32_t (&bi)[KMAX], double d, uint32_t id) {
+#pragma unroll
+    for (int k = KMAX - 1; k >= 0; --k) {
+        const bool here = nb_before(d, id, bd[k], bi[k]);
+        const bool prev = k > 0 && nb_before(d, id, bd[k > 0 ? k - 1 : 0], bi[k > 0 ? k - 1 : 0]);
+        if (here) {
+            bd[k] = prev ? bd[k > 0 ? k - 1 : 0] : d;
+            bi[k] = prev ? bi[k > 0 ? k - 1 : 0] : id;
+        }
     }
+}
+
+__device__ __forceinline__ float bcast_f32(float x, uint32_t l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), (int)l));
+}
+
+__device__ __forceinline__ double bcast_f64(double x, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// largest value over the wave (DPP: prefix max within rows of 16, then the
+// row maxima carried by row broadcasts to lane 63)
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x111, 0xf, 0xf, false));   // row_shr:1
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x112, 0xf, 0xf, false));   // row_shr:2
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x114, 0xf, 0xf, false));   // row_shr:4
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x118, 0xf, 0xf, false));   // row_shr:8
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// an FP32 value at least x >= 0
+__device__ __forceinline__ float f32_up(double x) {
+    const float f = (float)x;
+    // below x: f is finite and non-negative, the next FP32 value is one up in its bits
+    return (double)f < x ? __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u) : f;
+}
+
+__device__ __forceinline__ float wave_min_f32(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    return x;
+}
+
+// FP32 screen of a squared distance against the K-th (FP64) wd: the FP32
+// value of dx^2 + dy^2 + dz^2 from FP32 differences is within 5 units of
+// 2^-24 (relative) of the exact one, plus a few units of 2^-149 where
+// values are subnormal, so a point whose FP64 distance is at most wd has an
+// FP32 distance at most wd (1 + 2^-18) rounded to FP32, plus 2^-126.
+__device__ __forceinline__ float screen_bound(double wd) {
+    return (float)(wd * (1.0 + 0x1p-18)) + 0x1p-126f;
+}
+
+// padding of a leaf chunk: infinitely far, index above every Gaussian's
+constexpr uint32_t PAD_ID_U = 0xFFFFFFFFu;
+#define PAD_ID __builtin_bit_cast(float, PAD_ID_U)
+
+// first range entry of level L for 2^B finest cells per axis: the levels
+// below hold 8^B + 8^(B-1) + ... + 8^(B-L+1) cells
+__device__ __forceinline__ uint32_t level_offset(int B, int L) {
+    return ((1u << (3 * (B + 1))) - (1u << (3 * (B + 1 - L)))) / 7u;
+}
+
+constexpr int KNN_WAVES = 4;   // independent waves per block
+constexpr int STACK = 64;      // a descent of BMAX levels leaves at most 1 + 7 BMAX nodes
+static_assert(STACK >= 1 + 7 * BMAX, "neighbour-search stack too small");
+constexpr uint32_t LEAF = 256; // scan a cell's points directly at or below this count
+constexpr int HEAVY_NODES = 64;   // a wave past this many nodes raises its issue priority
+constexpr int SCREEN = 8;      // leaf points screened together (divides 64)
+
+__global__ void __launch_bounds__(64 * KNN_WAVES) k_reg_knn(RegArgs a) {
+    // One wave answers 64 consecutive queries of the Morton order (spatial
+    // neighbours) with one shared best-first descent of the implicit octree
+    // (cells of every level are Morton runs): a node is skipped when its box
+    // is farther from the queries' bounding box than the largest current
+    // K-th neighbour distance of the wave, children are visited nearest
+    // first, and every point of a visited leaf is offered to every lane.
+    // The skipped points are farther than each lane's K-th neighbour, so
+    // every lane's result is its exact K nearest.  Boxes are widened by a
+    // margin because cells were assigned in FP32.
+    __shared__ uint4 stk_all[KNN_WAVES][STACK];
+    __shared__ float4 pts_all[KNN_WAVES][64];
+    const uint32_t lane = threadIdx.x & 63;
+    uint4* stk = stk_all[threadIdx.x >> 6];
+    float4* pts = pts_all[threadIdx.x >> 6];
+    const int64_t wave = (int64_t)blockIdx.x * KNN_WAVES + (threadIdx.x >> 6);
+    if (wave >= (a.N + 63) / 64) return;   // wave-uniform
+    const int64_t qi = (int64_t)a.worder[wave] * 64 + lane;
     const GridInfo& gi = *a.grid;
     const int K = (int)((uint32_t)a.K < gi.n_src ? (uint32_t)a.K : gi.n_src);
-    if (K == 0) {
-        a.ncnt[g] = 0;
-        return;
+    int64_t g = -1;
+    if (qi < a.N) {
+        g = a.qorder[qi];
+        if (a.cls[g] == CLS_STATIC || K == 0) {
+            a.ncnt[g] = 0;
+            g = -1;
+        }
     }
-    const double p[3] = {a.m0[3 * g], a.m0[3 * g + 1], a.m0[3 * g + 2]};
-    const double margin = 1e-3 * gi.h;
-    uint32_t* st = stk + threadIdx.x * STACK;
+    const bool act = g >= 0;
+    if (__ballot(act) == 0ull) return;   // wave-uniform
+    double p[3], qlo[3], qhi[3];
+    float pf[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const float x = act ? a.m0[3 * g + ax] : 0.0f;
+        pf[ax] = x;
+        p[ax] = x;
+        qlo[ax] = wave_min_f32(act ? x : INFINITY);
+        qhi[ax] = -wave_min_f32(act ? -x : INFINITY);
+    }
+    // grid in registers (the loop's wave barriers would reload it from memory)
+    const double gh = gi.h, glo[3] = {gi.lo[0], gi.lo[1], gi.lo[2]};
+    const double margin = 1e-3 * gh;
+    // every active lane's K-th neighbour distance^2 is at most R2 (wave-uniform);
+    // pruned: a box at distance^2 d2 (to the queries' box) with d2 > Rm2 =
+    // (sqrt(R2) + margin)^2, raised by 2^-40 for the rounding of this bound
+    double Rm2 = INFINITY;
+    auto pruned = [&](double d2) { return d2 > Rm2; };
+    // the K best so far (the first K of KMAX sorted entries) and the K-th
     double bd[KMAX];
     uint32_t bi[KMAX];
-    int cnt = 0;
-    int sp = 0;
-    st[sp++] = ((uint32_t)gi.B << 24);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        bd[k] = INFINITY;
+        bi[k] = 0xFFFFFFFFu;
+    }
+    double wd = INFINITY;
+    uint32_t wi = 0xFFFFFFFFu;
+    float wdf = INFINITY;
+    // stack entries: node (level << 24 | Morton code), its point range and
+    // its box distance^2 to the queries' box rounded toward zero
+    const int B = gi.B;
+    if (lane == 0) {
+        const uint2 r0 = a.ranges[level_offset(B, B)];
+        stk[0] = make_uint4((uint32_t)B << 24, r0.x, r0.y, 0u);
+    }
+    int sp = 1, visited = 0;
     while (sp > 0) {
-        const uint32_t node = st[--sp];
+        __builtin_amdgcn_wave_barrier();
+        const uint4 e = stk[--sp];
+        const uint32_t node = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.x);
+        const uint2 rg = make_uint2((uint32_t)__builtin_amdgcn_readfirstlane((int)e.y),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)e.z));
+        if (pruned((double)__builtin_bit_cast(float, __builtin_amdgcn_readfirstlane((int)e.w)))) continue;
         const int L = (int)(node >> 24);
         const uint32_t code = node & 0xFFFFFFu;
-        const uint2 rg = a.ranges[gi.lvl_off[L] + code];
-        if (rg.y <= rg.x) continue;
-        if (cnt == K) {
-            const double dn = sqrt(box_dist2(gi, L, code, p)) - margin;
-            if (dn > 0.0 && dn * dn > bd[K - 1]) continue;
-        }
+        // the few long searches (queries far from every solved Gaussian) set
+        // the launch's length: let them issue ahead of the short ones
+        if (++visited == HEAVY_NODES) __builtin_amdgcn_s_setprio(2);
         if (L == 0 || rg.y - rg.x <= LEAF) {
-            for (uint32_t i = rg.x; i < rg.y; ++i) {
-                const float4 q = a.spos[i];
-                const double dx = (double)q.x - p[0], dy = (double)q.y - p[1], dz = (double)q.z - p[2];
-                topk_insert(bd, bi, cnt, K, dx * dx + dy * dy + dz * dz, __builtin_bit_cast(uint32_t, q.w));
+            // the leaf's points in chunks of 64 through LDS, read back by
+            // every lane SCREEN at a time (broadcast reads); an FP32 screen
+            // (never below the FP64 distance, see wdf) sends the few points
+            // that may enter a list to the exact FP64 test
+            for (uint32_t b = rg.x; b < rg.y; b += 64) {
+                const uint32_t m = rg.y - b < 64u ? rg.y - b : 64u;
+                pts[lane] = lane < m ? a.spos[b + lane] : make_float4(INFINITY, INFINITY, INFINITY, PAD_ID);
+                __builtin_amdgcn_wave_barrier();
+                for (uint32_t t = 0; t < m; t += SCREEN) {
+                    bool hit = false;
+#pragma unroll
+                    for (int u = 0; u < SCREEN; ++u) {
+                        const float4 c = pts[t + u];
+                        const float dx = c.x - pf[0], dy = c.y - pf[1], dz = c.z - pf[2];
+                        hit |= dx * dx + dy * dy + dz * dz <= wdf;
+                    }
+                    if (act && hit) {
+#pragma unroll 1
+                        for (int u = 0; u < SCREEN; ++u) {
+                            const float4 cu = pts[t + u];
+                            const double dx = (double)cu.x - p[0], dy = (double)cu.y - p[1], dz = (double)cu.z - p[2];
+                            const double d2 = dx * dx + dy * dy + dz * dz;
+                            const uint32_t id = __builtin_bit_cast(uint32_t, cu.w);
+                            if (nb_before(d2, id, wd, wi)) {
+                                nb_insert(bd, bi, d2, id);
+#pragma unroll
+                                for (int k = 0; k < KMAX; ++k)
+                                    if (k == K - 1) {
+                                        wd = bd[k];
+                                        wi = bi[k];
+                                    }
+                                wdf = screen_bound(wd);
+                            }
+                        }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            // (non-negative FP32 values order as their bit patterns)
+            const double R2 = (double)__builtin_bit_cast(
+                float, wave_max_u32(__builtin_bit_cast(uint32_t, act ? f32_up(wd) : 0.0f)));
+            if (R2 < INFINITY) {
+                const double r = sqrt(R2) + margin;
+                Rm2 = r * r * (1.0 + 0x1p-40);
             }
             continue;
         }
-        // children, pushed farthest first so the nearest is visited next
-        double cd[8];
-        uint32_t cc[8];
-        int nc = 0;
-        const uint2* rc = a.ranges + gi.lvl_off[L - 1];
-        for (uint32_t k = 0; k < 8; ++k) {
-            const uint32_t ch = (code << 3) | k;
-            const uint2 r2 = rc[ch];
-            if (r2.y <= r2.x) continue;
-            const double d2 = box_dist2(gi, L - 1, ch, p);
-            int j = nc++;
-            while (j > 0 && cd[j - 1] < d2) {   // descending by distance
-                cd[j] = cd[j - 1];
-                cc[j] = cc[j - 1];
-                --j;
+        // children on lanes 0..7, pushed farthest first so the nearest is
+        // visited next (ties by child number)
+        const uint2* rc = a.ranges + level_offset(B, L - 1);
+        const uint32_t ch = (code << 3) | (lane & 7u);
+        bool ok = false;
+        double cd = INFINITY;
+        uint2 r2 = make_uint2(0u, 0u);
+        if (lane < 8) {
+            r2 = rc[ch];
+            if (r2.y > r2.x) {
+                cd = box_box_dist2(glo, gh, L - 1, ch, qlo, qhi);
+                ok = !pruned(cd);
             }
-            cd[j] = d2;
-            cc[j] = ch;
         }
-        for (int k = 0; k < nc && sp < STACK; ++k) st[sp++] = ((uint32_t)(L - 1) << 24) | cc[k];
+        const uint64_t okm = __ballot(ok);
+        const int nc = __popcll(okm);
+        int rank = 0;
+        for (int j = 0; j < 8; ++j) {
+            const double dj = bcast_f64(cd, j);
+            rank += (((okm >> j) & 1ull) && (dj < cd || (dj == cd && j < (int)lane))) ? 1 : 0;
+        }
+        if (ok)
+            stk[sp + nc - 1 - rank] = make_uint4(((uint32_t)(L - 1) << 24) | ch, r2.x, r2.y,
+                                                 __builtin_bit_cast(uint32_t, __double2float_rz(cd)));
+        sp += nc;
     }
-    for (int k = 0; k < K; ++k) a.nbr[g * KMAX + k] = bi[k];
-    a.ncnt[g] = (uint8_t)K;
+    if (act) {
+        for (int k = 0; k < K; ++k) a.nbr[g * KMAX + k] = bi[k];
+        a.ncnt[g] = (uint8_t)K;
+    }
 }
 
 __global__ void __launch_bounds__(128) k_reg_filter(RegArgs a) {
@@ -529,6 +740,8 @@ extern "C" tg_status tg_regularize(const tg_gaussians* g_ref, const tg_gaussians
     a.ranges = (uint2*)(w + L.ranges);
     a.spos = (float4*)(w + L.spos);
     a.grid = (GridInfo*)(w + L.grid);
+    a.qorder = nullptr;
+    a.worder = nullptr;
     hipStream_t s = (hipStream_t)stream;
     const unsigned b256 = (unsigned)((N + 255) / 256), b128 = (unsigned)((N + 127) / 128);
     hipLaunchKernelGGL(k_reg_init, dim3(1), dim3(1), 0, s, a.grid);
@@ -543,7 +756,25 @@ extern "C" tg_status tg_regularize(const tg_gaussians* g_ref, const tg_gaussians
     hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)((RANGES_MAX + 255) / 256)), dim3(256), 0, s, a.ranges,
                        (int64_t)RANGES_MAX);
     hipLaunchKernelGGL(k_reg_cells, dim3(b256), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_reg_knn, dim3(b128), dim3(KNN_THREADS), 0, s, a);
+    // queries in Morton order (the sorted sources' buffers are free now:
+    // the search reads the cell ranges and the sorted positions)
+    hipLaunchKernelGGL(k_reg_qkeys, dim3(b256), dim3(256), 0, s, a);
+    TG_CHECK_LAUNCH();
+    st = tg_radix_sort(a.keys, nullptr, (uint32_t*)(w + L.ka), (uint32_t*)(w + L.va), (uint32_t*)(w + L.kb),
+                       (uint32_t*)(w + L.vb), nullptr, (uint32_t*)(w + L.vf), N, 1, nullptr, 0, SORT_PASSES,
+                       w + L.sort, s);
+    if (st != TG_OK) return st;
+    a.qorder = (const uint32_t*)(w + L.vf);
+    const int64_t n_groups = (N + 63) / 64;
+    hipLaunchKernelGGL(k_reg_wkeys, dim3((unsigned)((n_groups + 255) / 256)), dim3(256), 0, s, a, n_groups);
+    TG_CHECK_LAUNCH();
+    st = tg_radix_sort(a.keys, nullptr, (uint32_t*)(w + L.ka), (uint32_t*)(w + L.va), (uint32_t*)(w + L.kb),
+                       (uint32_t*)(w + L.vb), nullptr, (uint32_t*)(w + L.kf), n_groups, 1, nullptr, 0, 1,
+                       w + L.sort, s);
+    if (st != TG_OK) return st;
+    a.worder = (const uint32_t*)(w + L.kf);
+    hipLaunchKernelGGL(k_reg_knn, dim3((unsigned)((N + 64 * KNN_WAVES - 1) / (64 * KNN_WAVES))),
+                       dim3(64 * KNN_WAVES), 0, s, a);
     hipLaunchKernelGGL(k_reg_filter, dim3(b128), dim3(128), 0, s, a);
     hipLaunchKernelGGL(k_reg_apply, dim3(b128), dim3(128), 0, s, a);
     TG_CHECK_LAUNCH();
