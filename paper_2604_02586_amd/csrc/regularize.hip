@@ -27,7 +27,7 @@
 //                   largest current K-th neighbour distance, so queries far
 //                   from every solved Gaussian (the occluded interior of a
 //                   scene, say) share one traversal instead of diverging.
-//   k_reg_filter    per solved Gaussian: component-wise median of its
+//   k_reg_filter    per solved Gaussian (in Morton order): component-wise median of its
 //                   neighbours' changes (itself included).
 //   k_reg_apply     per Gaussian: static -> first frame; solved -> first
 //                   frame + filtered change; other -> first frame + mean of
@@ -278,35 +278,6 @@ __global__ void __launch_bounds__(256) k_reg_qkeys(RegArgs a) {
     a.keys[g] = key;
 }
 
-// Launch order of the neighbour search's waves (groups of 64 consecutive
-// queries): by the level of the smallest cell around a query that holds K
-// solved Gaussians, the largest over the group, largest first (stable).
-// Queries far from every solved Gaussian have the longest searches; starting
-// their waves first keeps them off the end of the launch.
-__global__ void __launch_bounds__(256) k_reg_wkeys(RegArgs a, int64_t n_groups) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= n_groups) return;
-    const GridInfo& gi = *a.grid;
-    const uint32_t K = (uint32_t)a.K < gi.n_src ? (uint32_t)a.K : gi.n_src;
-    const int dim = 1 << gi.B;
-    int deepest = -1;
-    for (int64_t i = w * 64; i < a.N && i < (w + 1) * 64; ++i) {
-        const int64_t g = a.qorder[i];
-        if (a.cls[g] == CLS_STATIC || K == 0) continue;
-        const int cx = cell_coord(a.m0[3 * g], gi.lo[0], gi.inv_h, dim);
-        const int cy = cell_coord(a.m0[3 * g + 1], gi.lo[1], gi.inv_h, dim);
-        const int cz = cell_coord(a.m0[3 * g + 2], gi.lo[2], gi.inv_h, dim);
-        const uint32_t code = morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
-        int L = 0;
-        for (; L < gi.B; ++L) {
-            const uint2 r = a.ranges[gi.lvl_off[L] + (code >> (3 * L))];
-            if (r.y - r.x >= K) break;
-        }
-        deepest = L > deepest ? L : deepest;
-    }
-    a.keys[w] = deepest < 0 ? 0xFFu : (uint32_t)(BMAX - deepest);
-}
-
 __global__ void __launch_bounds__(256) k_fill_ranges(uint2* r, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) r[i] = make_uint2(0u, 0u);
@@ -418,6 +389,8 @@ __device__ __forceinline__ float screen_bound(double wd) {
     return (float)(wd * (1.0 + 0x1p-18)) + 0x1p-126f;
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // padding of a leaf chunk: infinitely far, index above every Gaussian's
 constexpr uint32_t PAD_ID_U = 0xFFFFFFFFu;
 #define PAD_ID __builtin_bit_cast(float, PAD_ID_U)
@@ -428,14 +401,45 @@ __device__ __forceinline__ uint32_t level_offset(int B, int L) {
     return ((1u << (3 * (B + 1))) - (1u << (3 * (B + 1 - L)))) / 7u;
 }
 
+// Launch order of the neighbour search's waves (groups of 64 consecutive
+// queries): by the level of the smallest cell around a query that holds K
+// solved Gaussians, the largest over the group, largest first (stable).
+// Queries far from every solved Gaussian have the longest searches; starting
+// their waves first keeps them off the end of the launch.  One wave per group.
+__global__ void __launch_bounds__(256) k_reg_wkeys(RegArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (((i >> 6) << 6) >= a.N) return;   // wave-uniform
+    const GridInfo& gi = *a.grid;
+    const uint32_t K = (uint32_t)a.K < gi.n_src ? (uint32_t)a.K : gi.n_src;
+    uint32_t level = 0;   // deepest level + 1, 0 for no query
+    if (i < a.N && K > 0) {
+        const int64_t g = a.qorder[i];
+        if (a.cls[g] != CLS_STATIC) {
+            const int dim = 1 << gi.B;
+            const int cx = cell_coord(a.m0[3 * g], gi.lo[0], gi.inv_h, dim);
+            const int cy = cell_coord(a.m0[3 * g + 1], gi.lo[1], gi.inv_h, dim);
+            const int cz = cell_coord(a.m0[3 * g + 2], gi.lo[2], gi.inv_h, dim);
+            const uint32_t code = morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
+            int L = 0;
+            for (; L < gi.B; ++L) {
+                const uint2 r = a.ranges[gi.lvl_off[L] + (code >> (3 * L))];
+                if (r.y - r.x >= K) break;
+            }
+            level = (uint32_t)L + 1u;
+        }
+    }
+    level = wave_max_u32(level);
+    if ((threadIdx.x & 63) == 0) a.keys[i >> 6] = level == 0 ? 0xFFu : (uint32_t)(BMAX + 1) - level;
+}
+
 constexpr int KNN_WAVES = 4;   // independent waves per block
 constexpr int STACK = 64;      // a descent of BMAX levels leaves at most 1 + 7 BMAX nodes
 static_assert(STACK >= 1 + 7 * BMAX, "neighbour-search stack too small");
 constexpr uint32_t LEAF = 256; // scan a cell's points directly at or below this count
 constexpr int HEAVY_NODES = 64;   // a wave past this many nodes raises its issue priority
-constexpr int SCREEN = 8;      // leaf points screened together (divides 64)
+constexpr int SCREEN = 4;      // points screened together on the exact pass (divides 64)
 
-__global__ void __launch_bounds__(64 * KNN_WAVES) k_reg_knn(RegArgs a) {
+__global__ void __launch_bounds__(64 * KNN_WAVES) __attribute__((amdgpu_waves_per_eu(4, 8))) k_reg_knn(RegArgs a) {
     // One wave answers 64 consecutive queries of the Morton order (spatial
     // neighbours) with one shared best-first descent of the implicit octree
     // (cells of every level are Morton runs): a node is skipped when its box
@@ -446,10 +450,14 @@ __global__ void __launch_bounds__(64 * KNN_WAVES) k_reg_knn(RegArgs a) {
     // every lane's result is its exact K nearest.  Boxes are widened by a
     // margin because cells were assigned in FP32.
     __shared__ uint4 stk_all[KNN_WAVES][STACK];
-    __shared__ float4 pts_all[KNN_WAVES][64];
+    __shared__ float4 pts_all[KNN_WAVES][64];    // a leaf chunk: positions and indices
+    __shared__ float4 rel_all[KNN_WAVES][64];    // the same relative to o, and |c - o|^2
+    __shared__ float thr_all[KNN_WAVES][64];     // each query's screen threshold
     const uint32_t lane = threadIdx.x & 63;
     uint4* stk = stk_all[threadIdx.x >> 6];
     float4* pts = pts_all[threadIdx.x >> 6];
+    float4* rel = rel_all[threadIdx.x >> 6];
+    float* thr_l = thr_all[threadIdx.x >> 6];
     const int64_t wave = (int64_t)blockIdx.x * KNN_WAVES + (threadIdx.x >> 6);
     if (wave >= (a.N + 63) / 64) return;   // wave-uniform
     const int64_t qi = (int64_t)a.worder[wave] * 64 + lane;
@@ -465,18 +473,54 @@ __global__ void __launch_bounds__(64 * KNN_WAVES) k_reg_knn(RegArgs a) {
     }
     const bool act = g >= 0;
     if (__ballot(act) == 0ull) return;   // wave-uniform
-    double p[3], qlo[3], qhi[3];
+    double qlo[3], qhi[3];
     float pf[3];
     for (int ax = 0; ax < 3; ++ax) {
         const float x = act ? a.m0[3 * g + ax] : 0.0f;
         pf[ax] = x;
-        p[ax] = x;
         qlo[ax] = wave_min_f32(act ? x : INFINITY);
         qhi[ax] = -wave_min_f32(act ? -x : INFINITY);
     }
     // grid in registers (the loop's wave barriers would reload it from memory)
     const double gh = gi.h, glo[3] = {gi.lo[0], gi.lo[1], gi.lo[2]};
     const double margin = 1e-3 * gh;
+    // Matrix-core screen of a leaf chunk: with o the centre of the queries'
+    // box, c' = c - o and q' = q - o in FP32, a 16x16x4 FP32 MFMA forms
+    // |c'|^2 - 2 c'.q' for 16 points x 16 queries, i.e. |c - q|^2 - |q'|^2.
+    // The FP32 roundings of c', q', |c'|^2 and the MFMA sums move this by
+    // less than 2^-17 S^2 with S >= |c'| + |q'| (S from the grid's box and
+    // the queries' box), so thr = wd (1 + 2^-18) - |q'|^2 + 2^-17 S^2
+    // never rejects a point whose FP64 distance is at most wd.
+    const float ofx = 0.5f * ((float)qlo[0] + (float)qhi[0]), ofy = 0.5f * ((float)qlo[1] + (float)qhi[1]),
+                ofz = 0.5f * ((float)qlo[2] + (float)qhi[2]);
+    double slack;
+    {
+        const double ext = gh * (double)(1 << gi.B);
+        const double o3[3] = {ofx, ofy, ofz};
+        double c2 = 0.0, q2 = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            const double c = fmax(fabs(glo[ax] - o3[ax]), fabs(glo[ax] + ext - o3[ax]));
+            const double q = fmax(fabs(qlo[ax] - o3[ax]), fabs(qhi[ax] - o3[ax]));
+            c2 += c * c;
+            q2 += q * q;
+        }
+        const double S = (sqrt(c2) + sqrt(q2)) * (1.0 + 0x1p-20) + 1e-30;
+        slack = 0x1p-17 * S * S;
+    }
+    const float qx = pf[0] - ofx, qy = pf[1] - ofy, qz = pf[2] - ofz;
+    const double qq = (double)(qx * qx + qy * qy + qz * qz);
+    auto screen_thr = [&](double w) {
+        return act ? f32_up(w * (1.0 + 0x1p-18) - qq + slack) : -INFINITY;
+    };
+    // B operands (query columns): lane l holds component l / 16 of
+    // (-2 q', 1) of query 16 qb + l % 16
+    float bq[4];
+    rel[lane] = act ? make_float4(-2.0f * qx, -2.0f * qy, -2.0f * qz, 1.0f) : make_float4(0.f, 0.f, 0.f, 1.0f);
+    thr_l[lane] = screen_thr(INFINITY);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) bq[qb] = ((const float*)&rel[16 * qb + (lane & 15)])[lane >> 4];
+    __builtin_amdgcn_wave_barrier();
     // every active lane's K-th neighbour distance^2 is at most R2 (wave-uniform);
     // pruned: a box at distance^2 d2 (to the queries' box) with d2 > Rm2 =
     // (sqrt(R2) + margin)^2, raised by 2^-40 for the rounding of this bound
@@ -501,6 +545,25 @@ __global__ void __launch_bounds__(64 * KNN_WAVES) k_reg_knn(RegArgs a) {
         stk[0] = make_uint4((uint32_t)B << 24, r0.x, r0.y, 0u);
     }
     int sp = 1, visited = 0;
+    auto is_leaf = [&](int L, uint2 r) { return L == 0 || r.y - r.x <= LEAF; };
+    auto load_chunk = [&](uint32_t b, uint32_t end) {
+        return lane < end - b ? a.spos[b + lane] : make_float4(INFINITY, INFINITY, INFINITY, PAD_ID);
+    };
+    // the first chunk of the leaf on top of the stack, loaded while the
+    // previous leaf's last chunk is screened (pre_tag: that leaf's node,
+    // wave-uniform)
+    float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t pre_tag = 0xFFFFFFFFu;
+    auto prefetch_top = [&]() {
+        if (sp == 0) return;
+        const uint4 t = stk[sp - 1];
+        const uint32_t tn = (uint32_t)__builtin_amdgcn_readfirstlane((int)t.x);
+        const uint2 tr = make_uint2((uint32_t)__builtin_amdgcn_readfirstlane((int)t.y),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)t.z));
+        if (!is_leaf((int)(tn >> 24), tr)) return;
+        pre = load_chunk(tr.x, tr.y - tr.x < 64u ? tr.y : tr.x + 64u);
+        pre_tag = tn;
+    };
     while (sp > 0) {
         __builtin_amdgcn_wave_barrier();
         const uint4 e = stk[--sp];
@@ -513,42 +576,76 @@ __global__ void __launch_bounds__(64 * KNN_WAVES) k_reg_knn(RegArgs a) {
         // the few long searches (queries far from every solved Gaussian) set
         // the launch's length: let them issue ahead of the short ones
         if (++visited == HEAVY_NODES) __builtin_amdgcn_s_setprio(2);
-        if (L == 0 || rg.y - rg.x <= LEAF) {
+        if (is_leaf(L, rg)) {
             // the leaf's points in chunks of 64 through LDS, read back by
             // every lane SCREEN at a time (broadcast reads); an FP32 screen
             // (never below the FP64 distance, see wdf) sends the few points
             // that may enter a list to the exact FP64 test
+            // (the next chunk, or the next leaf's first, is loaded while one
+            // is screened)
+            float4 cur = pre_tag == node ? pre : load_chunk(rg.x, rg.y - rg.x < 64u ? rg.y : rg.x + 64u);
             for (uint32_t b = rg.x; b < rg.y; b += 64) {
                 const uint32_t m = rg.y - b < 64u ? rg.y - b : 64u;
-                pts[lane] = lane < m ? a.spos[b + lane] : make_float4(INFINITY, INFINITY, INFINITY, PAD_ID);
+                {
+                    const float cx = cur.x - ofx, cy = cur.y - ofy, cz = cur.z - ofz;
+                    pts[lane] = cur;
+                    rel[lane] = lane < m ? make_float4(cx, cy, cz, cx * cx + cy * cy + cz * cz)
+                                         : make_float4(0.f, 0.f, 0.f, INFINITY);
+                }
                 __builtin_amdgcn_wave_barrier();
-                for (uint32_t t = 0; t < m; t += SCREEN) {
+                if (b + 64u < rg.y)
+                    cur = load_chunk(b + 64u, rg.y - (b + 64u) < 64u ? rg.y : b + 128u);
+                else
+                    prefetch_top();
+                // screen: rows = 16 points of block pb, columns = 16 queries of block qb
+                float tq[4];
+#pragma unroll
+                for (int qb = 0; qb < 4; ++qb) tq[qb] = thr_l[16 * qb + (lane & 15)];
+                uint32_t hit_blocks = 0;   // point blocks with a screen hit (wave-uniform)
+                for (uint32_t pb = 0; pb < (m + 15) / 16; ++pb) {
+                    const float av = ((const float*)&rel[16 * pb + (lane & 15)])[lane >> 4];
                     bool hit = false;
 #pragma unroll
-                    for (int u = 0; u < SCREEN; ++u) {
-                        const float4 c = pts[t + u];
-                        const float dx = c.x - pf[0], dy = c.y - pf[1], dz = c.z - pf[2];
-                        hit |= dx * dx + dy * dy + dz * dz <= wdf;
+                    for (int qb = 0; qb < 4; ++qb) {
+                        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bq[qb], f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                             0, 0, 0);
+                        hit |= (d[0] <= tq[qb]) | (d[1] <= tq[qb]) | (d[2] <= tq[qb]) | (d[3] <= tq[qb]);
                     }
-                    if (act && hit) {
-#pragma unroll 1
-                        for (int u = 0; u < SCREEN; ++u) {
-                            const float4 cu = pts[t + u];
-                            const double dx = (double)cu.x - p[0], dy = (double)cu.y - p[1], dz = (double)cu.z - p[2];
-                            const double d2 = dx * dx + dy * dy + dz * dz;
-                            const uint32_t id = __builtin_bit_cast(uint32_t, cu.w);
-                            if (nb_before(d2, id, wd, wi)) {
-                                nb_insert(bd, bi, d2, id);
+                    if (__ballot(hit) != 0ull) hit_blocks |= 1u << pb;
+                }
+                if (hit_blocks != 0u) {
+                    // exact pass over the blocks with hits (per-lane FP32 screen, then FP64)
+                    for (uint32_t t = 0; t < m; t += SCREEN) {
+                        if (!((hit_blocks >> (t / 16)) & 1u)) continue;
+                        bool h2 = false;
 #pragma unroll
-                                for (int k = 0; k < KMAX; ++k)
-                                    if (k == K - 1) {
-                                        wd = bd[k];
-                                        wi = bi[k];
-                                    }
-                                wdf = screen_bound(wd);
+                        for (int u = 0; u < SCREEN; ++u) {
+                            const float4 c = pts[t + u];
+                            const float dx = c.x - pf[0], dy = c.y - pf[1], dz = c.z - pf[2];
+                            h2 |= dx * dx + dy * dy + dz * dz <= wdf;
+                        }
+                        if (act && h2) {
+#pragma unroll 1
+                            for (int u = 0; u < SCREEN; ++u) {
+                                const float4 cu = pts[t + u];
+                                const double dx = (double)cu.x - (double)pf[0], dy = (double)cu.y - (double)pf[1],
+                                             dz = (double)cu.z - (double)pf[2];
+                                const double d2 = dx * dx + dy * dy + dz * dz;
+                                const uint32_t id = __builtin_bit_cast(uint32_t, cu.w);
+                                if (nb_before(d2, id, wd, wi)) {
+                                    nb_insert(bd, bi, d2, id);
+#pragma unroll
+                                    for (int k = 0; k < KMAX; ++k)
+                                        if (k == K - 1) {
+                                            wd = bd[k];
+                                            wi = bi[k];
+                                        }
+                                    wdf = screen_bound(wd);
+                                }
                             }
                         }
                     }
+                    thr_l[lane] = screen_thr(wd);
                 }
                 __builtin_amdgcn_wave_barrier();
             }
@@ -594,8 +691,11 @@ __global__ void __launch_bounds__(64 * KNN_WAVES) k_reg_knn(RegArgs a) {
 }
 
 __global__ void __launch_bounds__(128) k_reg_filter(RegArgs a) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.N || a.cls[g] != CLS_SOURCE) return;
+    // one thread per solved Gaussian, in the Morton order of the sorted
+    // positions (neighbouring threads gather neighbouring changes)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)a.grid->n_src) return;
+    const int64_t g = __builtin_bit_cast(uint32_t, a.spos[i].w);
     const int K = a.ncnt[g];
     uint32_t nb[KMAX];
     for (int k = 0; k < K; ++k) nb[k] = a.nbr[g * KMAX + k];
@@ -766,7 +866,7 @@ extern "C" tg_status tg_regularize(const tg_gaussians* g_ref, const tg_gaussians
     if (st != TG_OK) return st;
     a.qorder = (const uint32_t*)(w + L.vf);
     const int64_t n_groups = (N + 63) / 64;
-    hipLaunchKernelGGL(k_reg_wkeys, dim3((unsigned)((n_groups + 255) / 256)), dim3(256), 0, s, a, n_groups);
+    hipLaunchKernelGGL(k_reg_wkeys, dim3(b256), dim3(256), 0, s, a);
     TG_CHECK_LAUNCH();
     st = tg_radix_sort(a.keys, nullptr, (uint32_t*)(w + L.ka), (uint32_t*)(w + L.va), (uint32_t*)(w + L.kb),
                        (uint32_t*)(w + L.vb), nullptr, (uint32_t*)(w + L.kf), n_groups, 1, nullptr, 0, 1,
