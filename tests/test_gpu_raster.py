@@ -147,7 +147,7 @@ def test_l1_and_adam_match_formulas():
     x = torch.tensor(a, device="cuda", requires_grad=True)
     loss = L1Loss.apply(x, torch.tensor(b, device="cuda"))
     loss.backward()
-    np.testing.assert_allclose(float(loss), np.abs(a.astype(np.float64) - b).mean(), rtol=1e-5)
+    np.testing.assert_allclose(float(loss.detach()), np.abs(a.astype(np.float64) - b).mean(), rtol=1e-5)
     np.testing.assert_array_equal(x.grad.cpu().numpy(), (np.sign(a - b) / a.size).astype(np.float32))
     # Adam: bias-corrected moments (Kingma & Ba, Alg. 1), three steps
     p0 = rng.standard_normal(5000).astype(np.float32)
