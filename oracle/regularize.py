@@ -83,15 +83,36 @@ def deltas(means0, quats0, scales0, means1, quats1, scales1):
 
 
 def knn(points, sources, queries, k=K):
-    """Indices (into `sources`) of the min(k, |sources|) nearest sources of
-    each query point, nearest first, and their distances."""
+    """Indices (into `sources`, ascending Gaussian indices) of the
+    min(k, |sources|) nearest sources of each query point, nearest first,
+    and their distances.  Equal distances are ordered by index (the paper
+    does not say; the reading is that of the neighbourhood row of the design
+    notes): the tree's candidates are re-sorted by (distance, index), and a
+    query whose candidates all tie with its k-th is decided over all
+    sources."""
     pts = np.asarray(points, np.float64)
+    sources = np.asarray(sources)
     kk = min(k, len(sources))
+    if kk == 0:
+        return np.zeros((len(queries), 0), np.int64), np.zeros((len(queries), 0))
     tree = cKDTree(pts[sources])
-    dist, idx = tree.query(pts[queries], k=kk)
-    if kk == 1:
-        dist, idx = dist[:, None], idx[:, None]
-    return idx, dist
+    extra = min(len(sources), kk + 8)
+    qp = pts[queries]
+    _, idx = tree.query(qp, k=extra)
+    if extra == 1:
+        idx = idx[:, None]
+    # squared distances of the candidates (the order is decided on these)
+    d2 = ((pts[sources][idx] - qp[:, None, :]) ** 2).sum(-1)
+    order = np.lexsort((idx, d2))            # per row: by distance, then index
+    d2 = np.take_along_axis(d2, order, 1)
+    idx = np.take_along_axis(idx, order, 1)
+    # ties may reach past the fetched candidates: decide those rows over all sources
+    open_rows = np.nonzero((extra < len(sources)) & (d2[:, extra - 1] == d2[:, kk - 1]))[0]
+    for r in open_rows:
+        d = ((pts[sources] - qp[r]) ** 2).sum(1)
+        o = np.lexsort((np.arange(len(sources)), d))[:extra]
+        d2[r], idx[r] = d[o], o
+    return idx[:, :kk], np.sqrt(d2[:, :kk])
 
 
 def regularize(means0, quats0, scales0, means1, quats1, scales1, status, acc, k=K):

@@ -43,6 +43,25 @@ def test_knn_matches_brute_force():
     np.testing.assert_allclose(dist, np.sqrt(np.take_along_axis(d2, order, 1)), rtol=1e-12)
 
 
+def test_knn_ties_by_index():
+    """Exact duplicates (equal distances, also past the tree's first
+    candidates): neighbours are the lowest indices among equal distances,
+    as a stable brute-force sort orders them."""
+    rng = np.random.default_rng(1)
+    base = rng.uniform(-1, 1, (40, 3)).astype(np.float32)
+    pts = base[rng.integers(0, 40, 400)]          # every position about 10 times
+    pts[:30] = pts[0]                              # one position 30+ times
+    src = np.nonzero(rng.random(400) < 0.7)[0]
+    src = np.union1d(src, np.arange(30))
+    qry = np.arange(400)
+    idx, dist = rg.knn(pts, src, qry, 8)
+    p64 = pts.astype(np.float64)
+    d2 = ((p64[qry][:, None, :] - p64[src][None, :, :]) ** 2).sum(-1)
+    order = np.argsort(d2, axis=1, kind="stable")[:, :8]
+    np.testing.assert_array_equal(idx, order)
+    assert (dist[:30] == 0).all()
+
+
 def test_euler_convention_against_scipy():
     rng = np.random.default_rng(1)
     R = Rotation.random(200, random_state=2)
