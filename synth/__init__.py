@@ -579,7 +579,14 @@ class RegCase:
 
 
 def make_reg_case(n=3000, views=4, *, seed=0, angle_deg=10.0, trans=0.1, noise=0.002, outlier_frac=0.05,
-                  unsolved_frac=0.1, posonly_frac=0.05, static_frac=0.1, uniform=False) -> RegCase:
+                  unsolved_frac=0.1, posonly_frac=0.05, static_frac=0.1, uniform=False, offset=None,
+                  dup_frac=0.0, shell=None) -> RegCase:
+    """Seeded regularisation input.  The options after `uniform` leave the
+    base draws untouched: `offset` translates both frames (a scene far from
+    the origin), `dup_frac` gives that fraction of Gaussians the first-frame
+    position of another one (equal distances, ties by index), `shell` = r
+    leaves only Gaussians farther than r from the ball's centre solved (the
+    visible-surface pattern: an interior far from every solved Gaussian)."""
     rng = np.random.default_rng(seed)
     sc = random_gaussians(rng, n, domain="ball", radius=2.0)
     axis = rng.standard_normal(3)
@@ -619,5 +626,18 @@ def make_reg_case(n=3000, views=4, *, seed=0, angle_deg=10.0, trans=0.1, noise=0
         vs = rng.choice(views, 2, replace=False)
         acc[vs, i, 12] = rng.integers(10, 40, 2)
         acc[vs, i, 13] = acc[vs, i, 12]
+    rng2 = np.random.default_rng(seed + 7919)
+    if dup_frac > 0.0:
+        d = np.nonzero(rng2.random(n) < dup_frac)[0]
+        src = rng2.integers(0, n, d.size)
+        sc.means[d] = sc.means[src]
+    if shell is not None:
+        inner = np.linalg.norm(sc.means.astype(np.float64), axis=1) <= shell
+        status[inner & (status == 3)] = 4
+    if offset is not None:
+        off = np.asarray(offset, np.float64)
+        sc.means[:] = (sc.means.astype(np.float64) + off).astype(np.float32)
+        mu1 = mu1 + off
+        truth["means"] = truth["means"] + off
     return RegCase(scene=sc, means1=mu1.astype(np.float32), quats1=q1.astype(np.float32),
                    scales1=s1.astype(np.float32), status=status, acc=acc, truth=truth)

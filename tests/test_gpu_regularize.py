@@ -1,8 +1,10 @@
 """GPU parity of tg_regularize (motion regularisation, Sec. 4.5) against the
 oracle on the same seeded inputs: classification (static / filtered /
-propagated / unchanged) bit-exact; means within 1e-5, rotation matrices
-within 1e-5 and scales within 1e-5 relative (the kernel stores the changes in
-FP32; medians and means are continuous in them)."""
+propagated / unchanged) bit-exact; means within 1e-5 plus one FP32 ulp of
+the coordinate (the output positions are FP32, so a scene far from the origin
+carries one rounding of its own size), rotation matrices within 1e-5 and
+scales within 1e-5 relative (the kernel stores the changes in FP32; medians
+and means are continuous in them)."""
 import numpy as np
 import pytest
 import torch
@@ -20,6 +22,16 @@ CASES = {
     "dense_outliers": dict(n=20000, views=5, seed=9, outlier_frac=0.15, unsolved_frac=0.3),
     "few_sources": dict(n=4000, views=4, seed=10, unsolved_frac=0.97, posonly_frac=0.0),
     "large": dict(n=200_000, views=6, seed=11),
+    # a scene 1000 units from the origin: the FP32 screens' roundings are
+    # largest relative to the distances
+    "far_offset": dict(n=20000, views=4, seed=13, offset=(1000.0, -750.0, 500.0)),
+    # a fifth of the Gaussians share another's position: equal distances,
+    # neighbours decided by index
+    "duplicates": dict(n=20000, views=4, seed=14, dup_frac=0.2),
+    # only a shell of the ball solved: queries in the interior are far from
+    # every solved Gaussian (long searches, the screens' bounds near their
+    # thresholds for many points at once)
+    "shell": dict(n=60000, views=4, seed=15, shell=1.8, unsolved_frac=0.0, static_frac=0.0),
 }
 
 
@@ -51,14 +63,15 @@ def test_regularize_matches_oracle(case):
                                       status, c.acc)
     np.testing.assert_array_equal(reg, oreg)
     moved = (oreg & (rg.RG_FILTERED | rg.RG_PROPAGATED)) > 0
-    dm = np.abs(m.astype(np.float64) - om).max() if m.size else 0.0
+    err_m = np.abs(m.astype(np.float64) - om)
+    dm = err_m.max() if m.size else 0.0
     Rg = oracle.quat_to_rot(q[moved].astype(np.float64))
     Ro = oracle.quat_to_rot(oq[moved])
     dr = np.abs(Rg - Ro).max() if moved.any() else 0.0
     ds = np.abs(s[moved] / os_[moved] - 1).max() if moved.any() else 0.0
     log(f"[{case}] filtered {int(((oreg & 2) > 0).sum())} propagated {int(((oreg & 4) > 0).sum())} "
         f"static {int((oreg == 1).sum())}; max |dmu| {dm:.2e}, |dR| {dr:.2e}, |dS/S| {ds:.2e}")
-    assert dm <= 1e-5 and dr <= 1e-5 and ds <= 1e-5
+    assert (err_m <= 1e-5 + 2.0 ** -23 * np.abs(om)).all() and dr <= 1e-5 and ds <= 1e-5
     assert (q[moved][:, 0] >= 0).all()
     # everything that does not move is copied bit-exactly
     keep = ~moved
