@@ -26,9 +26,12 @@
 //                   farther from the queries' bounding box than the wave's
 //                   largest current K-th neighbour distance, so queries far
 //                   from every solved Gaussian (the occluded interior of a
-//                   scene, say) share one traversal instead of diverging.
-//   k_reg_filter    per solved Gaussian (in Morton order): component-wise median of its
-//                   neighbours' changes (itself included).
+//                   scene, say) share one traversal instead of diverging;
+//                   leaf points screened on the matrix cores (|c'|^2 -
+//                   2 c'.q' by FP32 MFMA against a conservative bound),
+//                   the few candidates tested exactly in FP64.
+//   k_reg_filter    per solved Gaussian (in Morton order): component-wise
+//                   median of its neighbours' changes (itself included).
 //   k_reg_apply     per Gaussian: static -> first frame; solved -> first
 //                   frame + filtered change; other -> first frame + mean of
 //                   the neighbours' filtered changes.
@@ -445,10 +448,12 @@ __global__ void __launch_bounds__(64 * KNN_WAVES) __attribute__((amdgpu_waves_pe
     // (cells of every level are Morton runs): a node is skipped when its box
     // is farther from the queries' bounding box than the largest current
     // K-th neighbour distance of the wave, children are visited nearest
-    // first, and every point of a visited leaf is offered to every lane.
-    // The skipped points are farther than each lane's K-th neighbour, so
-    // every lane's result is its exact K nearest.  Boxes are widened by a
-    // margin because cells were assigned in FP32.
+    // first, and every point of a visited leaf is offered to every lane
+    // (an MFMA screen, then a per-lane FP32 screen, then the FP64 test).
+    // The skipped points are farther than each lane's K-th neighbour and the
+    // screens never reject a point the FP64 test would take, so every lane's
+    // result is its exact K nearest.  Boxes are widened by a margin because
+    // cells were assigned in FP32.
     __shared__ uint4 stk_all[KNN_WAVES][STACK];
     __shared__ float4 pts_all[KNN_WAVES][64];    // a leaf chunk: positions and indices
     __shared__ float4 rel_all[KNN_WAVES][64];    // the same relative to o, and |c - o|^2
