@@ -582,6 +582,14 @@ __global__ void __launch_bounds__(64 * KNN_WAVES) __attribute__((amdgpu_waves_pe
         // the launch's length: let them issue ahead of the short ones
         if (++visited == HEAVY_NODES) __builtin_amdgcn_s_setprio(2);
         if (is_leaf(L, rg)) {
+            // per lane, against its own query and K-th neighbour (tighter
+            // than the wave's bound): skip a leaf no lane can take a point from
+            {
+                const double pq[3] = {(double)pf[0], (double)pf[1], (double)pf[2]};
+                const double r = sqrt(wd) + margin;
+                const bool maybe = act && !(box_box_dist2(glo, gh, L, code, pq, pq) > r * r * (1.0 + 0x1p-40));
+                if (__ballot(maybe) == 0ull) continue;
+            }
             // the leaf's points in chunks of 64 through LDS, read back by
             // every lane SCREEN at a time (broadcast reads); an FP32 screen
             // (never below the FP64 distance, see wdf) sends the few points
