@@ -180,9 +180,11 @@ __global__ void __launch_bounds__(256) k_reg_classify(RegArgs a) {
         // them static, in at least static_views views (decided in FP64 on the
         // exact integer counts)
         int sv = 0;
+#pragma unroll 4
         for (int v = 0; v < a.V; ++v) {
-            const float* r = a.acc + ((int64_t)v * a.N + g) * TG_ACC_STRIDE;
-            const double n = r[12], sn = r[13];
+            // the pixel counts of the record (slots 12 and 13), one 8-byte load
+            const float2 r = *(const float2*)(a.acc + ((int64_t)v * a.N + g) * TG_ACC_STRIDE + 12);
+            const double n = r.x, sn = r.y;
             if (n > (double)a.static_min_pix && sn > a.static_frac * n) ++sv;
         }
         const bool stat = sv >= a.static_views;
