@@ -350,10 +350,6 @@ __device__ __forceinline__ void nb_insert(double (&bd)[KMAX], uint32_t (&bi)[KMA
     }
 }
 
-__device__ __forceinline__ float bcast_f32(float x, uint32_t l) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), (int)l));
-}
-
 __device__ __forceinline__ double bcast_f64(double x, int l) {
     const uint64_t u = __builtin_bit_cast(uint64_t, x);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
