@@ -280,10 +280,11 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
                     p[i] = c.R[3 * i] * mu3[0] + c.R[3 * i + 1] * mu3[1] + c.R[3 * i + 2] * mu3[2] + c.t[i];
                 const double limx = (double)prm.j_clamp * (0.5 * c.width / (double)c.fx);
                 const double limy = (double)prm.j_clamp * (0.5 * c.height / (double)c.fy);
-                const double tx = fmin(limx, fmax(-limx, p[0] / p[2]));
-                const double ty = fmin(limy, fmax(-limy, p[1] / p[2]));
-                const double J00 = c.fx / p[2], J02 = -c.fx * tx / p[2];
-                const double J11 = c.fy / p[2], J12 = -c.fy * ty / p[2];
+                const double ip2 = 1.0 / p[2];   // one FP64 reciprocal instead of six divisions
+                const double tx = fmin(limx, fmax(-limx, p[0] * ip2));
+                const double ty = fmin(limy, fmax(-limy, p[1] * ip2));
+                const double J00 = c.fx * ip2, J02 = -c.fx * tx * ip2;
+                const double J11 = c.fy * ip2, J12 = -c.fy * ty * ip2;
                 double T0[3], T1[3];
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
