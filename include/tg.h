@@ -172,7 +172,8 @@ int64_t tg_num_tiles(const tg_camera* cams, int32_t V);
  * conic and a 3-sigma radius; the tile rectangle covers the centre +- radius.
  * The integer-deciding quantities (centre, radius, rectangle, depth key) use
  * FP32 in a fixed operation order; Sigma_2D and the conic are formed in FP64
- * and rounded.  With g->sh != NULL and out->colors != NULL, colours are the
+ * and rounded.  A Gaussian with a non-finite mean, quaternion, scale or
+ * opacity (as passed in) is culled in every view.  With g->sh != NULL and out->colors != NULL, colours are the
  * degree-d SH evaluated in the viewing direction, +0.5, clamped at 0.
  *
  * cams: host [V] (any V >= 1; launched in chunks of TG_MAX_VIEWS).
@@ -289,7 +290,9 @@ tg_status tg_splat_accumulate_batch(const tg_acc_slot* slots, int32_t n_slots, c
  * (view, Gaussian): 1 solved, 2 culled, 4 fewer than pix_min pixels,
  * 8 accumulated alpha below wsum_min, 16 near-singular V1: det V1 below
  * det_min, or 4 det(C)/tr(C)^2 below iso_min with C = Suu/Sw - (Su/Sw)(Su/Sw)^T
- * the weighted covariance of the pixel offsets (bits 2-16 may combine).  Unsolved entries get zero mu'/Sigma'.
+ * the weighted covariance of the pixel offsets, 32 a non-finite statistic
+ * (a non-finite track reached the record) (bits 2-32 may combine).
+ * Unsolved entries get zero mu'/Sigma'.
  * mu2d_new [V,N,2], cov2d_new [V,N,3] float32, vflags [V,N] uint8: device.
  * wn: device [V,N,2] float32 or NULL: receives each record's accumulated
  * alpha (slot 0) and pixel count (slot 12), the compact totals that
@@ -314,7 +317,10 @@ tg_status tg_solve_views(const float* acc, const tg_splats* s, int64_t N, int32_
  * det +1, quaternion with w >= 0, scales = sqrt(eigenvalues).
  * Status bits: 1 mean updated, 2 rotation/scale updated, 4 few views,
  * 8 low total alpha, 16 few total pixels, 32 non-positive eigenvalue or
- * singular covariance system, 64 degenerate DLT, 128 behind a camera.
+ * singular covariance system, 64 degenerate DLT, 128 behind a camera,
+ * 256 non-finite input: a non-finite parameter of the Gaussian (culled in
+ * every view by tg_preprocess, so never updated) or a view whose statistics
+ * were non-finite (left out of the update like any unsolved view).
  * Everything not updated is copied from g_in.  g_out may alias g_in (in-place
  * update).  cams: host [V]; V <= TG_MAX_VIEWS.  wn: device [V,N,2] from
  * tg_solve_views (accumulated alpha and pixel count per view, summed here

@@ -12,8 +12,8 @@ Contents, in the order the method runs (TrackerSplat, SIGGRAPH Asia 2025):
                    renderer's FP32 precision; see tg_oracle.c).
   project64()      FP64 EWA covariance Sigma_2D = J W Sigma_3D W^T J^T and the
                    conic of its dilated form (Sec. 3.1, Eq. 1).
-  cell_lists()     brute-force depth-ordered per-tile lists (Sec. 3.1,
-                   "alpha-blending ... according to its depth").
+  cell_lists()     brute-force depth-ordered per-tile lists (Sec. 3.1: the
+                   splats are blended front to back by depth).
   composite()      per-pixel compositing with w = alpha*T and the weighted
                    incremental LS statistics (Sec. 4.3.3, Sec. 4.3.4 Eq. 4).
   solve_views()    [A|b] per (Gaussian, view) from V1^{-1} V2 and Eq. 2
@@ -56,7 +56,7 @@ PIX_TOTAL_MIN = 3        # Sec. 5.2: fewer than 3 pixels across views
 JCLAMP = 1.3
 
 # per-view flags
-VF_OK, VF_CULLED, VF_FEW_PIX, VF_LOW_ALPHA, VF_SINGULAR = 1, 2, 4, 8, 16
+VF_OK, VF_CULLED, VF_FEW_PIX, VF_LOW_ALPHA, VF_SINGULAR, VF_NONFINITE = 1, 2, 4, 8, 16, 32
 # per-Gaussian status bits
 ST_POS, ST_COV, ST_FEW_VIEWS, ST_LOW_ALPHA, ST_FEW_PIX = 1, 2, 4, 8, 16
 ST_NEG_EIG, ST_DLT_DEGEN, ST_BEHIND, ST_NONFINITE = 32, 64, 128, 256
@@ -86,8 +86,21 @@ def lib():
         L.orc_composite.argtypes = [i32, P, i64, P, P, P, P, P, P, P, P, f64, f64,
                                     P, P, P, P, P, P, P, P]
         L.orc_composite.restype = None
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = i32
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
 
 
 def _p(a):
@@ -120,7 +133,20 @@ def geometry(scene, cams) -> Geometry:
     valid = np.zeros((V, N), np.uint8)
     m, q, s = _c(scene.means, np.float32), _c(scene.quats, np.float32), _c(scene.scales, np.float32)
     lib().orc_geometry_f32(N, _p(m), _p(q), _p(s), V, _p(ca), _p(mu), _p(rect), _p(key), _p(valid))
+    # a Gaussian with a non-finite parameter is culled in every view
+    bad = ~finite_params(scene)
+    if bad.any():
+        mu[:, bad] = 0.0
+        rect[:, bad] = 0
+        key[:, bad] = 0xFFFFFFFF
+        valid[:, bad] = 0
     return Geometry(mu, rect, key, valid)
+
+
+def finite_params(scene):
+    """[N] bool: mean, quaternion, scale and opacity all finite."""
+    return (np.isfinite(scene.means).all(1) & np.isfinite(scene.quats).all(1) &
+            np.isfinite(scene.scales).all(1) & np.isfinite(scene.opacity))
 
 
 def project64(scene, cams):
@@ -201,12 +227,14 @@ def composite(scene, cams, geom: Geometry, conic, lists, disp, vis=None, pixmask
 def v1_v2(mom):
     """Centred V1 (3x3) and V2 (3x2) from accumulator records [...,16]."""
     m = mom
-    V1 = np.stack([np.stack([m[..., S_UXUX], m[..., S_UXUY], m[..., S_UX]], -1),
-                   np.stack([m[..., S_UXUY], m[..., S_UYUY], m[..., S_UY]], -1),
-                   np.stack([m[..., S_UX], m[..., S_UY], m[..., S_W]], -1)], -2)
-    V2 = np.stack([np.stack([m[..., S_UXDX], m[..., S_UXDY]], -1),
-                   np.stack([m[..., S_UYDX], m[..., S_UYDY]], -1),
-                   np.stack([m[..., S_DX], m[..., S_DY]], -1)], -2)
+    V1 = np.empty(m.shape[:-1] + (3, 3))
+    V1[..., 0, 0], V1[..., 0, 1], V1[..., 0, 2] = m[..., S_UXUX], m[..., S_UXUY], m[..., S_UX]
+    V1[..., 1, 0], V1[..., 1, 1], V1[..., 1, 2] = m[..., S_UXUY], m[..., S_UYUY], m[..., S_UY]
+    V1[..., 2, 0], V1[..., 2, 1], V1[..., 2, 2] = m[..., S_UX], m[..., S_UY], m[..., S_W]
+    V2 = np.empty(m.shape[:-1] + (3, 2))
+    V2[..., 0, 0], V2[..., 0, 1] = m[..., S_UXDX], m[..., S_UXDY]
+    V2[..., 1, 0], V2[..., 1, 1] = m[..., S_UYDX], m[..., S_UYDY]
+    V2[..., 2, 0], V2[..., 2, 1] = m[..., S_DX], m[..., S_DY]
     return V1, V2
 
 
@@ -216,7 +244,8 @@ def solve_views(mom, mu_c, cov, rendered):
     The LS regresses the displacement dd = x' - x on [u; 1], u = x - mu_c,
     which is the paper's x' = A x + b re-parametrised (exact in real
     arithmetic): Theta = V1^{-1} V2 = [G^T; c^T], A = I + G,
-    mu' = mu_c + c, Sigma' = A Sigma A^T."""
+    mu' = mu_c + c, Sigma' = A Sigma A^T.  Unsolved entries keep A = I,
+    c = 0 and get zero mu' and Sigma'."""
     V, N = mom.shape[:2]
     V1, V2 = v1_v2(mom)
     det = np.linalg.det(V1)
@@ -225,6 +254,8 @@ def solve_views(mom, mu_c, cov, rendered):
     flags |= np.where(mom[..., S_N] < PIX_MIN, VF_FEW_PIX, 0).astype(np.uint8)
     flags |= np.where(mom[..., S_W] < WSUM_MIN, VF_LOW_ALPHA, 0).astype(np.uint8)
     flags |= np.where(~(det >= DET_MIN), VF_SINGULAR, 0).astype(np.uint8)
+    # a non-finite track leaves non-finite sums in the record
+    flags |= np.where(~np.isfinite(mom[..., :13]).all(-1), VF_NONFINITE, 0).astype(np.uint8)
     # weighted covariance C of the pixel offsets u; near-singular when
     # 4 det(C) / tr(C)^2 < ISO_MIN (its eigenvalues differ by ~1/ISO_MIN)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -238,18 +269,23 @@ def solve_views(mom, mu_c, cov, rendered):
     flags |= np.where(~iso_ok, VF_SINGULAR, 0).astype(np.uint8)
     ok = flags == 0
     flags[ok] = VF_OK
-    theta = np.zeros((V, N, 3, 2))
+    A = np.zeros((V, N, 2, 2))
+    A[..., 0, 0] = A[..., 1, 1] = 1.0
+    c = np.zeros((V, N, 2))
+    mu_new = np.zeros((V, N, 2))
+    cov_new = np.zeros((V, N, 3))
     if ok.any():
-        theta[ok] = np.linalg.solve(V1[ok], V2[ok])
-    G = np.swapaxes(theta[..., 0:2, :], -1, -2)
-    c = theta[..., 2, :]
-    A = np.eye(2) + G
-    mu_new = np.asarray(mu_c, np.float64) + c
-    S = np.stack([np.stack([cov[..., 0], cov[..., 1]], -1), np.stack([cov[..., 1], cov[..., 2]], -1)], -2)
-    Sn = A @ S @ np.swapaxes(A, -1, -2)
-    cov_new = np.stack([Sn[..., 0, 0], Sn[..., 0, 1], Sn[..., 1, 1]], -1)
-    mu_new[~ok] = 0.0
-    cov_new[~ok] = 0.0
+        theta = np.linalg.solve(V1[ok], V2[ok])               # [n,3,2]
+        Ak = np.eye(2) + np.swapaxes(theta[:, 0:2, :], -1, -2)
+        ck = theta[:, 2, :]
+        S = cov[ok]
+        Sk = np.empty((S.shape[0], 2, 2))
+        Sk[:, 0, 0], Sk[:, 0, 1], Sk[:, 1, 0], Sk[:, 1, 1] = S[:, 0], S[:, 1], S[:, 1], S[:, 2]
+        Sn = Ak @ Sk @ np.swapaxes(Ak, -1, -2)
+        A[ok] = Ak
+        c[ok] = ck
+        mu_new[ok] = np.asarray(mu_c, np.float64)[ok] + ck
+        cov_new[ok] = np.stack([Sn[:, 0, 0], Sn[:, 0, 1], Sn[:, 1, 1]], -1)
     return dict(flags=flags, mu_new=mu_new, cov_new=cov_new, A=A, c=c, det=det)
 
 
@@ -356,6 +392,9 @@ def triangulate(scene, cams, sv, mom, rendered, chunk=65536):
     sw_tot = (mom[..., S_W] * (rendered != 0)).sum(0)
     n_tot = (mom[..., S_N] * (rendered != 0)).sum(0)
     status = np.zeros(N, np.uint32)
+    # non-finite input: the Gaussian's own parameters, or a view's statistics
+    nonfinite = ~finite_params(scene) | ((sv["flags"] & VF_NONFINITE) > 0).any(0)
+    status |= np.where(nonfinite, ST_NONFINITE, 0).astype(np.uint32)
     status |= np.where(nv < VIEWS_MIN, ST_FEW_VIEWS, 0).astype(np.uint32)
     status |= np.where(~(sw_tot >= WSUM_TOTAL_MIN), ST_LOW_ALPHA, 0).astype(np.uint32)
     status |= np.where(n_tot < PIX_TOTAL_MIN, ST_FEW_PIX, 0).astype(np.uint32)
@@ -366,7 +405,7 @@ def triangulate(scene, cams, sv, mom, rendered, chunk=65536):
     eig = np.zeros((N, 3))
     for s in range(0, N, chunk):
         e = min(N, s + chunk)
-        cand = status[s:e] == 0
+        cand = (status[s:e] & ~np.uint32(ST_NONFINITE)) == 0
         if not cand.any():
             continue
         idx = np.nonzero(cand)[0] + s
@@ -429,7 +468,7 @@ def triangulate(scene, cams, sv, mom, rendered, chunk=65536):
             scales[ii] = sn
             eig[ii] = lc
         st |= np.where(cov_ok, ST_COV, 0).astype(np.uint32)
-        status[idx] = st
+        status[idx] |= st
     return dict(means=means, quats=quats, scales=scales, status=status, eig=eig)
 
 

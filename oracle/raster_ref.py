@@ -108,9 +108,15 @@ def _project(means, S3, sh, deg, cam, dil, jclamp, sel):
 
 def _composite(pix, mu, Q, o, col, rect, bg, alpha_min, alpha_max, t_min, margin_rel):
     """Front-to-back compositing of depth-ordered Gaussians at pixels
-    pix [P,2]; returns colours [P,3] and, per pixel, whether a discrete
-    decision (alpha threshold, alpha clamp, termination) lies within
-    margin_rel (relative) of flipping."""
+    pix [P,2]; returns colours [P,3], per pixel whether a discrete decision
+    (alpha threshold, alpha clamp, termination) lies within margin_rel
+    (relative) of flipping, and a bound on how far such flips can move the
+    pixel's colour (slack [P]): including or dropping Gaussian i changes
+    its own term alpha_i T_i c_i and scales everything behind it (at most
+    T_i times the largest colour) by (1 - alpha_i), so each near-threshold
+    decision moves any channel by at most 2 alpha_i T_i cmax; a clamp
+    decision by at most 2 margin_rel T_i cmax; the terminating Gaussian
+    (T_i alpha_i and the rest are below T_i) by at most 2 T_i cmax."""
     dt = torch.float64
     ptx = (pix[:, 0] // 16).long()[:, None]
     pty = (pix[:, 1] // 16).long()[:, None]
@@ -139,17 +145,26 @@ def _composite(pix, mu, Q, o, col, rect, bg, alpha_min, alpha_max, t_min, margin
             ((rawd / alpha_min - 1).abs() < margin_rel) | ((rawd / alpha_max - 1).abs() < margin_rel) |
             (use & ((Tin / t_min - 1).abs() < margin_rel)))
         marginal = marg.any(1)
+        Tfront = torch.cat([torch.ones_like(al[:, :1]), Tin[:, :-1]], 1)
+        cmax = float(col.detach().abs().max()) if col.numel() else 0.0
+        cmax = max(cmax, max(abs(float(x)) for x in bg))
+        live = inrect & upto & (power.detach() <= 0)
+        a_m = live & ((rawd / alpha_min - 1).abs() < margin_rel)
+        c_m = live & ((rawd / alpha_max - 1).abs() < margin_rel)
+        t_m = use & upto & ((Tin / t_min - 1).abs() < margin_rel)
+        slack = 2.0 * cmax * (Tfront * (a_m * rawd.clamp(max=alpha_max) * (1 + margin_rel) +
+                                        c_m * margin_rel + t_m)).sum(1)
     al = torch.where(keep, al, torch.zeros_like(al))
     Tex = torch.cat([torch.ones_like(al[:, :1]), torch.cumprod(1.0 - al, dim=1)[:, :-1]], 1)
     w = al * Tex
     Tfin = torch.prod(1.0 - al, dim=1)
     C = w @ col + Tfin[:, None] * torch.tensor(bg, dtype=dt)[None, :]
-    return C, marginal
+    return C, marginal, slack
 
 
 def render(means, quats, log_scales, logit_opacity, sh, cams, bg=(0.0, 0.0, 0.0), geom=None, pixels=None,
            dil=0.3, jclamp=1.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, margin_rel=1e-3,
-           return_marginal=False):
+           return_marginal=False, return_slack=False):
     """FP64 reference colours (torch, differentiable).
 
     Dense images [V,H,W,3] when pixels is None; else pixels = (v, x, y)
@@ -157,7 +172,9 @@ def render(means, quats, log_scales, logit_opacity, sh, cams, bg=(0.0, 0.0, 0.0)
     Geometry holding the FP32 decisions (tile rectangles, depth keys);
     computed from the inputs (scales = exp(log_scales) in FP32) when None.
     With return_marginal, also a boolean mask (same leading shape) of
-    pixels holding a decision within margin_rel of flipping."""
+    pixels holding a decision within margin_rel of flipping; with
+    return_slack as well, the bound on the colour change such flips can
+    cause (see _composite)."""
     dt = torch.float64
     if geom is None:
         geom = _geom_of(means, quats, log_scales, cams)
@@ -169,7 +186,7 @@ def render(means, quats, log_scales, logit_opacity, sh, cams, bg=(0.0, 0.0, 0.0)
     deg = int(round(math.sqrt(sh.shape[1]))) - 1
     args = (bg, alpha_min, alpha_max, t_min, margin_rel)
     if pixels is None:
-        imgs, margs = [], []
+        imgs, margs, slacks = [], [], []
         for v, cam in enumerate(cams):
             order = torch.tensor(_order(geom, v).astype(np.int64))
             mu, Q, col = _project(means, S3, sh, deg, cam, dil, jclamp, order)
@@ -177,14 +194,16 @@ def render(means, quats, log_scales, logit_opacity, sh, cams, bg=(0.0, 0.0, 0.0)
             H, W = cam.H, cam.W
             yy, xx = torch.meshgrid(torch.arange(H, dtype=dt), torch.arange(W, dtype=dt), indexing="ij")
             pix = torch.stack([xx.reshape(-1), yy.reshape(-1)], -1)
-            C, mg = _composite(pix, mu, Q, o[order], col, rect, *args)
+            C, mg, sl = _composite(pix, mu, Q, o[order], col, rect, *args)
             imgs.append(C.reshape(H, W, 3))
             margs.append(mg.reshape(H, W))
-        out, marg = torch.stack(imgs, 0), torch.stack(margs, 0)
+            slacks.append(sl.reshape(H, W))
+        out, marg, slack = torch.stack(imgs, 0), torch.stack(margs, 0), torch.stack(slacks, 0)
     else:
         pv, px, py = (np.asarray(a, np.int64) for a in pixels)
         out = [None] * len(pv)
         marg = torch.zeros(len(pv), dtype=torch.bool)
+        slack = torch.zeros(len(pv), dtype=dt)
         for v in np.unique(pv):
             at = np.nonzero(pv == v)[0]
             order = _order(geom, v)
@@ -196,16 +215,19 @@ def render(means, quats, log_scales, logit_opacity, sh, cams, bg=(0.0, 0.0, 0.0)
             sel = torch.tensor(order[cand])
             mu, Q, col = _project(means, S3, sh, deg, cams[v], dil, jclamp, sel)
             pix = torch.tensor(np.stack([px[at], py[at]], -1).astype(np.float64))
-            C, mg = _composite(pix, mu, Q, o[sel], col, torch.tensor(rect_all[cand]), *args)
+            C, mg, sl = _composite(pix, mu, Q, o[sel], col, torch.tensor(rect_all[cand]), *args)
             for j, i in enumerate(at):
                 out[i] = C[j]
             marg[torch.tensor(at)] = mg
+            slack[torch.tensor(at)] = sl
         out = torch.stack(out, 0)
+    if return_slack:
+        return out, marg, slack
     return (out, marg) if return_marginal else out
 
 
 # ---------------------------------------------------------------------------
-# 3DGS objective (Sec. 4.6 refines "following the original 3DGS method"):
+# 3DGS objective (Sec. 4.6: the refinement uses the original 3DGS training):
 # L = (1 - lambda) L1 + lambda (1 - SSIM), SSIM with an 11x11 Gaussian window
 # (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, zero padding, mean over pixels and
 # channels of every image.

@@ -2,11 +2,12 @@
 
 Plain numpy/scipy, FP64.  Steps in the paper's order:
 
-  static_mask()   Sec. 4.5.2: a Gaussian is static when, in at least 2
-                  views, it is hit by more than 9 pixels of which more than
-                  90% are static (|x' - x| < 1 px; counted by the
-                  accumulation, slots S_N and S_STATN).  Static Gaussians
-                  keep their first-frame parameters and take no further part.
+  static_mask()   Sec. 4.5.2: a Gaussian counts as static when at least two
+                  of its views each see it with ten or more covering pixels,
+                  over nine tenths of them static (|x' - x| < 1 px; counted
+                  by the accumulation, slots S_N and S_STATN).  Static
+                  Gaussians keep their first-frame parameters and take no
+                  further part.
   deltas()        Sec. 4.5.1: the change of a Gaussian against the first
                   frame: d_mu = mu' - mu, d_S = s' - s (linear scales) and
                   the rotation change Q = R' R^T in Euler-angle form
@@ -14,12 +15,13 @@ Plain numpy/scipy, FP64.  Steps in the paper's order:
   knn()           the K = 8 nearest solved Gaussians (Sec. 5.2), by the
                   Euclidean distance between first-frame means; a solved
                   Gaussian's own entry is among them (distance 0).
-  regularize()    median filter (Sec. 4.5.1): a solved Gaussian takes the
-                  component-wise median of its neighbours' changes;
-                  propagation (Sec. 4.5.2): a Gaussian that is neither
-                  solved nor static takes the component-wise mean of its
-                  neighbours' filtered changes; the change is added to the
-                  first-frame parameters (rotation: R_new = Q(angles) R).
+  median_filter() Sec. 4.5.1: a solved Gaussian takes the component-wise
+                  median of its neighbours' changes.
+  propagate()     Sec. 4.5.2: a Gaussian that is neither solved nor static
+                  takes the component-wise mean of its neighbours' filtered
+                  changes.
+  regularize()    the steps above; the change is added to the first-frame
+                  parameters (rotation: R_new = Q(angles) R).
 
 "Solved" means position and covariance both updated by the multi-view step
 (status bits 1 and 2); Gaussians with only a position (negative eigenvalue
@@ -35,9 +37,9 @@ from scipy.spatial import cKDTree
 from . import S_N, S_STATN, ST_COV, ST_POS, quat_to_rot, rot_to_quat
 
 K = 8                 # neighbours (Sec. 5.2)
-STATIC_MIN_PIX = 9    # "hit by more than 9 pixels" (Sec. 4.5.2)
-STATIC_FRAC = 0.9     # "more than 90% of its pixels fixed"
-STATIC_VIEWS = 2      # "in at least 2 views"
+STATIC_MIN_PIX = 9    # static in a view: pixel count must exceed this (Sec. 4.5.2)
+STATIC_FRAC = 0.9     # ... and the static share of them must exceed this
+STATIC_VIEWS = 2      # static Gaussian: static in at least this many views
 
 RG_STATIC, RG_FILTERED, RG_PROPAGATED = 1, 2, 4
 
@@ -115,8 +117,20 @@ def knn(points, sources, queries, k=K):
     return idx[:, :kk], np.sqrt(d2[:, :kk])
 
 
-def regularize(means0, quats0, scales0, means1, quats1, scales1, status, acc, k=K):
-    """Returns (means, quats, scales, reg_status) after Sec. 4.5."""
+def median_filter(vals):
+    """[n, K, 9] neighbours' changes (own entry first) -> [n, 9] (Sec. 4.5.1)."""
+    return np.median(vals, axis=1)
+
+
+def propagate(vals):
+    """[n, K, 9] neighbours' filtered changes -> [n, 9] (Sec. 4.5.2)."""
+    return vals.mean(axis=1)
+
+
+def regularize(means0, quats0, scales0, means1, quats1, scales1, status, acc, k=None):
+    """Returns (means, quats, scales, reg_status) after Sec. 4.5; k defaults
+    to the module's K."""
+    k = K if k is None else k
     N = means0.shape[0]
     status = np.asarray(status, np.uint32)
     static = static_mask(acc)
@@ -128,7 +142,7 @@ def regularize(means0, quats0, scales0, means1, quats1, scales1, status, acc, k=
     if src.size:
         # median filter of the solved Gaussians
         idx, _ = knn(means0, src, src, k)
-        filt = np.median(d[src][idx], axis=1)                 # [n_src, 9]
+        filt = median_filter(d[src][idx])                     # [n_src, 9]
         out_d[src] = filt
         reg[src] |= RG_FILTERED
         # propagation of the filtered changes to the rest (not static)
@@ -137,7 +151,7 @@ def regularize(means0, quats0, scales0, means1, quats1, scales1, status, acc, k=
             fd = np.zeros((N, 9))
             fd[src] = filt
             idx, _ = knn(means0, src, tgt, k)
-            out_d[tgt] = fd[src][idx].mean(axis=1)
+            out_d[tgt] = propagate(fd[src][idx])
             reg[tgt] |= RG_PROPAGATED
     moved = (reg & (RG_FILTERED | RG_PROPAGATED)) > 0
     means = np.asarray(means0, np.float64).copy()

@@ -208,71 +208,82 @@ void orc_project_f64(int64_t N, const float* means, const float* quats, const fl
  * coarse lists of 2^k x 2^k tiles.  Output is CSR over all views:
  * starts[T_total+1] and ids[].  Returns the number of ids, or -1 if ids_cap
  * is too small (call with ids == NULL to count).
+ *
+ * The Gaussians of a view are first put in (depth key, index) order; walking
+ * them in that order and appending each to every tile its rectangle covers
+ * leaves every tile's list in that order.
  * ---------------------------------------------------------------------- */
-static const uint32_t* g_sort_key;
-static int cmp_key_id(const void* a, const void* b)
+static int cmp_u64(const void* a, const void* b)
 {
-    uint32_t ia = *(const uint32_t*)a, ib = *(const uint32_t*)b;
-    uint32_t ka = g_sort_key[ia], kb = g_sort_key[ib];
-    if (ka != kb) return ka < kb ? -1 : 1;
-    return ia < ib ? -1 : (ia > ib ? 1 : 0);
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static void cell_dims(const ocam* c, int32_t cell, int* CX, int* CY)
+{
+    int TX = (c->W + O_TILE - 1) / O_TILE, TY = (c->H + O_TILE - 1) / O_TILE;
+    *CX = (TX + cell - 1) / cell;
+    *CY = (TY + cell - 1) / cell;
 }
 
 int64_t orc_tile_lists(int64_t N, int32_t V, const ocam* cams, const int32_t* rect,
                        const uint32_t* key, const uint8_t* valid, int32_t cell,
                        int64_t* starts, uint32_t* ids, int64_t ids_cap)
 {
-    int64_t total_cells = 0;
+    int64_t* view_base = (int64_t*)malloc(sizeof(int64_t) * (size_t)(V + 1));
+    view_base[0] = 0;
     for (int v = 0; v < V; ++v) {
-        int TX = (cams[v].W + O_TILE - 1) / O_TILE, TY = (cams[v].H + O_TILE - 1) / O_TILE;
-        int CX = (TX + cell - 1) / cell, CY = (TY + cell - 1) / cell;
-        total_cells += (int64_t)CX * CY;
+        int CX, CY;
+        cell_dims(cams + v, cell, &CX, &CY);
+        view_base[v + 1] = view_base[v] + (int64_t)CX * CY;
     }
+    const int64_t total_cells = view_base[V];
     int64_t* cnt = (int64_t*)calloc((size_t)total_cells + 1, sizeof(int64_t));
-    int64_t base = 0;
+    /* count: views own disjoint ranges of cells */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int v = 0; v < V; ++v) {
-        int TX = (cams[v].W + O_TILE - 1) / O_TILE, TY = (cams[v].H + O_TILE - 1) / O_TILE;
-        int CX = (TX + cell - 1) / cell, CY = (TY + cell - 1) / cell;
+        int CX, CY;
+        cell_dims(cams + v, cell, &CX, &CY);
         for (int64_t g = 0; g < N; ++g) {
             int64_t o = (int64_t)v * N + g;
             if (!valid[o]) continue;
             const int32_t* r = rect + 4 * o;
             int x0 = r[0] / cell, y0 = r[1] / cell, x1 = (r[2] - 1) / cell + 1, y1 = (r[3] - 1) / cell + 1;
             for (int y = y0; y < y1; ++y)
-                for (int x = x0; x < x1; ++x) cnt[base + (int64_t)y * CX + x]++;
+                for (int x = x0; x < x1; ++x) cnt[view_base[v] + (int64_t)y * CX + x]++;
         }
-        base += (int64_t)CX * CY;
     }
     int64_t run = 0;
     for (int64_t i = 0; i < total_cells; ++i) { int64_t c = cnt[i]; cnt[i] = run; run += c; }
     cnt[total_cells] = run;
     if (starts) memcpy(starts, cnt, sizeof(int64_t) * (size_t)(total_cells + 1));
-    if (!ids) { free(cnt); return run; }
-    if (run > ids_cap) { free(cnt); return -1; }
-    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(total_cells + 1));
-    memcpy(fill, cnt, sizeof(int64_t) * (size_t)(total_cells + 1));
-    base = 0;
+    if (!ids || run > ids_cap) {
+        free(cnt);
+        free(view_base);
+        return ids ? -1 : run;
+    }
+    /* fill in (depth key, index) order */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int v = 0; v < V; ++v) {
-        int TX = (cams[v].W + O_TILE - 1) / O_TILE, TY = (cams[v].H + O_TILE - 1) / O_TILE;
-        int CX = (TX + cell - 1) / cell, CY = (TY + cell - 1) / cell;
-        for (int64_t g = 0; g < N; ++g) {
-            int64_t o = (int64_t)v * N + g;
-            if (!valid[o]) continue;
-            const int32_t* r = rect + 4 * o;
+        int CX, CY;
+        cell_dims(cams + v, cell, &CX, &CY);
+        uint64_t* ord = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(N > 0 ? N : 1));
+        int64_t n = 0;
+        for (int64_t g = 0; g < N; ++g)
+            if (valid[(int64_t)v * N + g]) ord[n++] = ((uint64_t)key[(int64_t)v * N + g] << 32) | (uint64_t)g;
+        qsort(ord, (size_t)n, sizeof(uint64_t), cmp_u64);
+        int64_t* fill = cnt + view_base[v];     /* this view's cells only */
+        for (int64_t i = 0; i < n; ++i) {
+            uint32_t g = (uint32_t)(ord[i] & 0xFFFFFFFFu);
+            const int32_t* r = rect + 4 * ((int64_t)v * N + g);
             int x0 = r[0] / cell, y0 = r[1] / cell, x1 = (r[2] - 1) / cell + 1, y1 = (r[3] - 1) / cell + 1;
             for (int y = y0; y < y1; ++y)
-                for (int x = x0; x < x1; ++x) ids[fill[base + (int64_t)y * CX + x]++] = (uint32_t)g;
+                for (int x = x0; x < x1; ++x) ids[fill[(int64_t)y * CX + x]++] = g;
         }
-        /* sort each cell list by (key, id) */
-        g_sort_key = key + (int64_t)v * N;
-        for (int64_t cidx = 0; cidx < (int64_t)CX * CY; ++cidx) {
-            int64_t s = cnt[base + cidx], e = cnt[base + cidx + 1];
-            if (e - s > 1) qsort(ids + s, (size_t)(e - s), sizeof(uint32_t), cmp_key_id);
-        }
-        base += (int64_t)CX * CY;
+        free(ord);
     }
-    free(fill);
     free(cnt);
+    free(view_base);
     return run;
 }
 
@@ -298,6 +309,8 @@ int64_t orc_tile_lists(int64_t N, int32_t V, const ocam* cams, const int32_t* re
  * legitimately decide the other way; nmarg counts such own decisions.
  * pixmask (nullable, [V][H][W]) restricts which pixels are composited.
  * ---------------------------------------------------------------------- */
+#define O_BAND_TILES 4   /* tile rows per compositing task */
+
 void orc_composite(int32_t V, const ocam* cams, int64_t N,
                    const float* mu, const double* conic, const float* opacity,
                    const int64_t* tstarts, const uint32_t* tids,
@@ -306,94 +319,156 @@ void orc_composite(int32_t V, const ocam* cams, int64_t N,
                    double* mom, double* absm, double* slack, int32_t* nmarg, double* raw,
                    double* tfinal, uint8_t* pixmarg, int64_t* counters)
 {
-    /* per-view pixel and tile offsets */
+    /* per-view pixel and tile offsets; tasks are bands of tile rows */
     int64_t* pix_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(V + 1));
     int64_t* tile_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(V + 1));
+    int64_t ntask = 0;
     pix_off[0] = 0; tile_off[0] = 0;
     for (int v = 0; v < V; ++v) {
         int TX = (cams[v].W + O_TILE - 1) / O_TILE, TY = (cams[v].H + O_TILE - 1) / O_TILE;
         pix_off[v + 1] = pix_off[v] + (int64_t)cams[v].W * cams[v].H;
         tile_off[v + 1] = tile_off[v] + (int64_t)TX * TY;
+        ntask += (TY + O_BAND_TILES - 1) / O_BAND_TILES;
     }
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int v = 0; v < V; ++v) {
-        const ocam* c = cams + v;
-        int W = c->W, H = c->H, TX = (W + O_TILE - 1) / O_TILE;
-        int64_t ev = 0, ec = 0;
-        for (int r = 0; r < H; ++r)
-            for (int col = 0; col < W; ++col) {
-                int64_t pi = pix_off[v] + (int64_t)r * W + col;
-                if (pixmask && !pixmask[pi]) continue;
-                int64_t tile = tile_off[v] + (int64_t)(r / O_TILE) * TX + col / O_TILE;
-                double x = col, y = r;
-                double ddx = disp[2 * pi], ddy = disp[2 * pi + 1];
-                int visible = vis ? vis[pi] != 0 : 1;
-                /* static pixel (Sec. 4.5.2): |x' - x| < 1 px, decided in the
-                 * renderer's FP32 (it decides an integer count) */
-                float fdx = disp[2 * pi], fdy = disp[2 * pi + 1];
-                float s2 = fdx * fdx;
-                s2 = s2 + fdy * fdy;
-                int is_static = s2 < 1.0f;
-                double T = 1.0, taint = 0.0;
-                int marg = 0;
-                for (int64_t k = tstarts[tile]; k < tstarts[tile + 1]; ++k) {
-                    uint32_t g = tids[k];
-                    int64_t o = (int64_t)v * N + g;
-                    double dx = x - (double)mu[2 * o], dy = y - (double)mu[2 * o + 1];
-                    const double* cn = conic + 3 * o;
-                    double power = -0.5 * (cn[0] * dx * dx + cn[2] * dy * dy) - cn[1] * dx * dy;
-                    ++ev;
-                    if (power > 0.0) continue;
-                    double alpha = (double)opacity[g] * exp(power);
-                    if (alpha > O_ALPHA_MAX) alpha = O_ALPHA_MAX;
-                    int own_marg = 0;
-                    if (fabs(alpha - O_ALPHA_MIN) <= band_alpha * O_ALPHA_MIN) own_marg = 1;
-                    double test = T * (1.0 - alpha);
-                    double tband = (band_t + 1.5 * taint) * O_T_MIN;
-                    int term_marg = alpha >= O_ALPHA_MIN && fabs(test - O_T_MIN) <= tband;
-                    double w = alpha * T;
-                    double term[16];
-                    term[0] = w; term[1] = w * dx; term[2] = w * dy;
-                    term[3] = w * dx * dx; term[4] = w * dx * dy; term[5] = w * dy * dy;
-                    term[6] = w * ddx; term[7] = w * ddy;
-                    term[8] = w * dx * ddx; term[9] = w * dx * ddy;
-                    term[10] = w * dy * ddx; term[11] = w * dy * ddy;
-                    term[12] = 1.0; term[13] = is_static ? 1.0 : 0.0;
-                    term[14] = is_static ? alpha : 0.0; term[15] = 0.0;
-                    if ((own_marg || term_marg) && visible) {
-                        for (int i = 0; i < 15; ++i) slack[16 * o + i] += fabs(term[i]);
-                        nmarg[o] += 1;
-                    }
-                    if (own_marg || term_marg) marg = 1;
-                    if (alpha < O_ALPHA_MIN) {
-                        if (own_marg) taint += alpha / (1.0 - alpha);
-                        continue;
-                    }
-                    if (test < O_T_MIN) break;
-                    ++ec;
-                    if (visible) {
-                        double* m = mom + 16 * o;
-                        double* a = absm + 16 * o;
-                        for (int i = 0; i < 15; ++i) { m[i] += term[i]; a[i] += fabs(term[i]); }
-                        if (taint > 0.0)
-                            for (int i = 0; i < 12; ++i) slack[16 * o + i] += taint * fabs(term[i]);
-                        if (raw) {
-                            double xv[3] = {x, y, 1.0}, xp[2] = {x + ddx, y + ddy};
-                            double* rr = raw + 15 * o;
-                            for (int i = 0; i < 3; ++i)
-                                for (int j = 0; j < 3; ++j) rr[3 * i + j] += w * xv[i] * xv[j];
-                            for (int i = 0; i < 3; ++i)
-                                for (int j = 0; j < 2; ++j) rr[9 + 2 * i + j] += w * xv[i] * xp[j];
+    int32_t* task_v = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ntask > 0 ? ntask : 1));
+    int32_t* task_r0 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ntask > 0 ? ntask : 1));
+    {
+        int64_t t = 0;
+        for (int v = 0; v < V; ++v) {
+            int TY = (cams[v].H + O_TILE - 1) / O_TILE;
+            for (int b = 0; b < TY; b += O_BAND_TILES) { task_v[t] = v; task_r0[t] = b * O_TILE; ++t; }
+        }
+    }
+    if (counters) memset(counters, 0, sizeof(int64_t) * 2 * (size_t)V);
+#pragma omp parallel
+    {
+        /* this thread's sums for the band it composites, dense over the
+         * Gaussians; `touched` lists the entries written */
+        double* lm = (double*)calloc((size_t)N * 16 + 1, sizeof(double));
+        double* la = (double*)calloc((size_t)N * 16 + 1, sizeof(double));
+        double* ls = (double*)calloc((size_t)N * 16 + 1, sizeof(double));
+        double* lr = raw ? (double*)calloc((size_t)N * 15 + 1, sizeof(double)) : NULL;
+        int32_t* ln = (int32_t*)calloc((size_t)N + 1, sizeof(int32_t));
+        uint8_t* seen = (uint8_t*)calloc((size_t)N + 1, 1);
+        uint32_t* touched = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+#pragma omp for ordered schedule(dynamic, 1)
+        for (int64_t task = 0; task < ntask; ++task) {
+            const int v = task_v[task];
+            const ocam* c = cams + v;
+            const int W = c->W, H = c->H, TX = (W + O_TILE - 1) / O_TILE;
+            const int r0 = task_r0[task];
+            const int r1 = r0 + O_BAND_TILES * O_TILE < H ? r0 + O_BAND_TILES * O_TILE : H;
+            int64_t ev = 0, ec = 0, nt = 0;
+            for (int r = r0; r < r1; ++r)
+                for (int col = 0; col < W; ++col) {
+                    int64_t pi = pix_off[v] + (int64_t)r * W + col;
+                    if (pixmask && !pixmask[pi]) continue;
+                    int64_t tile = tile_off[v] + (int64_t)(r / O_TILE) * TX + col / O_TILE;
+                    double x = col, y = r;
+                    double ddx = disp[2 * pi], ddy = disp[2 * pi + 1];
+                    int visible = vis ? vis[pi] != 0 : 1;
+                    /* static pixel (Sec. 4.5.2): |x' - x| < 1 px, decided in the
+                     * renderer's FP32 (it decides an integer count) */
+                    float fdx = disp[2 * pi], fdy = disp[2 * pi + 1];
+                    float s2 = fdx * fdx;
+                    s2 = s2 + fdy * fdy;
+                    int is_static = s2 < 1.0f;
+                    double T = 1.0, taint = 0.0;
+                    int marg = 0;
+                    for (int64_t k = tstarts[tile]; k < tstarts[tile + 1]; ++k) {
+                        uint32_t g = tids[k];
+                        int64_t o = (int64_t)v * N + g;
+                        double dx = x - (double)mu[2 * o], dy = y - (double)mu[2 * o + 1];
+                        const double* cn = conic + 3 * o;
+                        double power = -0.5 * (cn[0] * dx * dx + cn[2] * dy * dy) - cn[1] * dx * dy;
+                        ++ev;
+                        if (power > 0.0) continue;
+                        double alpha = (double)opacity[g] * exp(power);
+                        if (alpha > O_ALPHA_MAX) alpha = O_ALPHA_MAX;
+                        int own_marg = 0;
+                        if (fabs(alpha - O_ALPHA_MIN) <= band_alpha * O_ALPHA_MIN) own_marg = 1;
+                        double test = T * (1.0 - alpha);
+                        double tband = (band_t + 1.5 * taint) * O_T_MIN;
+                        int term_marg = alpha >= O_ALPHA_MIN && fabs(test - O_T_MIN) <= tband;
+                        double w = alpha * T;
+                        double term[16];
+                        term[0] = w; term[1] = w * dx; term[2] = w * dy;
+                        term[3] = w * dx * dx; term[4] = w * dx * dy; term[5] = w * dy * dy;
+                        term[6] = w * ddx; term[7] = w * ddy;
+                        term[8] = w * dx * ddx; term[9] = w * dx * ddy;
+                        term[10] = w * dy * ddx; term[11] = w * dy * ddy;
+                        term[12] = 1.0; term[13] = is_static ? 1.0 : 0.0;
+                        term[14] = is_static ? alpha : 0.0; term[15] = 0.0;
+                        int writes = ((own_marg || term_marg) && visible) ||
+                                     (alpha >= O_ALPHA_MIN && test >= O_T_MIN && visible);
+                        if (writes && !seen[g]) { seen[g] = 1; touched[nt++] = g; }
+                        if ((own_marg || term_marg) && visible) {
+                            for (int i = 0; i < 15; ++i) ls[16 * (int64_t)g + i] += fabs(term[i]);
+                            ln[g] += 1;
                         }
+                        if (own_marg || term_marg) marg = 1;
+                        if (alpha < O_ALPHA_MIN) {
+                            if (own_marg) taint += alpha / (1.0 - alpha);
+                            continue;
+                        }
+                        if (test < O_T_MIN) break;
+                        ++ec;
+                        if (visible) {
+                            double* m = lm + 16 * (int64_t)g;
+                            double* a = la + 16 * (int64_t)g;
+                            for (int i = 0; i < 15; ++i) { m[i] += term[i]; a[i] += fabs(term[i]); }
+                            if (taint > 0.0)
+                                for (int i = 0; i < 12; ++i) ls[16 * (int64_t)g + i] += taint * fabs(term[i]);
+                            if (lr) {
+                                double xv[3] = {x, y, 1.0}, xp[2] = {x + ddx, y + ddy};
+                                double* rr = lr + 15 * (int64_t)g;
+                                for (int i = 0; i < 3; ++i)
+                                    for (int j = 0; j < 3; ++j) rr[3 * i + j] += w * xv[i] * xv[j];
+                                for (int i = 0; i < 3; ++i)
+                                    for (int j = 0; j < 2; ++j) rr[9 + 2 * i + j] += w * xv[i] * xp[j];
+                            }
+                        }
+                        if (own_marg) taint += alpha / (1.0 - alpha);
+                        T = test;
                     }
-                    if (own_marg) taint += alpha / (1.0 - alpha);
-                    T = test;
+                    if (tfinal) tfinal[pi] = T;
+                    if (pixmarg) pixmarg[pi] = (uint8_t)(marg || taint > 0.0);
                 }
-                if (tfinal) tfinal[pi] = T;
-                if (pixmarg) pixmarg[pi] = (uint8_t)(marg || taint > 0.0);
+            /* add the band's sums to the view's records, bands in order
+             * (the FP64 sums are then independent of the thread count) */
+#pragma omp ordered
+            {
+                for (int64_t i = 0; i < nt; ++i) {
+                    const uint32_t g = touched[i];
+                    const int64_t o = (int64_t)v * N + g;
+                    for (int k = 0; k < 16; ++k) {
+                        mom[16 * o + k] += lm[16 * (int64_t)g + k];
+                        absm[16 * o + k] += la[16 * (int64_t)g + k];
+                        slack[16 * o + k] += ls[16 * (int64_t)g + k];
+                        lm[16 * (int64_t)g + k] = la[16 * (int64_t)g + k] = ls[16 * (int64_t)g + k] = 0.0;
+                    }
+                    if (lr)
+                        for (int k = 0; k < 15; ++k) {
+                            raw[15 * o + k] += lr[15 * (int64_t)g + k];
+                            lr[15 * (int64_t)g + k] = 0.0;
+                        }
+                    nmarg[o] += ln[g];
+                    ln[g] = 0;
+                    seen[g] = 0;
+                }
+                if (counters) { counters[2 * v] += ev; counters[2 * v + 1] += ec; }
             }
-        if (counters) { counters[2 * v] = ev; counters[2 * v + 1] = ec; }
+        }
+        free(lm); free(la); free(ls); free(lr); free(ln); free(seen); free(touched);
     }
+    free(task_v);
+    free(task_r0);
     free(pix_off);
     free(tile_off);
 }
+
+/* Threads used by the parallel loops above (OpenMP's current setting), and a
+ * way to change it (the CPU baseline times one thread as well as all). */
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }

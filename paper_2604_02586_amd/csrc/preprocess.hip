@@ -75,8 +75,12 @@ __global__ void __launch_bounds__(256) k_preprocess(
     const float m0 = means[3 * g], m1 = means[3 * g + 1], m2 = means[3 * g + 2];
     float qw = quats[4 * g], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
     float s0 = scales[3 * g], s1 = scales[3 * g + 1], s2 = scales[3 * g + 2];
-    if (scale_mode == 1) { s0 = expf(s0); s1 = expf(s1); s2 = expf(s2); }
     float o = opac[g];
+    // a Gaussian with any non-finite parameter is culled in every view
+    const bool finite_in = isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(qw) && isfinite(qx) &&
+                           isfinite(qy) && isfinite(qz) && isfinite(s0) && isfinite(s1) && isfinite(s2) &&
+                           isfinite(o);
+    if (scale_mode == 1) { s0 = expf(s0); s1 = expf(s1); s2 = expf(s2); }
     if (opacity_mode == 1) o = 1.0f / (1.0f + expf(-o));
 
     // FP32 rotation of the normalised quaternion (fixed order).
@@ -145,7 +149,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
         ushort4 rc = make_ushort4(0, 0, 0, 0);
         uint32_t key = 0xFFFFFFFFu;
         float cov[3] = {0.f, 0.f, 0.f};
-        bool ok = pz > prm.near_z;
+        bool ok = finite_in && pz > prm.near_z;
         if (ok) {
             float ux = px / pz, uy = py / pz;
             float mx = c.fx * ux + c.cx;

@@ -40,6 +40,11 @@ __global__ void __launch_bounds__(256) k_solve_views(const float4* __restrict__ 
     if (n < (double)prm.pix_min) f |= 4;
     if (!(Sw >= prm.wsum_min)) f |= 8;
     if (!(det >= prm.det_min)) f |= 16;
+    // a non-finite track leaves non-finite sums in the record
+    if (!(isfinite(a0.x) && isfinite(a0.y) && isfinite(a0.z) && isfinite(a0.w) && isfinite(a1.x) &&
+          isfinite(a1.y) && isfinite(a1.z) && isfinite(a1.w) && isfinite(a2.x) && isfinite(a2.y) &&
+          isfinite(a2.z) && isfinite(a2.w) && isfinite(a3.x)))
+        f |= 32;
     {
         // scale-invariant near-singularity: pixel offsets (nearly) collinear
         const double iw = Sw > 0.0 ? 1.0 / Sw : 0.0;
@@ -181,6 +186,7 @@ struct TriArgs {
     const float* means_in;
     const float* quats_in;
     const float* scales_in;
+    const float* opacity_in;
     float* means_out;
     float* quats_out;
     float* scales_out;
@@ -214,6 +220,7 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
         const float2 t = a.wn[o];
         sw += (double)t.x;
         nt += (double)t.y;
+        if (a.vflags[o] & 32) st |= 256;
         if (a.vflags[o] != 1) continue;
         ++nv;
         const tg_camera& c = cams.cam[v];
@@ -235,7 +242,7 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
     if (nv < prm.views_min) st |= 4;
     if (!(sw >= prm.wsum_total_min)) st |= 8;
     if (nt < (double)prm.pix_total_min) st |= 16;
-    if (st == 0) {
+    if ((st & ~256u) == 0) {
         double E[16];
         jacobi_eig<4>(M, E);
         int kmin = 0;
@@ -248,7 +255,7 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
         const double hn = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2] + h[3] * h[3]);
         if (!(fabs(h[3]) >= 1e-12 * hn)) st |= 64;
         double mu3[3] = {0, 0, 0};
-        if (st == 0) {
+        if ((st & ~256u) == 0) {
             mu3[0] = h[0] / h[3];
             mu3[1] = h[1] / h[3];
             mu3[2] = h[2] / h[3];
@@ -259,7 +266,7 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
                 if (!(pz > prm.near_z)) st |= 128;
             }
         }
-        if (st == 0) {
+        if ((st & ~256u) == 0) {
             st |= 1;
             nm[0] = (float)mu3[0];
             nm[1] = (float)mu3[1];
@@ -435,15 +442,18 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
 // solved, accumulated alpha, pixels); a non-candidate is copied and done.
 __device__ __forceinline__ uint32_t tri_light(const TriArgs& a, const tg_params& prm, int64_t g) {
     int nv = 0;
+    bool nonfinite = false;
     double sw = 0.0, nt = 0.0;
     for (int v = 0; v < a.V; ++v) {
         const int64_t o = (int64_t)v * a.N + g;
         const float2 t = a.wn[o];
         sw += (double)t.x;
         nt += (double)t.y;
-        if (a.vflags[o] == 1) ++nv;
+        const uint8_t f = a.vflags[o];
+        if (f == 1) ++nv;
+        if (f & 32) nonfinite = true;
     }
-    uint32_t st = 0;
+    uint32_t st = nonfinite ? 256u : 0u;
     if (nv < prm.views_min) st |= 4;
     if (!(sw >= prm.wsum_total_min)) st |= 8;
     if (nt < (double)prm.pix_total_min) st |= 16;
@@ -468,13 +478,29 @@ __global__ void __launch_bounds__(TRI_THREADS) k_triangulate(TriArgs a, CamPack 
     for (int it = 0; it < TRI_ITEMS; ++it) {
         const int64_t g = base + (int64_t)it * TRI_THREADS + t;
         if (g >= a.N) break;
-        const uint32_t st = tri_light(a, prm, g);
-        if (st == 0) {
+        uint32_t st = tri_light(a, prm, g);
+        if ((st & ~256u) == 0) {
             cand[atomicAdd(&cn, 1u)] = (uint32_t)(g - base);
         } else {
-            for (int i = 0; i < 3; ++i) a.means_out[3 * g + i] = a.means_in[3 * g + i];
-            for (int i = 0; i < 4; ++i) a.quats_out[4 * g + i] = a.quats_in[4 * g + i];
-            for (int i = 0; i < 3; ++i) a.scales_out[3 * g + i] = a.scales_in[3 * g + i];
+            // not updated: copied (a Gaussian with a non-finite parameter
+            // is always here, culled in every view)
+            bool fin = isfinite(a.opacity_in[g]);
+            for (int i = 0; i < 3; ++i) {
+                const float x = a.means_in[3 * g + i];
+                fin = fin && isfinite(x);
+                a.means_out[3 * g + i] = x;
+            }
+            for (int i = 0; i < 4; ++i) {
+                const float x = a.quats_in[4 * g + i];
+                fin = fin && isfinite(x);
+                a.quats_out[4 * g + i] = x;
+            }
+            for (int i = 0; i < 3; ++i) {
+                const float x = a.scales_in[3 * g + i];
+                fin = fin && isfinite(x);
+                a.scales_out[3 * g + i] = x;
+            }
+            if (!fin) st |= 256;
             if (a.status) a.status[g] = st;
         }
     }
@@ -509,7 +535,7 @@ extern "C" tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_ne
     if (!mu2d_new || !cov2d_new || !vflags || !wn || !s || !g_in || !cams || !p || !g_out || N < 0 || V < 1)
         return TG_ERR_INVALID_ARG;
     if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
-    if (!g_in->means || !g_in->quats || !g_in->scales || !g_out->means || !g_out->quats ||
+    if (!g_in->means || !g_in->quats || !g_in->scales || !g_in->opacity || !g_out->means || !g_out->quats ||
         !g_out->scales)
         return TG_ERR_INVALID_ARG;
     if (g_in->scale_mode < 0 || g_in->scale_mode > 1) return TG_ERR_INVALID_ARG;
@@ -523,6 +549,7 @@ extern "C" tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_ne
     a.means_in = g_in->means;
     a.quats_in = g_in->quats;
     a.scales_in = g_in->scales;
+    a.opacity_in = g_in->opacity;
     a.means_out = g_out->means;
     a.quats_out = g_out->quats;
     a.scales_out = g_out->scales;

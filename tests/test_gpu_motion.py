@@ -5,7 +5,8 @@ import pytest
 
 import oracle
 import synth
-from helpers import check_end_to_end, compare_accumulators, dump, log, oracle_full, run_gpu
+from helpers import (check_accumulate, check_bins, check_end_to_end, check_preprocess, check_solve, dump, log,
+                     oracle_full, run_gpu)
 
 pytestmark = pytest.mark.gpu
 
@@ -36,95 +37,20 @@ def pair(request):
 
 
 def test_preprocess_parity(pair):
-    case, wl, ref, gpu = pair
-    g = ref["geom"]
-    valid = g.valid.astype(bool)
-    rect = gpu["rect"].astype(np.int32)
-    gvalid = (rect[..., 2] > rect[..., 0]) & (rect[..., 3] > rect[..., 1])
-    np.testing.assert_array_equal(gvalid, valid)
-    # integer-deciding FP32 quantities: bit-exact
-    np.testing.assert_array_equal(gpu["key"][valid], g.key[valid])
-    np.testing.assert_array_equal(rect[valid], g.rect[valid])
-    np.testing.assert_array_equal(gpu["rec"][..., 0:2][valid].view(np.uint32), g.mu[valid].view(np.uint32))
-    # FP64-formed conic / covariance, rounded once to FP32
-    conic = gpu["rec"][..., 2:5][valid].astype(np.float64)
-    np.testing.assert_allclose(conic, ref["conic"][valid], rtol=2e-6, atol=1e-9 * np.abs(ref["conic"]).max())
-    cov = gpu["cov2d"][valid].astype(np.float64)
-    scale = np.abs(ref["cov"][valid]).max(-1, keepdims=True)
-    assert np.all(np.abs(cov - ref["cov"][valid]) <= 2e-6 * scale + 1e-12)
-    np.testing.assert_array_equal(gpu["rec"][..., 5][valid], np.broadcast_to(wl.scene.opacity, valid.shape)[valid])
+    check_preprocess(*pair)
 
 
 def test_bin_sort_bit_exact(pair):
-    case, wl, ref, gpu = pair
-    V, N = ref["geom"].key.shape
-    assert gpu["overflow"] == 0
-    orders = oracle.depth_order(ref["geom"])
-    for v in range(V):
-        o = orders[v]
-        np.testing.assert_array_equal(gpu["order"][v, :o.size], o)
-    mt = gpu["mt"]
-    cell = 1 << 3
-    starts, ids = oracle.cell_lists(ref["geom"], wl.cams, cell)
-    assert gpu["n_pairs"] == ids.size
-    rg = gpu["cell_ranges"].reshape(-1, 2)
-    assert rg.shape[0] == starts.size - 1
-    for c in range(rg.shape[0]):
-        a, b = int(starts[c]), int(starts[c + 1])
-        if a == b:
-            assert rg[c, 0] == rg[c, 1]
-            continue
-        np.testing.assert_array_equal(gpu["cell_ids"][rg[c, 0]:rg[c, 1]], ids[a:b])
-    # expanded per-tile lists equal the brute-force per-tile lists
-    from paper_2604_02586_amd import api
-    tids, tr = api.bin_expand(mt.splats, mt.bins, N, wl.cams, mt.params)
-    tids = tids.cpu().numpy().view(np.uint32)
-    tr = tr.cpu().numpy().view(np.uint32)
-    ts, tl = oracle.cell_lists(ref["geom"], wl.cams, 1)
-    assert tids.size == tl.size
-    for t in range(tr.shape[0]):
-        np.testing.assert_array_equal(tids[tr[t, 0]:tr[t, 1]], tl[ts[t]:ts[t + 1]])
+    check_bins(*pair)
 
 
 def test_accumulate_parity(pair):
-    case, wl, ref, gpu = pair
-    comp = ref["comp"]
-    nbad, ntot, info = compare_accumulators(gpu["acc"], comp)
-    log(f"[{case}] accumulators: {nbad}/{ntot} outside tolerance, {info}")
-    assert nbad == 0, info
-    # final transmittance per pixel (Sigma w = 1 - T_final), marginal pixels excluded
-    ok = comp["pixmarg"] == 0
-    np.testing.assert_allclose(gpu["t_final"][ok], comp["tfinal"][ok], rtol=1e-4, atol=1e-6)
-    # pair counters in the sequential semantics: contributions are the same;
-    # evaluations can only drop (exact culling of Gaussians whose alpha stays
-    # below alpha_min on a whole tile)
-    ev, ec = comp["counters"].sum(0)
-    assert abs(int(gpu["stats"][1]) - ec) <= max(3, 1e-4 * ec)
-    assert ec <= int(gpu["stats"][0]) <= ev + max(3, 1e-4 * ev)
-    log(f"[{case}] pairs: evaluated {int(gpu['stats'][0])} (oracle lists {ev}), contributing "
-        f"{int(gpu['stats'][1])}, pixel steps {int(gpu['stats'][2])}")
+    check_accumulate(*pair)
 
 
 def test_solve_views_parity(pair):
-    case, wl, ref, gpu = pair
-    sv = ref["sv"]
-    comp = ref["comp"]
-    # flags agree except where the oracle's value sits within 1e-3 of a threshold
-    m = comp["mom"]
-    near = (np.abs(m[..., oracle.S_W] / oracle.WSUM_MIN - 1) < 1e-3) | \
-           (np.abs(sv["det"] / oracle.DET_MIN - 1) < 1e-2) | (comp["slack"][..., 0] > 0)
-    diff = (gpu["vflags"] != sv["flags"]) & ~near
-    assert diff.sum() <= max(2, 1e-3 * diff.size), (diff.sum(), diff.size)
-    both = (gpu["vflags"] == oracle.VF_OK) & (sv["flags"] == oracle.VF_OK) & ~near
-    # conditioning-aware: relative perturbation 1e-5 of the oracle's moments
-    V1, V2 = oracle.v1_v2(m)
-    cond = np.linalg.cond(np.where(both[..., None, None], V1, np.eye(3)))
-    well = both & (cond < 1e4)
-    err_mu = np.abs(gpu["mu_new"][well] - sv["mu_new"][well]).max(-1)
-    assert np.all(err_mu <= 1e-2 + 1e-6 * cond[well] * 10), err_mu.max()
-    log(f"[{case}] solve: {well.sum()} well-conditioned views, max |dmu'| = {err_mu.max():.2e} px")
+    check_solve(*pair)
 
 
 def test_end_to_end_parity(pair):
-    case, wl, ref, gpu = pair
-    check_end_to_end(case, wl, ref, gpu)
+    check_end_to_end(*pair)

@@ -199,7 +199,7 @@ def test_full_size_sampled_pixels():
     pv, py, px = lin // (H * W), (lin // W) % H, lin % W
     print(f"full size n={n} views={len(cams)}", flush=True)
     rp = _ref_params(p)
-    ref, marg = raster_ref.render(*rp, cams, bg=_bg(), pixels=(pv, px, py), return_marginal=True)
+    ref, marg, slack = raster_ref.render(*rp, cams, bg=_bg(), pixels=(pv, px, py), return_slack=True)
     gp = _gpu_params(p)
     rc = RasterContext(cams, n, bg=_bg())
     img = rasterize(*gp, rc)
@@ -207,10 +207,13 @@ def test_full_size_sampled_pixels():
     got = img.detach()[torch.tensor(pv), torch.tensor(py), torch.tensor(px)].cpu().double().numpy()
     ok = ~marg.numpy()
     err = np.abs(got - ref.detach().numpy()).max(-1)
-    print(f"max err {err[ok].max():.3e} marginal {int((~ok).sum())}")
-    # a pixel over hundreds of Gaussians has a decision within 1e-3 of a
-    # threshold more often than the small scenes' pixels
-    assert ok.sum() >= 0.8 * P and err[ok].max() <= 1e-4
+    sl = slack.numpy()
+    print(f"max err {err[ok].max():.3e}; marginal pixels {int((~ok).sum())} of {P}, "
+          f"max err/slack there {(err[~ok] / (1e-4 + sl[~ok])).max() if (~ok).any() else 0:.3f}")
+    # every pixel: within 1e-4, plus, where a decision sits within 1e-3 of
+    # its threshold, the most that flipping it can move the colour
+    assert np.all(err <= 1e-4 + sl), (err - sl).max()
+    assert err[ok].max() <= 1e-4
     # gradients from the sampled pixels only
     wts = torch.tensor(rng.standard_normal((P, 3))) * torch.tensor(ok)[:, None]
     (ref * wts).sum().backward()

@@ -633,3 +633,133 @@ def test_generator_outliers_visibility_and_cap():
     assert abs(p - 0.9) < 3 * math.sqrt(0.09 / n) + 1e-3
     big = (np.linalg.norm(disp, axis=-1) > 60).mean()
     assert 0.02 < big < 0.06
+
+
+# ----------------------------------------------------------------- static-pixel slots (Sec. 4.5.2)
+@pytest.mark.parametrize("disp,static", [((0.5, 0.0), True), ((0.0, -0.5), True),
+                                         ((np.nextafter(np.float32(1), np.float32(0)), 0.0), True),
+                                         ((1.0, 0.0), False), ((0.0, -1.0), False), ((0.8, 0.7), False)])
+def test_static_slots_count_and_alpha(disp, static):
+    """A covered pixel whose track moves less than 1 px adds 1 to slot 13
+    and its alpha (not the weight alpha T) to slot 14; at |d| = 1 it is not
+    static.  Two Gaussians front to back make alpha and w differ for the one
+    behind (w = alpha (1 - alpha_front)), so a weight in slot 14 fails, and
+    the boundary cases fail a <= in place of <."""
+    cam = axis_camera(4.0)
+    sc = scene_of([[0, 0, 0.5], [0, 0, -0.5]], [[1, 0, 0, 0]] * 2, [[0.1, 0.1, 0.1], [0.12, 0.12, 0.12]],
+                  [0.6, 0.8])
+    px = py = 31
+    g, cov, conic, r = _single_pixel_run(sc, cam, px, py, disp=disp)
+    m = r["mom"][0]
+    al = []
+    for i in range(2):
+        mu = g.mu[0, i].astype(np.float64)
+        d = np.array([px - mu[0], py - mu[1]])
+        cn = conic[0, i]
+        power = -0.5 * (cn[0] * d[0] ** 2 + cn[2] * d[1] ** 2) - cn[1] * d[0] * d[1]
+        al.append(min(0.99, float(sc.opacity[i]) * math.exp(power)))
+    assert m[1, oracle.S_N] == 1 and m[0, oracle.S_N] == 1
+    if static:
+        np.testing.assert_array_equal(m[:, oracle.S_STATN], [1.0, 1.0])
+        np.testing.assert_allclose(m[1, oracle.S_STATA], al[1], rtol=1e-12)    # front: alpha = w
+        np.testing.assert_allclose(m[0, oracle.S_STATA], al[0], rtol=1e-12)    # behind: alpha, not w
+        assert abs(m[0, oracle.S_STATA] - m[0, oracle.S_W]) > 0.05
+    else:
+        np.testing.assert_array_equal(m[:, oracle.S_STATN], [0.0, 0.0])
+        np.testing.assert_array_equal(m[:, oracle.S_STATA], [0.0, 0.0])
+    # an invisible track adds nothing, static or not
+    g, cov, conic, r = _single_pixel_run(sc, cam, px, py, disp=disp, vis=0)
+    np.testing.assert_array_equal(r["mom"][0, :, :15], 0.0)
+
+
+# ----------------------------------------------------------------- tile rectangle (Sec. 3.1, Eq. 1)
+def test_tile_rectangle_closed_form():
+    """An axis-aligned Gaussian off the optical axis: Eq. 1 gives
+    Sigma_2D = J diag(s^2) J^T with J = [[f/z, 0, -f x/z^2], [0, f/z, -f y/z^2]]
+    in closed form; the rectangle is the tiles met by the square of half
+    side ceil(3 sqrt(lambda_max(Sigma_2D + 0.3 I))) about the centre.  The
+    values are chosen away from every rounding boundary, so the FP32
+    rectangle must equal this one exactly (one tile more or less fails)."""
+    f, z, W = 200.0, 4.0, 256
+    cam = synth.Camera(R=np.eye(3, dtype=np.float32), t=np.array([0, 0, z], np.float32), fx=f, fy=f,
+                       cx=(W - 1) / 2, cy=(W - 1) / 2, W=W, H=W)
+    for (x, y, sx, sy, sz) in [(0.3, -0.2, 0.2, 0.1, 0.05), (-0.43, 0.35, 0.04, 0.15, 0.1),
+                               (0.13, 0.6, 0.3, 0.3, 0.02)]:
+        sc = scene_of([[x, y, 0.0]], [[1, 0, 0, 0]], [[sx, sy, sz]], [0.5])
+        g = oracle.geometry(sc, [cam])
+        xf, yf = np.float64(np.float32(x)), np.float64(np.float32(y))
+        s = np.asarray([sx, sy, sz], np.float32).astype(np.float64)
+        a = (f / z) ** 2 * s[0] ** 2 + (f * xf / z ** 2) ** 2 * s[2] ** 2 + 0.3
+        b = (f * xf / z ** 2) * (f * yf / z ** 2) * s[2] ** 2
+        c = (f / z) ** 2 * s[1] ** 2 + (f * yf / z ** 2) ** 2 * s[2] ** 2 + 0.3
+        lmax = 0.5 * (a + c) + math.sqrt(0.25 * (a - c) ** 2 + b * b)
+        r3 = 3.0 * math.sqrt(lmax)
+        assert abs(r3 - round(r3)) > 1e-3
+        rad = math.ceil(r3)
+        mu = np.array([f * xf / z + (W - 1) / 2, f * yf / z + (W - 1) / 2])
+        np.testing.assert_allclose(g.mu[0, 0], mu, atol=1e-4)
+        lo, hi = (mu - rad) / 16.0, (mu + rad) / 16.0
+        assert np.all(np.abs(lo - np.round(lo)) > 1e-3) and np.all(np.abs(hi - np.round(hi)) > 1e-3)
+        T = W // 16
+        want = [max(0, math.floor(lo[0])), max(0, math.floor(lo[1])), min(T, math.floor(hi[0]) + 1),
+                min(T, math.floor(hi[1]) + 1)]
+        np.testing.assert_array_equal(g.rect[0, 0], want)
+
+
+# ----------------------------------------------------------------- non-finite inputs
+def test_nonfinite_gaussian_equals_removed_gaussian():
+    """A Gaussian with a non-finite parameter is culled in every view, so the
+    rest of the frame equals the frame without it (bit for bit: same lists,
+    same sums); it reports status 256 and is copied."""
+    wl = synth.make_workload("small", seed=31, n=600)
+    bad = np.array([3, 50, 51, 200, 599])
+    sc = synth.Scene(means=wl.scene.means.copy(), quats=wl.scene.quats.copy(), scales=wl.scene.scales.copy(),
+                     opacity=wl.scene.opacity.copy(), rgb=wl.scene.rgb)
+    sc.means[3, 1] = np.nan
+    sc.quats[50, 0] = np.inf
+    sc.scales[51, 2] = np.nan
+    sc.opacity[200] = np.nan
+    sc.means[599, 0] = -np.inf
+    keep = np.setdiff1d(np.arange(sc.n), bad)
+    sub = synth.Scene(means=wl.scene.means[keep], quats=wl.scene.quats[keep], scales=wl.scene.scales[keep],
+                      opacity=wl.scene.opacity[keep], rgb=wl.scene.rgb[keep])
+    r = oracle.motion_transfer(sc, wl.cams, wl.disp, wl.vis)
+    r0 = oracle.motion_transfer(sub, wl.cams, wl.disp, wl.vis)
+    tri, tri0 = r["tri"], r0["tri"]
+    assert np.all(tri["status"][bad] & oracle.ST_NONFINITE)
+    assert not np.any(tri["status"][bad] & (oracle.ST_POS | oracle.ST_COV))
+    assert np.all(r["geom"].valid[:, bad] == 0)
+    np.testing.assert_array_equal(tri["status"][keep], tri0["status"])
+    np.testing.assert_array_equal(r["comp"]["mom"][:, keep], r0["comp"]["mom"])
+    np.testing.assert_array_equal(tri["means"][keep], tri0["means"])
+    np.testing.assert_array_equal(tri["quats"][keep], tri0["quats"])
+    np.testing.assert_array_equal(tri["means"][bad], sc.means[bad].astype(np.float64))
+
+
+def test_nonfinite_tracks_flag_exactly_the_views_they_reach():
+    """A non-finite track poisons the sums of every (view, Gaussian) record
+    its pixel feeds (visible and contributing); exactly those views get
+    flag 32 and are left out of the multi-view update, and their Gaussians
+    report status 256.  The records it feeds are found by compositing only
+    the poisoned pixels."""
+    wl = synth.make_workload("small", seed=32, n=800)
+    disp = wl.disp.copy()
+    pix = [(0, 40, 60), (1, 70, 20), (2, 64, 64), (3, 10, 100)]
+    mask = np.zeros(wl.vis.shape, np.uint8)
+    for v, y, x in pix:
+        disp[v, y, x, 0] = np.nan
+        mask[v, y, x] = 1
+    vis = np.ones_like(wl.vis)
+    r = oracle.motion_transfer(wl.scene, wl.cams, disp, vis)
+    g = r["geom"]
+    only = oracle.composite(wl.scene, wl.cams, g, r["conic"], r["lists"], wl.disp, vis, pixmask=mask)
+    reached = only["mom"][..., oracle.S_N] > 0
+    assert reached.sum() >= 4
+    np.testing.assert_array_equal((r["sv"]["flags"] & oracle.VF_NONFINITE) > 0, reached)
+    st = r["tri"]["status"]
+    np.testing.assert_array_equal((st & oracle.ST_NONFINITE) > 0, reached.any(0))
+    # the remaining views of those Gaussians still count as in any other frame
+    clean = oracle.motion_transfer(wl.scene, wl.cams, wl.disp, vis)
+    untouched = ~reached.any(0)
+    assert np.isfinite(r["tri"]["means"]).all()
+    np.testing.assert_array_equal(r["sv"]["flags"][:, untouched], clean["sv"]["flags"][:, untouched])

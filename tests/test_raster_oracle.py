@@ -174,3 +174,24 @@ def test_ssim_constant_images_closed_form():
     inner = raster_ref.ssim_map(x, y)[0, 0, 5:-5, 5:-5]
     np.testing.assert_allclose(inner.numpy(), (2 * a * b + raster_ref.SSIM_C1) / (a * a + b * b + raster_ref.SSIM_C1),
                                rtol=1e-12)
+
+
+def test_marginal_slack_bounds_flipped_decisions():
+    """The slack bound of the reference: moving every threshold (alpha_min,
+    the 0.99 clamp, T_min) anywhere inside the marginal band changes no
+    pixel's colour by more than its slack (and unmarked pixels not at all)."""
+    sc = _scene(300, 11, spread=0.4)
+    cams = synth.ring_cameras(2, 3.0, 48, 40)
+    params = _torch_params(sc)
+    bg = (0.2, 0.1, 0.0)
+    m = 1e-2                       # a wide band, so that many pixels are marginal
+    base, marg, slack = raster_ref.render(*params, cams, bg=bg, margin_rel=m, return_slack=True)
+    base, marg, slack = base.detach().numpy(), marg.numpy(), slack.numpy()
+    assert marg.sum() > 20
+    for fa, fc, ft in [(1 - 0.9 * m, 1, 1), (1 + 0.9 * m, 1, 1), (1, 1 - 0.9 * m, 1), (1, 1, 1 - 0.9 * m),
+                       (1, 1, 1 + 0.9 * m), (1 + 0.9 * m, 1 - 0.9 * m, 1 + 0.9 * m)]:
+        img = raster_ref.render(*params, cams, bg=bg, alpha_min=fa / 255.0, alpha_max=0.99 * fc,
+                                t_min=1e-4 * ft, margin_rel=m).detach().numpy()
+        d = np.abs(img - base).max(-1)
+        assert np.all(d[~marg] <= 1e-12)
+        assert np.all(d <= slack + 1e-12), (d - slack).max()

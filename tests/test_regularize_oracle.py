@@ -128,3 +128,78 @@ def test_median_of_eight_is_mean_of_middle_pair():
     x = rng.standard_normal((100, 8))
     xs = np.sort(x, 1)
     np.testing.assert_allclose(np.median(x, 1), 0.5 * (xs[:, 3] + xs[:, 4]), rtol=0, atol=0)
+
+
+def _propagation_scene():
+    """One unsolved target at the origin and 8 clusters of 8 solved
+    Gaussians.  Cluster i sits on a ray at 45 i degrees: its seed s_i at
+    radius 1 + 0.001 i (the 8 seeds are the target's 8 nearest solved
+    Gaussians, nearest first by i) and 7 companions 0.01-0.07 further out on
+    the ray (each cluster is its own members' 8-neighbourhood; clusters are
+    0.76 apart).  The companions move by c_i, the seed by c_i + 0.5 (a raw
+    outlier), so the filtered change of every member is c_i exactly: the
+    median of 8 values of which 7 equal c_i."""
+    base = np.array([1.0, -2.0, 0.5, 0.3, -0.2, 0.4, 0.1, 0.05, -0.08])
+    c = np.stack([0.01 * i * i * base for i in range(8)])          # asymmetric in i
+    pts, chg, role = [np.zeros(3)], [np.zeros(9)], [-1]
+    for i in range(8):
+        u = np.array([np.cos(np.pi / 4 * i), np.sin(np.pi / 4 * i), 0.0])
+        r = 1.0 + 0.001 * i
+        pts.append(r * u)
+        chg.append(c[i] + 0.5)
+        role.append(i)
+        for j in range(1, 8):
+            pts.append((r + 0.01 * j) * u)
+            chg.append(c[i])
+            role.append(i)
+    pts, chg, role = np.array(pts), np.array(chg), np.array(role)
+    n = len(pts)
+    rng = np.random.default_rng(9)
+    q0 = rng.standard_normal((n, 4))
+    q0 /= np.linalg.norm(q0, axis=1, keepdims=True)
+    q0[q0[:, 0] < 0] *= -1
+    s0 = np.full((n, 3), 0.1)
+    R1 = rg.rot_zyx(chg[:, 3:6]) @ oracle.quat_to_rot(q0)
+    q1 = oracle.rot_to_quat(R1)
+    status = np.full(n, oracle.ST_POS | oracle.ST_COV, np.uint32)
+    status[0] = oracle.ST_FEW_VIEWS                                   # the target
+    acc = np.zeros((2, n, 16), np.float32)                            # nothing static
+    return dict(m0=pts, q0=q0, s0=s0, m1=pts + chg[:, 0:3], q1=q1, s1=s0 + chg[:, 6:9], status=status,
+                acc=acc, c=c, outlier=c + 0.5)
+
+
+def _target_change(sc):
+    m, q, s, reg = rg.regularize(sc["m0"], sc["q0"], sc["s0"], sc["m1"], sc["q1"], sc["s1"], sc["status"],
+                                 sc["acc"])
+    assert reg[0] == rg.RG_PROPAGATED and (reg[1:] == rg.RG_FILTERED).all()
+    e = rg.euler_zyx(oracle.quat_to_rot(q[0:1]) @ oracle.quat_to_rot(sc["q0"][0:1]).swapaxes(-1, -2))[0]
+    return np.concatenate([m[0] - sc["m0"][0], e, s[0] - sc["s0"][0]])
+
+
+def test_propagation_is_mean_of_filtered_neighbour_changes():
+    """Sec. 4.5.2: an unsolved Gaussian takes the component-wise mean of its
+    K = 8 nearest solved Gaussians' filtered (median) changes; the expected
+    value is the mean of the 8 clusters' c_i, written out by hand."""
+    sc = _propagation_scene()
+    want = sc["c"].mean(0)
+    got = _target_change(sc)
+    np.testing.assert_allclose(got, want, atol=1e-9)
+    # the construction separates the readings a mistake would take
+    assert np.abs(np.median(sc["c"], 0) - want).max() > 0.01        # median instead of mean
+    assert np.abs(sc["outlier"].mean(0) - want).max() > 0.1         # raw instead of filtered
+    assert np.abs(sc["c"][:4].mean(0) - want).max() > 0.01          # K = 4
+
+
+@pytest.mark.parametrize("mistake", ["median", "raw", "k4"])
+def test_propagation_pin_catches_planted_mistakes(monkeypatch, mistake):
+    sc = _propagation_scene()
+    if mistake == "median":
+        monkeypatch.setattr(rg, "propagate", lambda vals: np.median(vals, axis=1))
+    elif mistake == "raw":
+        # each solved Gaussian passes on its own raw change (its nearest
+        # neighbour is itself) instead of the filtered one
+        monkeypatch.setattr(rg, "median_filter", lambda vals: vals[:, 0])
+    else:
+        monkeypatch.setattr(rg, "K", 4)
+    got = _target_change(sc)
+    assert not np.allclose(got, sc["c"].mean(0), atol=1e-6)
