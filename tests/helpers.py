@@ -84,32 +84,51 @@ def rotation_angle_deg(qa, qb):
     return np.degrees(2 * np.arccos(d))
 
 
-def sensitivity_mask(wl, ref, rel=1e-5, seeds=(1, 2), pos_tol=1e-3, rot_tol=0.05):
-    """Gaussians whose oracle result moves by more than half the tolerance
-    when the oracle's own FP64 accumulators are perturbed by `rel` (the size
-    of FP32 accumulation error).  Those results are not determined at FP32
-    input precision and are excluded from strict comparison."""
+# Relative sizes of the perturbations of the oracle's FP64 accumulators that
+# model FP32 accumulation: 1e-5 bounds the largest GPU-vs-oracle accumulator
+# error measured at the full shapes (5e-6 relative to sum|term|; median 1e-7),
+# 1e-6 its 99.9th percentile.  The method's response is not linear in the
+# perturbation (thresholds, eigenvector swaps), so both sizes are taken.
+SENS_REL = (1e-5, 1e-6)
+SENS_SEEDS = (1, 2)
+
+
+def _sigma3d(quats, scales):
+    R = oracle.quat_to_rot(np.asarray(quats, np.float64))
+    return R @ (np.asarray(scales, np.float64)[:, :, None] ** 2 * np.swapaxes(R, -1, -2))
+
+
+def sensitivity(wl, ref):
+    """Per Gaussian, the largest change of the oracle's own result when its
+    FP64 accumulators are perturbed at the size of FP32 accumulation error
+    (SENS_REL, SENS_SEEDS) and every decision within its marginal band is
+    moved anywhere inside its slack: 'flip' (the status changes), 'dp'
+    (position), 'ang' (rotation, degrees), 'sc' (relative scale), 'sig'
+    (relative Frobenius change of Sigma_3D').  Computed from the oracle
+    alone, so nothing on the GPU side can widen it."""
     comp, geom, cov = ref["comp"], ref["geom"], ref["cov"]
-    unstable = np.zeros(wl.scene.n, bool)
-    for s in seeds:
-        rng = np.random.default_rng(s)
-        mom = comp["mom"] * (1.0 + rel * rng.standard_normal(comp["mom"].shape))
-        # decisions within a band of their thresholds may go the other way in
-        # FP32: move each entry anywhere inside its slack bound, and the pixel
-        # counts by up to the number of such decisions
-        mom = mom + comp["slack"] * rng.uniform(-1.0, 1.0, comp["mom"].shape)
-        mom[..., 12:] = comp["mom"][..., 12:]
-        mom[..., 12] += np.round(comp["nmarg"] * rng.uniform(-1.0, 1.0, comp["nmarg"].shape))
-        sv = oracle.solve_views(mom, geom.mu, cov, geom.valid)
-        tri = oracle.triangulate(wl.scene, wl.cams, sv, mom, geom.valid)
-        t0 = ref["tri"]
-        unstable |= tri["status"] != t0["status"]
-        unstable |= np.linalg.norm(tri["means"] - t0["means"], axis=-1) > 0.5 * pos_tol
-        ang = rotation_angle_deg(tri["quats"], t0["quats"])
-        unstable |= ang > 0.5 * rot_tol
-        unstable |= np.abs(tri["scales"] / t0["scales"] - 1).max(-1) > 1e-3
-        unstable |= (sv["flags"] != ref["sv"]["flags"]).any(0)
-    return unstable
+    t0 = ref["tri"]
+    n = wl.scene.n
+    out = dict(flip=np.zeros(n, bool), dp=np.zeros(n), ang=np.zeros(n), sc=np.zeros(n), sig=np.zeros(n))
+    S0 = _sigma3d(t0["quats"], t0["scales"])
+    nS0 = np.linalg.norm(S0, axis=(1, 2))
+    for rel in SENS_REL:
+        for s in SENS_SEEDS:
+            rng = np.random.default_rng(s)
+            mom = comp["mom"] * (1.0 + rel * rng.standard_normal(comp["mom"].shape))
+            mom = mom + comp["slack"] * rng.uniform(-1.0, 1.0, comp["mom"].shape)
+            mom[..., 12:] = comp["mom"][..., 12:]
+            mom[..., 12] += np.round(comp["nmarg"] * rng.uniform(-1.0, 1.0, comp["nmarg"].shape))
+            sv = oracle.solve_views(mom, geom.mu, cov, geom.valid)
+            tri = oracle.triangulate(wl.scene, wl.cams, sv, mom, geom.valid)
+            out["flip"] |= tri["status"] != t0["status"]
+            out["flip"] |= (sv["flags"] != ref["sv"]["flags"]).any(0)
+            out["dp"] = np.maximum(out["dp"], np.linalg.norm(tri["means"] - t0["means"], axis=-1))
+            out["ang"] = np.maximum(out["ang"], rotation_angle_deg(tri["quats"], t0["quats"]))
+            out["sc"] = np.maximum(out["sc"], np.abs(tri["scales"] / t0["scales"] - 1).max(-1))
+            dS = np.linalg.norm(_sigma3d(tri["quats"], tri["scales"]) - S0, axis=(1, 2))
+            out["sig"] = np.maximum(out["sig"], dS / nS0)
+    return out
 
 
 def eigen_gap(eig):
@@ -117,49 +136,63 @@ def eigen_gap(eig):
     return np.minimum(e[..., 1] - e[..., 0], e[..., 2] - e[..., 1]) / np.maximum(e[..., 2], 1e-300)
 
 
-def check_end_to_end(case, wl, ref, gpu, max_unstable=0.05):
-    """End-to-end parity of one frame (status, positions, rotations,
-    scales, untouched copies) against the oracle; Gaussians whose oracle
-    result is not determined at FP32 input precision are excluded, at most
-    `max_unstable` of the updated ones (the fraction is logged)."""
+def _bounded(case, name, dev, tol, sens, k, max_widened, n_ref):
+    """dev <= tol + k * sens everywhere; at most max_widened of the n_ref
+    compared Gaussians may need more than tol (logged)."""
+    if dev.size == 0:
+        return
+    bound = tol + k * sens
+    worst = int(np.argmax(dev - bound))
+    assert np.all(dev <= bound), (name, float(dev[worst]), float(tol), float(sens[worst]))
+    widened = int((dev > tol).sum())
+    log(f"[{case}] {name}: {dev.size} compared, max {dev.max():.2e} (tolerance {tol:g}); "
+        f"{widened} beyond the tolerance, each within {k} x the oracle's own sensitivity")
+    assert widened <= max(2, max_widened * n_ref), (name, widened, n_ref)
+
+
+def check_end_to_end(case, wl, ref, gpu, k=3.0, max_widened=0.01, sens=None):
+    """End-to-end parity of one frame against the oracle, on every Gaussian:
+    statuses equal (a mismatch only where the oracle's own status flips under
+    FP32-sized perturbations of its accumulators), positions within 1e-3,
+    rotations within 0.05 degrees (relative eigen-gap >= 1e-2, else
+    Sigma_3D' within 1e-3 relative), scales within 1e-3 relative, each
+    widened by k times the oracle's sensitivity to those perturbations (a
+    result the FP32 accumulation cannot determine more closely), with at most
+    max_widened of the updated Gaussians needing the widening; parameters that
+    were not updated are copied bit-exactly."""
     tri = ref["tri"]
-    unstable = sensitivity_mask(wl, ref)
+    sens = sensitivity(wl, ref) if sens is None else sens
     st_g, st_o = gpu["status"], tri["status"]
-    mism = (st_g != st_o) & ~unstable
-    upd = (st_o & (oracle.ST_POS | oracle.ST_COV)) > 0
-    frac = float(unstable.sum()) / max(1, int((upd | unstable).sum()))
-    log(f"[{case}] status mismatches {mism.sum()} / {st_o.size}; unstable excluded {unstable.sum()} "
-        f"({100 * frac:.2f}% of the {int((upd | unstable).sum())} updated or unstable Gaussians)")
-    assert frac <= max_unstable, frac
-    assert mism.sum() <= max(2, 2e-3 * st_o.size)
-    pos = ((st_g & oracle.ST_POS) > 0) & ((st_o & oracle.ST_POS) > 0) & ~unstable
+    mism = st_g != st_o
+    unexplained = mism & ~sens["flip"]
+    log(f"[{case}] status mismatches {mism.sum()} / {st_o.size} ({unexplained.sum()} where the oracle's status "
+        f"is stable; {sens['flip'].sum()} statuses flip under perturbation)")
+    assert unexplained.sum() <= max(2, 2e-3 * st_o.size), unexplained.sum()
+    pos = ((st_g & oracle.ST_POS) > 0) & ((st_o & oracle.ST_POS) > 0)
     dpos = np.linalg.norm(gpu["means"][pos].astype(np.float64) - tri["means"][pos], axis=-1)
-    assert np.all(dpos <= 1e-3), dpos.max()
-    cov = ((st_g & oracle.ST_COV) > 0) & ((st_o & oracle.ST_COV) > 0) & ~unstable
+    _bounded(case, "positions", dpos, 1e-3, sens["dp"][pos], k, max_widened, pos.sum())
+    cov = ((st_g & oracle.ST_COV) > 0) & ((st_o & oracle.ST_COV) > 0)
     gap = eigen_gap(tri["eig"])
     rot = cov & (gap >= 1e-2)
     ang = rotation_angle_deg(gpu["quats"][rot].astype(np.float64), tri["quats"][rot])
-    assert np.all(ang <= 0.05), ang.max()
+    _bounded(case, "rotations (deg)", ang, 0.05, sens["ang"][rot], k, max_widened, cov.sum())
     assert np.all(gpu["quats"][rot][:, 0] >= 0)
     # degenerate eigen-gap: compare Sigma_3D' instead
     deg = cov & (gap < 1e-2)
     if deg.any():
-        Rg = oracle.quat_to_rot(gpu["quats"][deg].astype(np.float64))
-        Ro = oracle.quat_to_rot(tri["quats"][deg])
-        Sg = Rg @ (gpu["scales"][deg][:, :, None] ** 2 * np.swapaxes(Rg, -1, -2))
-        So = Ro @ (tri["scales"][deg][:, :, None] ** 2 * np.swapaxes(Ro, -1, -2))
+        Sg = _sigma3d(gpu["quats"][deg], gpu["scales"][deg])
+        So = _sigma3d(tri["quats"][deg], tri["scales"][deg])
         rel = np.linalg.norm(Sg - So, axis=(1, 2)) / np.linalg.norm(So, axis=(1, 2))
-        assert np.all(rel <= 1e-3), rel.max()
-    sc = np.abs(gpu["scales"][cov] / tri["scales"][cov] - 1)
-    assert np.all(sc <= 1e-3), sc.max()
+        _bounded(case, "Sigma_3D' (small eigen-gap)", rel, 1e-3, sens["sig"][deg], k, max_widened, cov.sum())
+    sc = np.abs(gpu["scales"][cov] / tri["scales"][cov] - 1).max(-1)
+    _bounded(case, "scales (relative)", sc, 1e-3, sens["sc"][cov], k, max_widened, cov.sum())
     # what was not updated is copied bit-exactly
     keep = (st_g & oracle.ST_POS) == 0
     np.testing.assert_array_equal(gpu["means"][keep], wl.scene.means[keep])
     keepc = (st_g & oracle.ST_COV) == 0
     np.testing.assert_array_equal(gpu["quats"][keepc], wl.scene.quats[keepc])
     np.testing.assert_array_equal(gpu["scales"][keepc], wl.scene.scales[keepc])
-    log(f"[{case}] e2e: pos {pos.sum()} max {dpos.max() if dpos.size else 0:.2e}; rot {rot.sum()} "
-        f"max {ang.max() if ang.size else 0:.2e} deg")
+    return sens
 
 
 # ------------------------------------------------------------ stage checks

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import synth
-from helpers import check_end_to_end, compare_accumulators, dump, eigen_gap, log, rotation_angle_deg, sensitivity_mask
+from helpers import check_end_to_end, compare_accumulators, dump, eigen_gap, log, rotation_angle_deg, sensitivity
 
 pytestmark = pytest.mark.gpu
 
@@ -113,17 +113,20 @@ def test_mix_equals_alone(runs):
         c = clips[ci]
         wl = SimpleNamespace(scene=c.scene, cams=c.cams)
         ref = oracle.motion_transfer(c.scene, c.cams, c.disp[f], c.vis[f])
-        unstable = sensitivity_mask(wl, ref)
-        # the end-to-end allowance for status flips between two FP32 runs
-        # (atomic order) on Gaussians the oracle's perturbation did not flag
-        diff = (a["status"] != m["status"]) & ~unstable
+        # two FP32 runs differ by the order of their atomic additions: the
+        # same allowance as against the oracle (the oracle's own sensitivity
+        # to FP32-sized perturbations of its accumulators)
+        sens = sensitivity(wl, ref)
+        diff = (a["status"] != m["status"]) & ~sens["flip"]
         assert diff.sum() <= max(2, 2e-3 * diff.size), diff.sum()
-        both = (a["status"] & oracle.ST_POS).astype(bool) & (m["status"] & oracle.ST_POS).astype(bool) & ~unstable
+        both = (a["status"] & oracle.ST_POS).astype(bool) & (m["status"] & oracle.ST_POS).astype(bool)
         dpos = np.linalg.norm(a["means"][both].astype(np.float64) - m["means"][both], axis=-1)
-        assert dpos.size == 0 or dpos.max() <= 1e-3, dpos.max()
-        cov = (a["status"] & oracle.ST_COV).astype(bool) & (m["status"] & oracle.ST_COV).astype(bool) & ~unstable
+        assert np.all(dpos <= 1e-3 + 6 * sens["dp"][both])
+        cov = (a["status"] & oracle.ST_COV).astype(bool) & (m["status"] & oracle.ST_COV).astype(bool)
         rot = cov & (eigen_gap(ref["tri"]["eig"]) >= 1e-2)
         ang = rotation_angle_deg(a["quats"][rot].astype(np.float64), m["quats"][rot].astype(np.float64))
-        assert ang.size == 0 or ang.max() <= 0.05, ang.max()
+        assert np.all(ang <= 0.05 + 6 * sens["ang"][rot])
+        wide = int((dpos > 1e-3).sum() + (ang > 0.05).sum())
+        assert wide <= max(2, 0.01 * max(1, both.sum())), wide
         log(f"clip {ci} frame {f}: status diff {diff.sum()}, max dpos {dpos.max() if dpos.size else 0:.2e}, "
-            f"max rot {ang.max() if ang.size else 0:.2e} deg")
+            f"max rot {ang.max() if ang.size else 0:.2e} deg, {wide} beyond the tolerance")
