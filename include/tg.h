@@ -209,6 +209,29 @@ tg_status tg_bin_sort(const tg_splats* s, int64_t N, const tg_camera* cams, int3
                       void* stream);
 
 /*
+ * tg_bin_sort_static -- tg_bin_sort for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that forbid
+ * hipMalloc): the same results, with the workspace taken from a scratch
+ * array that the library holds on each device it runs on (allocated when the
+ * library's code object is loaded, kept until the process ends).  The call
+ * allocates nothing and does no device synchronisation; the first call on a
+ * device looks the array's address up once (no allocation).
+ *
+ * Limit: the workspace tg_bin_sort would ask for (query it with ws == NULL)
+ * must be at most TG_BIN_SORT_STATIC_BYTES (64 MiB: about 2.4M (view,
+ * Gaussian) pairs with a pair capacity of 4M); larger requests return
+ * TG_ERR_WORKSPACE before anything runs.  Every call on a device shares that
+ * device's array, so calls whose executions overlap on one device (several
+ * streams or threads at once) race and must be serialised by the caller; a
+ * call's stream order alone makes consecutive calls on one stream safe.
+ * Other errors as tg_bin_sort, plus TG_ERR_DEVICE if the array's address
+ * cannot be found.
+ */
+#define TG_BIN_SORT_STATIC_BYTES (64u << 20)
+tg_status tg_bin_sort_static(const tg_splats* s, int64_t N, const tg_camera* cams, int32_t V,
+                             const tg_params* p, tg_bins* bins, void* stream);
+
+/*
  * tg_splat_accumulate -- PWI-LS statistics (Sec. 4.3.3, 4.3.4 Eq. 4,
  * Sec. 4.3.5; static-pixel counters of Sec. 4.5.2).
  *

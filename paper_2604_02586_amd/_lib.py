@@ -18,6 +18,7 @@ TG_ACC_STRIDE = 16
 TG_REC_STRIDE = 8
 TG_MAX_SLOTS = 8
 TG_MAX_FRAMES = 4
+TG_BIN_SORT_STATIC_BYTES = 64 << 20
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "misaligned buffer", 3: "workspace too small",
           4: "capacity overflow", 5: "HIP runtime error", 6: "request exceeds the memory budget",
@@ -87,6 +88,7 @@ def lib():
         "tg_num_tiles": ([P, c_i32], c_i64),
         "tg_preprocess": ([P, c_i64, P, c_i32, P, P, P], st),
         "tg_bin_sort": ([P, c_i64, P, c_i32, P, P, P, P, P], st),
+        "tg_bin_sort_static": ([P, c_i64, P, c_i32, P, P, P], st),
         "tg_splat_accumulate": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P, P], st),
         "tg_splat_accumulate_batch": ([P, c_i32, P, P, P], st),
         "tg_regularize": ([P, P, P, P, c_i64, c_i32, P, P, P, P, P, P], st),
@@ -111,7 +113,7 @@ def lib():
 
 def exported_symbols():
     return [n for n in ("tg_abi_version", "tg_status_string", "tg_default_params", "tg_num_cells",
-                        "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_splat_accumulate",
+                        "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_bin_sort_static", "tg_splat_accumulate",
                         "tg_splat_accumulate_batch", "tg_regularize", "tg_solve_views", "tg_triangulate", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
                         "tg_project_bwd", "tg_l1_loss_grad", "tg_ssim_loss_grad", "tg_adam_step",
                         "tg_adam_step_rows")]

@@ -16,7 +16,7 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-__all__ = ["GaussianTensors", "SplatTensors", "BinTensors", "MotionTransfer", "preprocess", "bin_sort",
+__all__ = ["GaussianTensors", "SplatTensors", "BinTensors", "MotionTransfer", "preprocess", "bin_sort", "bin_sort_static",
            "splat_accumulate", "splat_accumulate_batch", "regularize", "solve_views", "triangulate", "bin_expand", "stream_ptr", "default_params"]
 
 default_params = _lib.default_params
@@ -139,6 +139,15 @@ def bin_sort(s: SplatTensors, n, cams, params, bins: BinTensors, ws: torch.Tenso
     nb = ctypes.c_size_t(ws.numel() * ws.element_size())
     check("tg_bin_sort", lib().tg_bin_sort(ctypes.byref(sc), n, cams, len(cams), ctypes.byref(params),
                                            ctypes.byref(bc), _ptr(ws), ctypes.byref(nb), stream_ptr(stream)))
+
+
+def bin_sort_static(s: SplatTensors, n, cams, params, bins: BinTensors, stream=None):
+    """tg_bin_sort_static: the binning with the library's own scratch (no
+    workspace argument, nothing allocated)."""
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    sc, bc = s.c(), bins.c()
+    check("tg_bin_sort_static", lib().tg_bin_sort_static(ctypes.byref(sc), n, cams, len(cams), ctypes.byref(params),
+                                                         ctypes.byref(bc), stream_ptr(stream)))
 
 
 def splat_accumulate(s: SplatTensors, bins: BinTensors, n, cams, disp, vis, params, acc, t_final=None,

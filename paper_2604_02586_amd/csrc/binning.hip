@@ -16,6 +16,7 @@
 //
 // The radix sort (sort.hip) is LSD with 8-bit digits and stable ranks.
 #include <algorithm>
+#include <mutex>
 
 #include "tg_internal.h"
 
@@ -623,4 +624,46 @@ extern "C" tg_status tg_bin_expand(const tg_splats* sp, const tg_bins* bins, int
                        tile_ids, capacity, 1);
     TG_CHECK_LAUNCH();
     return TG_OK;
+}
+
+// ---- tg_bin_sort_static: the same binning with a library-owned scratch -------
+// For callers that cannot allocate device memory.  The workspace is a
+// file-scope device array; each device holds its own copy at its own address,
+// which is looked up once per device (hipGetSymbolAddress with that device
+// current) and used from then on: the array's name is a host-side stand-in
+// and must never reach a kernel.  tg_bin_sort writes every workspace word it
+// reads within the call, so nothing carries over between calls.
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[TG_BIN_SORT_STATIC_BYTES];
+std::mutex g_static_mu;
+void* g_static_ptr[STATIC_MAX_DEVICES];
+
+tg_status static_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return TG_ERR_DEVICE;
+    if (dev >= STATIC_MAX_DEVICES) return TG_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TG_ERR_DEVICE;
+        g_static_ptr[dev] = ptr;
+    }
+    *out = g_static_ptr[dev];
+    return TG_OK;
+}
+}  // namespace
+
+extern "C" tg_status tg_bin_sort_static(const tg_splats* sp, int64_t N, const tg_camera* cams, int32_t V,
+                                        const tg_params* p, tg_bins* bins, void* stream)
+{
+    size_t need = 0;
+    tg_status st = tg_bin_sort(sp, N, cams, V, p, bins, nullptr, &need, stream);
+    if (st != TG_OK) return st;
+    if (need > (size_t)TG_BIN_SORT_STATIC_BYTES) return TG_ERR_WORKSPACE;
+    void* ws = nullptr;
+    st = static_scratch(&ws);
+    if (st != TG_OK) return st;
+    size_t have = (size_t)TG_BIN_SORT_STATIC_BYTES;
+    return tg_bin_sort(sp, N, cams, V, p, bins, ws, &have, stream);
 }

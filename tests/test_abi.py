@@ -166,6 +166,15 @@ def test_workspace_query_and_cell_counts(L):
     small = ctypes.c_size_t(16)
     assert L.tg_bin_sort(ctypes.byref(s), 100000, cams, 4, ctypes.byref(p), ctypes.byref(b), ctypes.c_void_p(0x10000),
                          ctypes.byref(small), None) == 3
+    # the allocation-free variant rejects a workspace beyond its scratch on
+    # the host, before touching the device
+    big = _lib.Bins()
+    big.capacity = 1 << 24
+    nbig = ctypes.c_size_t(0)
+    assert L.tg_bin_sort(ctypes.byref(s), 100000, cams, 4, ctypes.byref(p), ctypes.byref(big), None,
+                         ctypes.byref(nbig), None) == 0
+    assert nbig.value > _lib.TG_BIN_SORT_STATIC_BYTES
+    assert L.tg_bin_sort_static(ctypes.byref(s), 100000, cams, 4, ctypes.byref(p), ctypes.byref(big), None) == 3
 
 
 def test_product_path_has_no_cpu_fallback():
