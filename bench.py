@@ -42,6 +42,10 @@ HBM_PEAK = 8.0e12
 # counters, count (5 more products) -- see the design notes
 OPS_PER_EVAL = 16
 OPS_PER_CONTRIB = 24
+# the survey's single figure: 40 lane-ops per contributing pair (16 for the
+# alpha evaluation, 24 for the weight, transmittance and moments), nothing for
+# pairs that are evaluated and do not contribute
+OPS_PER_CONTRIB_SURVEY = 40
 
 
 def log(msg):
@@ -68,39 +72,66 @@ def measured_traffic():
     return float(m_b.group(1))
 
 
-def cpu_baseline(wl, sample_views=8):
-    """The oracle on a bounded sample: `sample_views` of the views, all
-    pixels, all Gaussians, through solve and triangulation; extrapolated
-    linearly in the number of views."""
-    import numpy as np
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(wl, single_core_views=1):
+    """The oracle (unchanged: C compositing parallel over bands of tile rows,
+    numpy solves) on the machine's host cores: the whole frame (every view, pixel
+    and Gaussian, through solve and triangulation) with all the threads the
+    OpenMP runtime gives it, then `single_core_views` views on one thread
+    (compositing only scales with the views; the time is extrapolated
+    linearly in them)."""
     import oracle
     import synth
     V = len(wl.cams)
-    cams = wl.cams[:sample_views]
-    sub = synth.Workload(name=wl.name, scene=wl.scene, cams=cams, motion=wl.motion,
-                         disp=wl.disp[:sample_views], vis=wl.vis[:sample_views])
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    r = oracle.motion_transfer(sub.scene, sub.cams, sub.disp, sub.vis)
-    t = time.perf_counter() - t0
-    t_frame = t * V / sample_views
     n = wl.scene.n
-    return dict(value=n / t_frame, unit="Gaussians/s", cores=min(sample_views, threads), kind="oracle",
-                sample=f"{sample_views} of {V} views at full resolution with all {n} Gaussians "
-                       f"(geometry, depth-ordered tile lists, FP64 compositing, per-view solve, "
-                       f"triangulation) in {t:.1f} s, extrapolated x{V / sample_views:g} to the full frame; "
-                       f"compositing parallel over views", seconds=t)
+    threads = oracle.threads()
+    t0 = time.perf_counter()
+    oracle.motion_transfer(wl.scene, wl.cams, wl.disp, wl.vis)
+    t_all = time.perf_counter() - t0
+    k = single_core_views
+    sub = synth.Workload(name=wl.name, scene=wl.scene, cams=wl.cams[:k], motion=wl.motion,
+                         disp=wl.disp[:k], vis=wl.vis[:k])
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.motion_transfer(sub.scene, sub.cams, sub.disp, sub.vis)
+        t_one = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return dict(value=n / t_all, unit="Gaussians/s", cores=threads, kind="oracle",
+                sample=f"the whole frame ({n} Gaussians x {V} views at full resolution: geometry, depth-ordered "
+                       f"tile lists, FP64 compositing, per-view solve, triangulation) in {t_all:.1f} s on "
+                       f"{threads} threads; single thread: {k} of {V} views in {t_one:.1f} s, x{V / k:g} "
+                       f"= {t_one * V / k:.0f} s per frame",
+                seconds=t_all, single_core_value=n / (t_one * V / k), single_core_seconds_per_frame=t_one * V / k,
+                nproc=os.cpu_count(), affinity_cpus=affinity, cpu_model=_cpu_model())
 
 
-def serving_bench(dev, n_frames=24, clients=4, rates=(2.0, 20.0), seed=12, n_templates=6, budget_gb=96.0):
-    """Serving form: clips drawn like the serving workload (Gaussians
-    log-uniform in [50k, 1M], views uniform in 8..27, resolution from
-    640x480 / 1352x1014 / 1920x1080, 1, 2 or 4 target frames per clip, tracks
-    of the medium workload's kind) from `clients` clients whose frame
-    requests form a Poisson stream at each rate, and with every request
-    waiting at t = 0 (saturation).  The server (continuous batching, HBM
-    budget, resident clips) runs against one-frame-at-a-time cold frames."""
+def serving_bench(dev, n_frames=200, clients=4, rates=(5.0, 20.0), seed=12, n_templates=6, budget_gb=96.0):
+    """Serving form at the serving workload's shape: clips drawn with
+    Gaussians log-uniform in [50k, 1M], views uniform in 8..27, resolution
+    from 640x480 / 1352x1014 / 1920x1080 and 1, 2, 4 or 8 target frames
+    (tracks of the medium workload's kind: smooth 8-body field, 1 px noise,
+    scaled per frame); `clients` clients send their clips' frames back to
+    back as Poisson streams totalling each rate, and once with every request
+    waiting at t = 0 (saturation).  `n_frames` frames per run.  The server
+    (libtg's tg_serve_*: continuous batching under an HBM budget, resident
+    clips, one batched accumulate and one fused update per step) runs against
+    one cold frame at a time (projection, binning, accumulation, fused update
+    for every frame, tracks uploaded from the same pinned host memory)."""
     import numpy as np
     import torch
 
@@ -116,84 +147,83 @@ def serving_bench(dev, n_frames=24, clients=4, rates=(2.0, 20.0), seed=12, n_tem
         n = int(round(math.exp(rng.uniform(math.log(50_000), math.log(1_000_000)))))
         V = int(rng.integers(8, 28))
         W, H = res[int(rng.integers(0, 3))]
-        F = int(rng.choice([1, 2, 4]))
         wl = synth.make_workload("medium", seed=100 + k, n=n, views=V, width=W, height=H)
-        frames = []
-        for f in range(1, F + 1):
-            d = torch.from_numpy((wl.disp * np.float32(f / F)).astype(np.float32)).pin_memory()
-            frames.append((d, torch.from_numpy(wl.vis).pin_memory()))
+        # two track fields per template (half and all of the motion); frame
+        # f of a clip uses field f mod 2
+        frames = [(torch.from_numpy((wl.disp * np.float32((f + 1) / 2)).astype(np.float32)).pin_memory(),
+                   torch.from_numpy(wl.vis).pin_memory()) for f in range(2)]
         g = api.GaussianTensors.from_scene(wl.scene, dev)
-        templates.append(dict(n=n, V=V, W=W, H=H, F=F, cams=wl.cams, g=g, frames=frames,
+        templates.append(dict(n=n, V=V, W=W, H=H, cams=wl.cams, g=g, frames=frames,
                               mt=api.MotionTransfer(wl.cams, n, dev)))
-        log(f"  serving template {k}: {n} G x {V} views x {W}x{H}, {F} frames")
+        del wl
+        log(f"  serving template {k}: {n} G x {V} views x {W}x{H}")
     log(f"  templates in {time.perf_counter() - t0:.1f} s")
 
-    def schedule(rate):
-        """[(arrival, client, clip_no, template, frame)] in arrival order."""
-        reqs, per = [], n_frames // clients
-        order = list(rng.permutation(n_templates))
-        ti = 0
+    def schedule(rate, count):
+        """[(arrival, client, clip_no, template, F, frame)] in arrival order."""
+        reqs = []
+        per = [count // clients + (1 if c < count % clients else 0) for c in range(clients)]
         for c in range(clients):
             t, made, clip = 0.0, 0, 0
-            while made < per:
-                tpl = int(order[ti % n_templates])
-                ti += 1
-                for f in range(templates[tpl]["F"]):
-                    if made == per:
-                        break
+            while made < per[c]:
+                tpl = int(rng.integers(0, n_templates))
+                F = int(rng.choice([1, 2, 4, 8]))
+                F = min(F, per[c] - made)
+                for f in range(F):
                     if rate:
                         t += rng.exponential(clients / rate)
-                    reqs.append((t, c, clip, tpl, f))
-                    made += 1
+                    reqs.append((t, c, clip, tpl, F, f))
+                made += F
                 clip += 1
-        reqs.sort(key=lambda r: (r[0], r[1], r[4]))
+        reqs.sort(key=lambda r: (r[0], r[1], r[5]))
         return reqs
-
-    def clip_sizes(reqs):
-        cnt = {}
-        for _, c, clip, tpl, f in reqs:
-            cnt[c, clip] = cnt.get((c, clip), 0) + 1
-        return cnt
 
     def run_server(reqs):
         srv = Server(budget_bytes=int(budget_gb * 2**30))
-        sizes = clip_sizes(reqs)
-        cids, frames, i = {}, [], 0
-        while i < len(reqs) or not srv.sched.idle() or srv.inflight:
-            now = srv.now()
+        sids, frames, i = {}, [], 0
+        t_start = srv.now()
+        while i < len(reqs) or srv.frames:
+            now = srv.now() - t_start
             while i < len(reqs) and reqs[i][0] <= now:
-                t, c, clip, tpl, f = reqs[i]
+                t, c, clip, tpl, F, f = reqs[i]
                 T = templates[tpl]
-                if (c, clip) not in cids:
-                    cids[c, clip] = len(cids)
-                    srv.open_clip(cids[c, clip], T["g"], T["cams"], sizes[c, clip], now=t)
-                d, v = T["frames"][f]
-                frames.append(srv.submit(cids[c, clip], f + 1, d, v, now=t))
+                if (c, clip) not in sids:
+                    sids[c, clip] = srv.open_clip(T["g"], T["cams"], arrival=t_start + t)
+                d, v = T["frames"][f % 2]
+                frames.append(srv.submit(sids[c, clip], f, d, v, arrival=t_start + t))
+                if f == F - 1:
+                    srv.close(sids[c, clip])
                 i += 1
             srv.poll()
-            if i < len(reqs) and not srv.inflight:
-                time.sleep(max(0.0, min(0.001, reqs[i][0] - srv.now())))
-            elif srv.inflight:
+            if i < len(reqs) and not srv.frames:
+                time.sleep(max(0.0, min(0.001, reqs[i][0] - (srv.now() - t_start))))
+            else:
                 time.sleep(0.0001)
+        srv.step()
+        st = srv.stats()
         lat = np.array([f.done - f.arrival for f in frames])
         span = max(f.done for f in frames) - min(f.arrival for f in frames)
-        return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                    frames_per_s=len(frames) / span, frames=len(frames), steps=srv.steps,
-                    mean_frames_per_step=float(np.mean(srv.frames_per_step)), max_admitted=srv.max_admitted)
+        out = dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                   frames_per_s=len(frames) / span, frames=len(frames), steps=st["steps"],
+                   mean_frames_per_step=st["frames"] / max(1, st["steps"]),
+                   mean_entries_per_step=st["entries"] / max(1, st["steps"]), max_admitted=st["max_admitted"],
+                   arena_peak_gb=st["arena_peak"] / 2**30, rebins=st["rebins"])
+        srv.destroy()
+        return out
 
     def run_sequential(reqs):
         stream = torch.cuda.current_stream()
         t0 = time.perf_counter()
         lat, done = [], []
-        for t, c, clip, tpl, f in reqs:
+        for t, c, clip, tpl, F, f in reqs:
             while time.perf_counter() - t0 < t:
                 time.sleep(0.0002)
             T = templates[tpl]
             mt = T["mt"]
-            d, v = T["frames"][f]
+            d, v = T["frames"][f % 2]
             dd = d.to(dev, non_blocking=True)
             vv = v.to(dev, non_blocking=True)
-            out = mt.run(T["g"], dd, vv)
+            out = mt.run(T["g"], dd, vv, fused=True)
             stream.synchronize()
             tn = time.perf_counter() - t0
             lat.append(tn - t)
@@ -204,23 +234,24 @@ def serving_bench(dev, n_frames=24, clients=4, rates=(2.0, 20.0), seed=12, n_tem
                     frames_per_s=len(reqs) / (max(done) - min(r[0] for r in reqs)), frames=len(reqs))
 
     # warm both paths once (library load, allocator, first launches)
-    warm = schedule(0)[:4]
+    warm = schedule(0, 8)
     run_server(warm)
     run_sequential(warm)
     torch.cuda.synchronize()
     out = {"clients": clients, "frames_per_run": n_frames, "budget_gb": budget_gb,
-           "templates": [dict(gaussians=T["n"], views=T["V"], width=T["W"], height=T["H"], frames=T["F"])
-                         for T in templates]}
+           "clip_frames": [1, 2, 4, 8],
+           "templates": [dict(gaussians=T["n"], views=T["V"], width=T["W"], height=T["H"]) for T in templates]}
     for rate in list(rates) + [0]:
-        reqs = schedule(rate)
+        reqs = schedule(rate, n_frames)
         key = f"{rate:g}_fps" if rate else "saturation"
         log(f"  serving at {key}: {len(reqs)} frames")
         srv = run_server(reqs)
         seq = run_sequential(reqs)
         out[key] = {"server": srv, "one_frame_at_a_time": seq,
                     "frames_per_s_ratio": srv["frames_per_s"] / seq["frames_per_s"]}
-        log(f"    server {srv['frames_per_s']:.1f} frames/s p50 {srv['p50_ms']:.1f} p99 {srv['p99_ms']:.1f} ms; "
-            f"one-at-a-time {seq['frames_per_s']:.1f} frames/s p50 {seq['p50_ms']:.1f} p99 {seq['p99_ms']:.1f} ms")
+        log(f"    server {srv['frames_per_s']:.1f} frames/s p50 {srv['p50_ms']:.1f} p99 {srv['p99_ms']:.1f} ms "
+            f"({srv['mean_frames_per_step']:.2f} frames/step); one-at-a-time {seq['frames_per_s']:.1f} frames/s "
+            f"p50 {seq['p50_ms']:.1f} p99 {seq['p99_ms']:.1f} ms")
     return out
 
 
@@ -299,7 +330,7 @@ def main():
                     help="independent frames in flight on separate streams for the throughput (value)")
     ap.add_argument("--no-warm", action="store_true", help="skip timing warm frames (resident splats and bins)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-form measurement")
-    ap.add_argument("--serving-frames", type=int, default=24)
+    ap.add_argument("--serving-frames", type=int, default=200)
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement measurement")
     ap.add_argument("--only", choices=["serving", "refine"],
                     help="run one secondary measurement alone (for profiling); prints its own JSON line")
@@ -449,6 +480,47 @@ def main():
             f"propagated {int(((rs & 4) > 0).sum())}, static {int((rs == 1).sum())}")
         del reg_ws
 
+    # one serving step's worth of work at the benchmark's shape: eight target
+    # frames of one clip (two entries of four frames sharing alpha and T) in
+    # one batched accumulate and one fused update launch
+    clip_pass = None
+    if not args.no_warm:
+        F8 = 8
+        disps = [(disp * float((f + 1) / F8)).contiguous() for f in range(F8)]
+        accs = [torch.empty_like(mt.acc) for _ in range(F8)]
+        outs8 = [api.GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.quats),
+                                     torch.empty_like(g.scales), g.opacity) for _ in range(F8)]
+        sts8 = [torch.empty(N, dtype=torch.int32, device=dev) for _ in range(F8)]
+        cams_dev = api.cameras_device(mt.cams_host, dev)
+
+        def clip_step():
+            for a in accs:
+                a.zero_()
+            api.splat_accumulate_batch(
+                [dict(splats=mt.splats, bins=mt.bins, n=N, cams=mt.cams_host, disp=disps[i:i + 4], vis=[vis] * 4,
+                      acc=accs[i:i + 4]) for i in (0, 4)], mt.params)
+            api.solve_triangulate_batch(
+                [dict(splats=mt.splats, g_in=g, cams=cams_dev, n=N, V=V, acc=accs[i:i + 4], g_out=outs8[i:i + 4],
+                      status=sts8[i:i + 4]) for i in (0, 4)], mt.params)
+
+        for _ in range(2):
+            clip_step()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(3, args.steps // 4)
+        e0.record(stream)
+        for _ in range(reps):
+            clip_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cp_ms = e0.elapsed_time(e1) / reps
+        clip_pass = {"frames": F8, "ms_per_pass": cp_ms, "ms_per_frame": cp_ms / F8,
+                     "gaussians_per_s": N * F8 / (cp_ms * 1e-3),
+                     "frames_per_s_ratio_vs_cold_frames": ms_single / (cp_ms / F8),
+                     "what": "8 target frames of one clip: zeroing, one tg_splat_accumulate_batch (2 entries of 4 "
+                             "frames sharing alpha and T), one tg_solve_triangulate_batch; resident splats and bins"}
+        log(f"clip pass (8 frames): {cp_ms:.3f} ms, {cp_ms / F8:.3f} ms per frame")
+        del disps, accs, outs8, sts8
+
     warm = None
     if not args.no_warm:
         for _ in range(args.warmup):
@@ -460,8 +532,9 @@ def main():
         torch.cuda.synchronize()
         warm = (time.perf_counter() - tw) * 1e3 / args.steps
 
-    alg_ops = OPS_PER_EVAL * e_eval + OPS_PER_CONTRIB * e_contrib
+    alg_ops = OPS_PER_CONTRIB_SURVEY * e_contrib
     achieved = alg_ops / (acc_ms * 1e-3)
+    own_ops = OPS_PER_EVAL * e_eval + OPS_PER_CONTRIB * e_contrib
     # algorithmic bytes per frame: parameters in and out, tracks, accumulators
     # written once and read once (13 used slots)
     b_alg = N * 44 * 2 + V * W * H * 9 + 2 * N * V * 52
@@ -493,10 +566,18 @@ def main():
         "roofline": {"kernel": "tg_splat_accumulate", "bound": "alu", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK / 1e12, "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK,
                      "traffic": measured_traffic(), "traffic_unit": "B per launch",
-                     "algorithmic_ops": alg_ops, "avg_ms": acc_ms},
+                     "algorithmic_ops": alg_ops,
+                     "ops_rule": f"{OPS_PER_CONTRIB_SURVEY} lane-ops per contributing (pixel, Gaussian) pair",
+                     "avg_ms": acc_ms,
+                     "frac_evaluated_rule": own_ops / (acc_ms * 1e-3) / VALU_PEAK,
+                     "evaluated_rule": f"{OPS_PER_EVAL} per evaluated + {OPS_PER_CONTRIB} per contributing pair",
+                     "alg_bytes_per_launch": V * W * H * 9 + N * V * 52 + V * N * 32,
+                     "hbm_frac_alg_bytes": (V * W * H * 9 + N * V * 52 + V * N * 32) / (acc_ms * 1e-3) / HBM_PEAK},
     }
     if warm is not None:
         out["warm_ms_per_frame"] = warm
+    if clip_pass is not None:
+        out["clip_pass_8_frames"] = clip_pass
     if reg_ms is not None:
         out["regularisation_ms"] = reg_ms
     if not args.no_serving:

@@ -355,6 +355,166 @@ tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_new, const ui
                          tg_gaussians* g_out, uint32_t* status, void* stream);
 
 /*
+ * tg_solve_triangulate -- tg_solve_views followed by tg_triangulate in one
+ * launch (Sec. 4.3.4 Eq. 4, Sec. 4.2 Eq. 2, Sec. 4.4, thresholds of
+ * Sec. 5.2): each Gaussian's per-view solves are computed from its
+ * accumulator records where the update needs them, with the same FP64
+ * arithmetic and the same FP32 rounding of mu' and Sigma' as the two calls,
+ * and nothing is stored in between (no mu2d_new, cov2d_new, vflags, wn).
+ * Outputs, statuses and errors as tg_triangulate; acc and s as for
+ * tg_solve_views.  cams: host [V], V <= TG_MAX_VIEWS.
+ */
+tg_status tg_solve_triangulate(const float* acc, const tg_splats* s, const tg_gaussians* g_in, int64_t N,
+                               const tg_camera* cams, int32_t V, const tg_params* p, tg_gaussians* g_out,
+                               uint32_t* status, void* stream);
+
+/*
+ * tg_solve_triangulate_batch -- the fused update of tg_solve_triangulate for
+ * several Gaussian sets and several frames per set in one launch (the
+ * per-step update of a serving loop whose accumulation ran as one
+ * tg_splat_accumulate_batch).  Per slot: s (the set's splats), g_in (its
+ * Gaussians, shared by its frames), cams: DEVICE [V] cameras (4-byte
+ * aligned; the launch reads them, so they must stay valid until it has
+ * run), N, V, F in 1..TG_MAX_FRAMES; per frame f < F: acc[f] device
+ * [V,N,16], g_out[f] (host struct of device pointers) and status[f] (device
+ * [N] or NULL).  n_slots <= TG_MAX_SLOTS.  Every argument is checked before
+ * anything is launched.
+ */
+typedef struct tg_upd_slot {
+    const tg_splats* s;
+    const tg_gaussians* g_in;
+    const tg_camera* cams;
+    int64_t N;
+    int32_t V;
+    int32_t F;
+    const float* acc[TG_MAX_FRAMES];
+    tg_gaussians* g_out[TG_MAX_FRAMES];
+    uint32_t* status[TG_MAX_FRAMES];
+} tg_upd_slot;
+
+tg_status tg_solve_triangulate_batch(const tg_upd_slot* slots, int32_t n_slots, const tg_params* p, void* stream);
+
+/*
+ * tg_serve_* -- continuous-batching motion-transfer server on one GPU (the
+ * one-GPU share of the frame-parallel pipeline, Sec. 4.7; clips of a first
+ * frame and several target frames, Sec. 5.1).
+ *
+ * Every target frame of a clip (a "stream" here) is transferred from the
+ * clip's first frame, so a stream's Gaussians are projected and binned once
+ * when it is admitted and stay resident while its frames arrive.  Each
+ * tg_serve_step retires finished work, admits waiting streams (first in,
+ * first out, no overtaking) whose resident set plus one frame's working set
+ * fit in the arena, uploads the tracks of admitted streams' frames as
+ * working sets fit (copy stream), and launches steps: a step takes the
+ * streams whose oldest ready frame is oldest, up to max_frames of their ready
+ * frames (in entries of at most TG_MAX_FRAMES), up to TG_MAX_SLOTS entries,
+ * and runs one tg_splat_accumulate_batch (alpha and T evaluated once per
+ * entry for its frames) and one tg_solve_triangulate_batch.  Up to
+ * max_inflight steps are in flight.  An admitted stream keeps one frame's
+ * working set reserved for its lifetime, so it can always progress.
+ *
+ * Memory: the caller owns everything.  `arena` (device, arena_bytes, the
+ * HBM budget) holds every buffer the server needs (splats, bins, binning
+ * workspace while binning, device cameras, per-frame accumulators and track
+ * copies), sub-allocated on the host; `host_scratch` (pinned host memory,
+ * at least TG_SERVE_HOST_BYTES) receives the pair counts of each binning.
+ * Gaussians (tg_serve_open_stream), tracks and outputs (tg_serve_submit)
+ * stay the caller's and must stay valid until the frame is reported done
+ * (the Gaussians until the stream's last frame is done).  Host tracks must
+ * be pinned (their upload is asynchronous).
+ *
+ * Times are seconds on the server's clock (tg_serve_now: host time since
+ * creation, aligned with the GPU clock by an event at creation); a frame's
+ * done time is when the GPU finished its step (an event), so latency =
+ * done - arrival.  The server is not thread-safe: one host thread drives it.
+ *
+ * Dry mode (arena == NULL, dry = 1): the same policy with no device at all
+ * (the arena is an address range that is never touched, uploads complete at
+ * once and steps when tg_serve_dry_complete says so), for testing the
+ * policy without a GPU.
+ */
+#define TG_SERVE_HOST_BYTES 4096
+typedef struct tg_server tg_server;
+
+typedef struct tg_serve_config {
+    void* arena;            /* device memory to sub-allocate (NULL in dry mode)   */
+    size_t arena_bytes;     /* its size: the HBM budget                           */
+    void* host_scratch;     /* pinned host memory, >= TG_SERVE_HOST_BYTES         */
+    void* compute_stream;   /* hipStream_t for every kernel                       */
+    void* copy_stream;      /* hipStream_t for track uploads (may equal compute)  */
+    int32_t max_inflight;   /* steps in flight, >= 1                              */
+    int32_t max_frames;     /* frames of one stream per step, 1..2*TG_MAX_FRAMES  */
+    int32_t max_slots;      /* entries per step, 1..TG_MAX_SLOTS                  */
+    int32_t dry;            /* 1: dry mode (no device)                            */
+} tg_serve_config;
+
+typedef struct tg_serve_done {
+    int64_t stream_id;
+    int64_t frame_id;
+    int64_t step;           /* the step that ran it (0, 1, ...; -1 if none)   */
+    double arrival;
+    double done;
+    int32_t status;         /* TG_OK, or the error that ended the frame        */
+    int32_t entry;          /* its entry within the step                       */
+} tg_serve_done;
+
+typedef struct tg_serve_stats {
+    int64_t steps;              /* steps launched                                */
+    int64_t entries;            /* stream entries over all steps                 */
+    int64_t frames;             /* frames over all steps                         */
+    int64_t rebins;             /* bindings repeated after a pair overflow       */
+    int64_t max_admitted;       /* most streams admitted at once                 */
+    int64_t arena_used;         /* bytes allocated now                           */
+    int64_t arena_peak;         /* most bytes allocated at once                  */
+    int64_t waiting_streams;    /* opened, not yet admitted                      */
+    int64_t admitted_streams;   /* admitted, not yet finished                    */
+    int64_t inflight_steps;
+} tg_serve_stats;
+
+/* Creates a server.  Errors: TG_ERR_INVALID_ARG for out-of-range config
+ * values or a missing arena / host_scratch outside dry mode. */
+tg_status tg_serve_create(const tg_serve_config* cfg, const tg_params* p, tg_server** out);
+/* Waits for the work in flight, then frees the host state (the caller's
+ * buffers stay the caller's). */
+tg_status tg_serve_destroy(tg_server* srv);
+/* Host seconds since creation (the clock of arrival and done times). */
+double tg_serve_now(const tg_server* srv);
+/* Opens a stream (a clip's first-frame Gaussians, N, cams host [V] with one
+ * resolution, V <= TG_MAX_VIEWS; g device, linear or log scales) that
+ * arrived at `arrival`; *stream_id receives its id.  TG_ERR_BUDGET when its
+ * resident set plus one frame's working set exceeds the whole arena. */
+tg_status tg_serve_open_stream(tg_server* srv, const tg_gaussians* g, int64_t N, const tg_camera* cams, int32_t V,
+                               double arrival, int64_t* stream_id);
+/* Submits target frame `frame_id` of a stream: disp [V,H,W,2] and vis
+ * [V,H,W] uint8 (or NULL: all visible), on the host (host_tracks = 1,
+ * pinned) or the device; the update goes to g_out (means, quats, scales;
+ * the opacity is the stream's) and status [N] (device, or NULL).  Errors:
+ * TG_ERR_INVALID_ARG for an unknown or closed stream. */
+tg_status tg_serve_submit(tg_server* srv, int64_t stream_id, int64_t frame_id, const float* disp,
+                          const uint8_t* vis, int32_t host_tracks, tg_gaussians* g_out, uint32_t* status,
+                          double arrival);
+/* No more frames for this stream: its resident set is released once its
+ * submitted frames are done. */
+tg_status tg_serve_close_stream(tg_server* srv, int64_t stream_id);
+/* Retire, admit, upload, launch; never waits for the device.  *launched
+ * (nullable) receives the number of steps launched. */
+tg_status tg_serve_step(tg_server* srv, int32_t* launched);
+/* Moves up to max finished frames into out (oldest first); *n receives the
+ * count. */
+tg_status tg_serve_poll(tg_server* srv, tg_serve_done* out, int32_t max, int32_t* n);
+tg_status tg_serve_get_stats(const tg_server* srv, tg_serve_stats* st);
+/* Dry mode only: completes the oldest n steps in flight at time `now`
+ * (uploads complete at once in dry mode). */
+tg_status tg_serve_dry_complete(tg_server* srv, int32_t n, double now);
+/* Host-only sizing of a stream as the server allocates it: the resident set
+ * (with the binning workspace and the first pair-list guess), and one
+ * frame's working set with host tracks (track copies included) or with
+ * device tracks.  Admission needs resident + frame_host bytes of the arena.
+ * Any output may be NULL. */
+tg_status tg_serve_stream_bytes(const tg_camera* cams, int32_t V, int64_t N, const tg_params* p,
+                                int64_t* resident, int64_t* frame_host, int64_t* frame_device);
+
+/*
  * tg_regularize -- motion regularisation after the multi-view update
  * (Sec. 4.5; K = 8 neighbours, Sec. 5.2).
  *

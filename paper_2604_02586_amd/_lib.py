@@ -66,6 +66,30 @@ class AccSlot(ctypes.Structure):
                 ("t_final", c_vp)]
 
 
+class UpdSlot(ctypes.Structure):
+    _fields_ = [("s", c_vp), ("g_in", c_vp), ("cams", c_vp), ("N", c_i64), ("V", c_i32), ("F", c_i32),
+                ("acc", c_vp * TG_MAX_FRAMES), ("g_out", c_vp * TG_MAX_FRAMES), ("status", c_vp * TG_MAX_FRAMES)]
+
+
+TG_SERVE_HOST_BYTES = 4096
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("arena", c_vp), ("arena_bytes", ctypes.c_size_t), ("host_scratch", c_vp),
+                ("compute_stream", c_vp), ("copy_stream", c_vp), ("max_inflight", c_i32), ("max_frames", c_i32),
+                ("max_slots", c_i32), ("dry", c_i32)]
+
+
+class ServeDone(ctypes.Structure):
+    _fields_ = [("stream_id", c_i64), ("frame_id", c_i64), ("step", c_i64), ("arrival", c_d), ("done", c_d),
+                ("status", c_i32), ("entry", c_i32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(k, c_i64) for k in ("steps", "entries", "frames", "rebins", "max_admitted", "arena_used",
+                                       "arena_peak", "waiting_streams", "admitted_streams", "inflight_steps")]
+
+
 _lib = None
 
 
@@ -94,6 +118,8 @@ def lib():
         "tg_regularize": ([P, P, P, P, c_i64, c_i32, P, P, P, P, P, P], st),
         "tg_solve_views": ([P, P, c_i64, c_i32, P, P, P, P, P, P], st),
         "tg_triangulate": ([P, P, P, P, P, P, c_i64, P, c_i32, P, P, P, P], st),
+        "tg_solve_triangulate": ([P, P, P, c_i64, P, c_i32, P, P, P, P], st),
+        "tg_solve_triangulate_batch": ([P, c_i32, P, P], st),
         "tg_bin_expand": ([P, P, c_i64, P, c_i32, P, P, P, c_i64, P, P, P, P], st),
         "tg_raster_fwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),
         "tg_raster_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),
@@ -102,6 +128,17 @@ def lib():
         "tg_ssim_loss_grad": ([P, P, c_i32, c_i32, c_i32, c_f, P, P, P, P, P], st),
         "tg_adam_step": ([P, P, P, P, c_i64, c_f, c_f, c_f, c_f, c_i32, P], st),
         "tg_adam_step_rows": ([P, P, P, P, c_i64, c_i32, c_i32, c_f, c_f, c_f, c_f, c_f, c_i32, P], st),
+        "tg_serve_create": ([P, P, P], st),
+        "tg_serve_destroy": ([P], st),
+        "tg_serve_now": ([P], c_d),
+        "tg_serve_open_stream": ([P, P, c_i64, P, c_i32, c_d, P], st),
+        "tg_serve_submit": ([P, c_i64, c_i64, P, P, c_i32, P, P, c_d], st),
+        "tg_serve_close_stream": ([P, c_i64], st),
+        "tg_serve_step": ([P, P], st),
+        "tg_serve_poll": ([P, P, c_i32, P], st),
+        "tg_serve_get_stats": ([P, P], st),
+        "tg_serve_dry_complete": ([P, c_i32, c_d], st),
+        "tg_serve_stream_bytes": ([P, c_i32, c_i64, P, P, P, P], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -114,9 +151,13 @@ def lib():
 def exported_symbols():
     return [n for n in ("tg_abi_version", "tg_status_string", "tg_default_params", "tg_num_cells",
                         "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_bin_sort_static", "tg_splat_accumulate",
-                        "tg_splat_accumulate_batch", "tg_regularize", "tg_solve_views", "tg_triangulate", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
-                        "tg_project_bwd", "tg_l1_loss_grad", "tg_ssim_loss_grad", "tg_adam_step",
-                        "tg_adam_step_rows")]
+                        "tg_splat_accumulate_batch", "tg_regularize", "tg_solve_views", "tg_triangulate",
+                        "tg_solve_triangulate", "tg_solve_triangulate_batch", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
+                        "tg_project_bwd", "tg_l1_loss_grad", "tg_ssim_loss_grad",
+                        "tg_adam_step",
+                        "tg_adam_step_rows", "tg_serve_create", "tg_serve_destroy", "tg_serve_now",
+                        "tg_serve_open_stream", "tg_serve_submit", "tg_serve_close_stream", "tg_serve_step",
+                        "tg_serve_poll", "tg_serve_get_stats", "tg_serve_dry_complete", "tg_serve_stream_bytes")]
 
 
 def check(fn, code):

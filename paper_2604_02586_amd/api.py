@@ -17,7 +17,8 @@ from . import _lib
 from ._lib import check, lib
 
 __all__ = ["GaussianTensors", "SplatTensors", "BinTensors", "MotionTransfer", "preprocess", "bin_sort", "bin_sort_static",
-           "splat_accumulate", "splat_accumulate_batch", "regularize", "solve_views", "triangulate", "bin_expand", "stream_ptr", "default_params"]
+           "splat_accumulate", "splat_accumulate_batch", "regularize", "solve_views", "triangulate", "solve_triangulate",
+           "solve_triangulate_batch", "cameras_device", "bin_expand", "stream_ptr", "default_params"]
 
 default_params = _lib.default_params
 
@@ -238,6 +239,58 @@ def triangulate(mu_new, cov_new, vflags, wn, s: SplatTensors, g_in: GaussianTens
         len(cams), ctypes.byref(params), ctypes.byref(go), _ptr(status), stream_ptr(stream)))
 
 
+def solve_triangulate(acc, s: SplatTensors, g_in: GaussianTensors, cams, params, g_out: GaussianTensors, status,
+                      stream=None):
+    """tg_solve_triangulate: per-view solves and the multi-view update in one
+    launch, nothing stored in between."""
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    sc, gi, go = s.c(), g_in.c(), g_out.c()
+    check("tg_solve_triangulate", lib().tg_solve_triangulate(
+        _ptr(acc), ctypes.byref(sc), ctypes.byref(gi), g_in.n, cams, len(cams), ctypes.byref(params),
+        ctypes.byref(go), _ptr(status), stream_ptr(stream)))
+
+
+def cameras_device(cams, device) -> torch.Tensor:
+    """The cameras as a device array ([V,20] float32, the tg_camera layout)
+    for tg_solve_triangulate_batch."""
+    cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
+    import numpy as np
+    host = np.frombuffer(bytes(cams), dtype=np.float32).reshape(len(cams), -1).copy()
+    return torch.from_numpy(host).to(device)
+
+
+def solve_triangulate_batch(slots, params, stream=None):
+    """One fused update launch over several Gaussian sets and frames.
+    slots: sequence of dicts with keys splats, g_in (GaussianTensors), cams
+    (device tensor from cameras_device), n, V, acc (per-frame [V,N,16]),
+    g_out (per-frame GaussianTensors), status (per-frame [N] int32 or None)."""
+    if len(slots) > _lib.TG_MAX_SLOTS:
+        raise ValueError(f"at most {_lib.TG_MAX_SLOTS} slots per launch")
+    keep = []
+    arr = (_lib.UpdSlot * max(1, len(slots)))()
+    for i, sl in enumerate(slots):
+        sc, gi = sl["splats"].c(), sl["g_in"].c()
+        acc, gout = list(sl["acc"]), list(sl["g_out"])
+        status = sl.get("status") or [None] * len(acc)
+        if not (len(acc) == len(gout) == len(status)) or not 1 <= len(acc) <= _lib.TG_MAX_FRAMES:
+            raise ValueError("acc, g_out and status need one entry per frame, 1..TG_MAX_FRAMES frames")
+        gos = [g.c() for g in gout]
+        keep += [sc, gi, gos]
+        arr[i].s = ctypes.addressof(sc)
+        arr[i].g_in = ctypes.addressof(gi)
+        arr[i].cams = _addr(sl["cams"])
+        arr[i].N = int(sl["n"])
+        arr[i].V = int(sl["V"])
+        arr[i].F = len(acc)
+        for f in range(len(acc)):
+            arr[i].acc[f] = _addr(acc[f])
+            arr[i].g_out[f] = ctypes.addressof(gos[f])
+            arr[i].status[f] = _addr(status[f])
+    check("tg_solve_triangulate_batch", lib().tg_solve_triangulate_batch(arr, len(slots), ctypes.byref(params),
+                                                                         stream_ptr(stream)))
+    del keep
+
+
 def bin_expand(s: SplatTensors, bins: BinTensors, n, cams, params, stream=None):
     """Per-tile depth-ordered lists (tile_ids, tile_ranges [T,2]); syncs."""
     cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
@@ -331,9 +384,14 @@ class MotionTransfer:
         triangulate(self.mu_new, self.cov_new, self.vflags, self.wn, self.splats, g_in, self.cams_host,
                     self.params, g_out, self.status)
 
+    def update(self, g_in: GaussianTensors, g_out: GaussianTensors):
+        """Fused per-view solve + multi-view update (tg_solve_triangulate)."""
+        solve_triangulate(self.acc, self.splats, g_in, self.cams_host, self.params, g_out, self.status)
+
     def run(self, g: GaussianTensors, disp, vis=None, g_out: GaussianTensors | None = None, check_overflow=True,
-            t_final=False, stats=False):
-        """Cold frame: preprocess -> bin_sort -> accumulate -> solve -> triangulate."""
+            t_final=False, stats=False, fused=False):
+        """Cold frame: preprocess -> bin_sort -> accumulate -> solve ->
+        triangulate (fused: the last two in one launch)."""
         if g_out is None:
             g_out = GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.quats),
                                     torch.empty_like(g.scales), g.opacity, g.sh, g.sh_degree, g.scale_mode,
@@ -341,8 +399,11 @@ class MotionTransfer:
         self.preprocess(g)
         self.bin_sort(check_overflow=check_overflow)
         self.accumulate(disp, vis, t_final=t_final, stats=stats)
-        self.solve()
-        self.triangulate(g, g_out)
+        if fused:
+            self.update(g, g_out)
+        else:
+            self.solve()
+            self.triangulate(g, g_out)
         return g_out
 
     def run_warm(self, g: GaussianTensors, disp, vis, g_out: GaussianTensors):

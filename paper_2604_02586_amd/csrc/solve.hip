@@ -12,16 +12,12 @@
 namespace {
 
 // ---------------------------------------------------------------- per view
-__global__ void __launch_bounds__(256) k_solve_views(const float4* __restrict__ acc, const float4* __restrict__ rec,
-                                                     const float* __restrict__ cov2d, const ushort4* __restrict__ rect,
-                                                     int64_t VN, tg_params prm, float2* __restrict__ mu_new,
-                                                     float* __restrict__ cov_new, uint8_t* __restrict__ flags,
-                                                     float2* __restrict__ wn)
+// Flags of one centred record and, when it is solved (flag 1), the FP64
+// solution Theta = V1^{-1} V2 as th = [t0x, t0y, t1x, t1y, t2x, t2y]
+// (rows of Theta: the x and y rows of G^T, then c^T).
+__device__ __forceinline__ uint8_t solve_record(const float4 a0, const float4 a1, const float4 a2, const float4 a3,
+                                                bool culled, const tg_params& prm, double th[6])
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= VN) return;
-    const float4 a0 = acc[4 * i], a1 = acc[4 * i + 1], a2 = acc[4 * i + 2], a3 = acc[4 * i + 3];
-    const ushort4 r = rect[i];
     // record: [Sw, Sux, Suy, Sxx, Sxy, Syy, Sdx, Sdy, Sxdx, Sxdy, Sydx, Sydy, n, ...]
     const double Sw = a0.x, Sux = a0.y, Suy = a0.z, Sxx = a0.w;
     const double Sxy = a1.x, Syy = a1.y, Sdx = a1.z, Sdy = a1.w;
@@ -36,7 +32,7 @@ __global__ void __launch_bounds__(256) k_solve_views(const float4* __restrict__ 
     const double c22 = Sxx * Syy - Sxy * Sxy;
     const double det = Sxx * c00 + Sxy * c01 + Sux * c02;
     uint8_t f = 0;
-    if (!(r.z > r.x && r.w > r.y)) f |= 2;
+    if (culled) f |= 2;
     if (n < (double)prm.pix_min) f |= 4;
     if (!(Sw >= prm.wsum_min)) f |= 8;
     if (!(det >= prm.det_min)) f |= 16;
@@ -53,32 +49,54 @@ __global__ void __launch_bounds__(256) k_solve_views(const float4* __restrict__ 
         const double tr = ca + cc;
         if (!(tr > 0.0) || !(4.0 * (ca * cc - cb * cb) >= prm.iso_min * tr * tr)) f |= 16;
     }
+    if (f != 0) return f;
+    const double id = 1.0 / det;
+    // inverse of V1 (symmetric): adj / det
+    const double i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
+    const double i11 = c11 * id, i12 = c12 * id, i22 = c22 * id;
+    // Theta = V1^{-1} V2, V2 = [[Sxdx, Sxdy], [Sydx, Sydy], [Sdx, Sdy]]
+    th[0] = i00 * Sxdx + i01 * Sydx + i02 * Sdx;
+    th[1] = i00 * Sxdy + i01 * Sydy + i02 * Sdy;
+    th[2] = i01 * Sxdx + i11 * Sydx + i12 * Sdx;
+    th[3] = i01 * Sxdy + i11 * Sydy + i12 * Sdy;
+    th[4] = i02 * Sxdx + i12 * Sydx + i22 * Sdx;
+    th[5] = i02 * Sxdy + i12 * Sydy + i22 * Sdy;
+    return 1;
+}
+
+// mu' = mu + c (Eq. 4's intercept in the centred frame), rounded to FP32.
+__device__ __forceinline__ float2 moved_centre(const double th[6], float mux, float muy) {
+    return make_float2((float)((double)mux + th[4]), (float)((double)muy + th[5]));
+}
+
+// Eq. 2: Sigma' = A Sigma A^T with A = I + G, rounded to FP32.
+__device__ __forceinline__ void moved_cov(const double th[6], double sa, double sb, double sc, float co[3]) {
+    const double A00 = 1.0 + th[0], A01 = th[2], A10 = th[1], A11 = 1.0 + th[3];
+    const double m00 = A00 * sa + A01 * sb, m01 = A00 * sb + A01 * sc;
+    const double m10 = A10 * sa + A11 * sb, m11 = A10 * sb + A11 * sc;
+    co[0] = (float)(m00 * A00 + m01 * A01);
+    co[1] = (float)(m00 * A10 + m01 * A11);
+    co[2] = (float)(m10 * A10 + m11 * A11);
+}
+
+__global__ void __launch_bounds__(256) k_solve_views(const float4* __restrict__ acc, const float4* __restrict__ rec,
+                                                     const float* __restrict__ cov2d, const ushort4* __restrict__ rect,
+                                                     int64_t VN, tg_params prm, float2* __restrict__ mu_new,
+                                                     float* __restrict__ cov_new, uint8_t* __restrict__ flags,
+                                                     float2* __restrict__ wn)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= VN) return;
+    const float4 a0 = acc[4 * i], a1 = acc[4 * i + 1], a2 = acc[4 * i + 2], a3 = acc[4 * i + 3];
+    const ushort4 r = rect[i];
+    double th[6];
+    const uint8_t f = solve_record(a0, a1, a2, a3, !(r.z > r.x && r.w > r.y), prm, th);
     float2 mo = make_float2(0.f, 0.f);
     float co[3] = {0.f, 0.f, 0.f};
-    if (f == 0) {
-        f = 1;
-        const double id = 1.0 / det;
-        // inverse of V1 (symmetric): adj / det
-        const double i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
-        const double i11 = c11 * id, i12 = c12 * id, i22 = c22 * id;
-        // Theta = V1^{-1} V2, V2 = [[Sxdx, Sxdy], [Sydx, Sydy], [Sdx, Sdy]]
-        const double t0x = i00 * Sxdx + i01 * Sydx + i02 * Sdx;
-        const double t0y = i00 * Sxdy + i01 * Sydy + i02 * Sdy;
-        const double t1x = i01 * Sxdx + i11 * Sydx + i12 * Sdx;
-        const double t1y = i01 * Sxdy + i11 * Sydy + i12 * Sdy;
-        const double t2x = i02 * Sxdx + i12 * Sydx + i22 * Sdx;
-        const double t2y = i02 * Sxdy + i12 * Sydy + i22 * Sdy;
-        // A = I + G with G = Theta[0:2]^T, c = Theta[2]
-        const double A00 = 1.0 + t0x, A01 = t1x, A10 = t0y, A11 = 1.0 + t1y;
+    if (f == 1) {
         const float4 rc = rec[2 * i];
-        mo = make_float2((float)((double)rc.x + t2x), (float)((double)rc.y + t2y));
-        const double sa = cov2d[3 * i], sb = cov2d[3 * i + 1], sc = cov2d[3 * i + 2];
-        // Sigma' = A Sigma A^T
-        const double m00 = A00 * sa + A01 * sb, m01 = A00 * sb + A01 * sc;
-        const double m10 = A10 * sa + A11 * sb, m11 = A10 * sb + A11 * sc;
-        co[0] = (float)(m00 * A00 + m01 * A01);
-        co[1] = (float)(m00 * A10 + m01 * A11);
-        co[2] = (float)(m10 * A10 + m11 * A11);
+        mo = moved_centre(th, rc.x, rc.y);
+        moved_cov(th, cov2d[3 * i], cov2d[3 * i + 1], cov2d[3 * i + 2], co);
     }
     mu_new[i] = mo;
     // accumulated alpha and pixel count, compact for the triangulation's
@@ -178,11 +196,8 @@ __device__ void quat_from_rot(const double* R, double* q) {
     q[3] = z * sg;
 }
 
-struct TriArgs {
-    const float2* mu_new;
-    const float* cov_new;
-    const uint8_t* vflags;
-    const float2* wn;
+// The Gaussians a multi-view update reads and writes.
+struct GaussIO {
     const float* means_in;
     const float* quats_in;
     const float* scales_in;
@@ -196,8 +211,70 @@ struct TriArgs {
     int scale_mode;
 };
 
-// The full multi-view update of Gaussian g.
-__device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, const tg_params& prm, int64_t g)
+// Per-view results as tg_solve_views stored them.
+struct StoredViews {
+    const float2* mu_new;
+    const float* cov_new;
+    const uint8_t* vflags;
+    const float2* wn;
+    // totals (accumulated alpha, pixels) and flag of view record o
+    __device__ __forceinline__ uint8_t screen(int64_t o, float2& t) const {
+        t = wn[o];
+        return vflags[o];
+    }
+    __device__ __forceinline__ uint8_t view(int64_t o, float2& t, float2& mu) const {
+        const uint8_t f = screen(o, t);
+        if (f == 1) mu = mu_new[o];
+        return f;
+    }
+    __device__ __forceinline__ void cov(int64_t o, float co[3]) const {
+        co[0] = cov_new[3 * o];
+        co[1] = cov_new[3 * o + 1];
+        co[2] = cov_new[3 * o + 2];
+    }
+};
+
+// Per-view results solved on the fly from the accumulator records (the
+// fused update): the same arithmetic as tg_solve_views, the same FP32
+// rounding of mu' and Sigma', nothing stored in between.
+struct RecordViews {
+    const float4* acc;
+    const float4* rec;
+    const float* cov2d;
+    const ushort4* rect;
+    const tg_params* prm;
+    __device__ __forceinline__ uint8_t solve(int64_t o, float2& t, double th[6]) const {
+        const float4 a0 = acc[4 * o], a1 = acc[4 * o + 1], a2 = acc[4 * o + 2], a3 = acc[4 * o + 3];
+        const ushort4 r = rect[o];
+        t = make_float2(a0.x, a3.x);
+        return solve_record(a0, a1, a2, a3, !(r.z > r.x && r.w > r.y), *prm, th);
+    }
+    __device__ __forceinline__ uint8_t screen(int64_t o, float2& t) const {
+        double th[6];
+        return solve(o, t, th);
+    }
+    __device__ __forceinline__ uint8_t view(int64_t o, float2& t, float2& mu) const {
+        double th[6];
+        const uint8_t f = solve(o, t, th);
+        if (f == 1) {
+            const float4 rc = rec[2 * o];
+            mu = moved_centre(th, rc.x, rc.y);
+        }
+        return f;
+    }
+    __device__ __forceinline__ void cov(int64_t o, float co[3]) const {
+        double th[6];
+        float2 t;
+        solve(o, t, th);
+        moved_cov(th, cov2d[3 * o], cov2d[3 * o + 1], cov2d[3 * o + 2], co);
+    }
+};
+
+// The full multi-view update of Gaussian g from the per-view results of
+// `src`; cams holds the V cameras.
+template <class Src>
+__device__ __forceinline__ void tri_one(const Src& src, const GaussIO& a, const tg_camera* cams,
+                                        const tg_params& prm, int64_t g)
 {
     const float om0 = a.means_in[3 * g], om1 = a.means_in[3 * g + 1], om2 = a.means_in[3 * g + 2];
     const float oq0 = a.quats_in[4 * g], oq1 = a.quats_in[4 * g + 1], oq2 = a.quats_in[4 * g + 2],
@@ -208,23 +285,25 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
     float ns[3] = {os0, os1, os2};
     uint32_t st = 0;
 
-    // ---- totals and DLT normal matrix (4x4, upper triangle)
+    // ---- totals and DLT normal matrix (4x4)
     double M[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) M[i] = 0.0;
     int nv = 0;
+    uint32_t solved = 0;   // bit v: view v solved (V <= 32)
     double sw = 0.0, nt = 0.0;
     for (int v = 0; v < a.V; ++v) {
         const int64_t o = (int64_t)v * a.N + g;
         // culled views accumulate nothing, so their totals are zero
-        const float2 t = a.wn[o];
+        float2 t, mu;
+        const uint8_t f = src.view(o, t, mu);
         sw += (double)t.x;
         nt += (double)t.y;
-        if (a.vflags[o] & 32) st |= 256;
-        if (a.vflags[o] != 1) continue;
+        if (f & 32) st |= 256;
+        if (f != 1) continue;
         ++nv;
-        const tg_camera& c = cams.cam[v];
-        const float2 mu = a.mu_new[o];
+        solved |= 1u << v;
+        const tg_camera& c = cams[v];
         const double xn = ((double)mu.x - c.cx) / c.fx, yn = ((double)mu.y - c.cy) / c.fy;
         double r1[4], r2[4];
 #pragma unroll
@@ -259,9 +338,8 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
             mu3[0] = h[0] / h[3];
             mu3[1] = h[1] / h[3];
             mu3[2] = h[2] / h[3];
-            for (int v = 0; v < a.V; ++v) {
-                if (a.vflags[(int64_t)v * a.N + g] != 1) continue;
-                const tg_camera& c = cams.cam[v];
+            for (uint32_t m = solved; m; m &= m - 1) {
+                const tg_camera& c = cams[__builtin_ctz(m)];
                 const double pz = c.R[6] * mu3[0] + c.R[7] * mu3[1] + c.R[8] * mu3[2] + c.t[2];
                 if (!(pz > prm.near_z)) st |= 128;
             }
@@ -277,10 +355,10 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
             for (int i = 0; i < 36; ++i) AtA[i] = 0.0;
 #pragma unroll
             for (int i = 0; i < 6; ++i) Atb[i] = 0.0;
-            for (int v = 0; v < a.V; ++v) {
+            for (uint32_t m = solved; m; m &= m - 1) {
+                const int v = __builtin_ctz(m);
                 const int64_t o = (int64_t)v * a.N + g;
-                if (a.vflags[o] != 1) continue;
-                const tg_camera& c = cams.cam[v];
+                const tg_camera& c = cams[v];
                 double p[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
@@ -298,7 +376,9 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
                     T0[j] = J00 * c.R[j] + J02 * c.R[6 + j];
                     T1[j] = J11 * c.R[3 + j] + J12 * c.R[6 + j];
                 }
-                const double rhs[3] = {a.cov_new[3 * o], a.cov_new[3 * o + 1], a.cov_new[3 * o + 2]};
+                float co[3];
+                src.cov(o, co);
+                const double rhs[3] = {co[0], co[1], co[2]};
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
                     const double* Ta = e == 2 ? T1 : T0;
@@ -337,26 +417,26 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
                 AtA[j * 6 + j] = d;
 #pragma unroll
                 for (int i = j + 1; i < 6; ++i) {
-                    double s = AtA[i * 6 + j];
+                    double sacc = AtA[i * 6 + j];
 #pragma unroll
-                    for (int k = 0; k < j; ++k) s -= AtA[i * 6 + k] * AtA[j * 6 + k];
-                    AtA[i * 6 + j] = s / d;
+                    for (int k = 0; k < j; ++k) sacc -= AtA[i * 6 + k] * AtA[j * 6 + k];
+                    AtA[i * 6 + j] = sacc / d;
                 }
             }
             double sol[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) {  // forward
-                double s = Atb[i];
+                double sacc = Atb[i];
 #pragma unroll
-                for (int k = 0; k < i; ++k) s -= AtA[i * 6 + k] * sol[k];
-                sol[i] = s / AtA[i * 6 + i];
+                for (int k = 0; k < i; ++k) sacc -= AtA[i * 6 + k] * sol[k];
+                sol[i] = sacc / AtA[i * 6 + i];
             }
 #pragma unroll
             for (int i = 5; i >= 0; --i) {  // backward
-                double s = sol[i];
+                double sacc = sol[i];
 #pragma unroll
-                for (int k = i + 1; k < 6; ++k) s -= AtA[k * 6 + i] * sol[k];
-                sol[i] = s / AtA[i * 6 + i];
+                for (int k = i + 1; k < 6; ++k) sacc -= AtA[k * 6 + i] * sol[k];
+                sol[i] = sacc / AtA[i * 6 + i];
             }
             double S[9] = {sol[0], sol[1], sol[2], sol[1], sol[3], sol[4], sol[2], sol[4], sol[5]};
             double Ev[9];
@@ -440,16 +520,16 @@ __device__ __forceinline__ void tri_one(const TriArgs& a, const CamPack& cams, c
 
 // The totals that decide whether Gaussian g is a candidate at all (views
 // solved, accumulated alpha, pixels); a non-candidate is copied and done.
-__device__ __forceinline__ uint32_t tri_light(const TriArgs& a, const tg_params& prm, int64_t g) {
+template <class Src>
+__device__ __forceinline__ uint32_t tri_light(const Src& src, const GaussIO& a, const tg_params& prm, int64_t g) {
     int nv = 0;
     bool nonfinite = false;
     double sw = 0.0, nt = 0.0;
     for (int v = 0; v < a.V; ++v) {
-        const int64_t o = (int64_t)v * a.N + g;
-        const float2 t = a.wn[o];
+        float2 t;
+        const uint8_t f = src.screen((int64_t)v * a.N + g, t);
         sw += (double)t.x;
         nt += (double)t.y;
-        const uint8_t f = a.vflags[o];
         if (f == 1) ++nv;
         if (f & 32) nonfinite = true;
     }
@@ -466,19 +546,19 @@ __device__ __forceinline__ uint32_t tri_light(const TriArgs& a, const tg_params&
 // Gaussians qualify.
 constexpr int TRI_THREADS = 256;
 constexpr int TRI_ITEMS = 8;
+constexpr int TRI_SPAN = TRI_THREADS * TRI_ITEMS;
 
-__global__ void __launch_bounds__(TRI_THREADS) k_triangulate(TriArgs a, CamPack cams, tg_params prm)
+template <class Src>
+__device__ __forceinline__ void tri_block(const Src& src, const GaussIO& a, const tg_camera* cams,
+                                          const tg_params& prm, int64_t base, uint32_t* cand, uint32_t& cn)
 {
-    __shared__ uint32_t cand[TRI_THREADS * TRI_ITEMS];
-    __shared__ uint32_t cn;
     const int t = threadIdx.x;
     if (t == 0) cn = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * (TRI_THREADS * TRI_ITEMS);
     for (int it = 0; it < TRI_ITEMS; ++it) {
         const int64_t g = base + (int64_t)it * TRI_THREADS + t;
         if (g >= a.N) break;
-        uint32_t st = tri_light(a, prm, g);
+        uint32_t st = tri_light(src, a, prm, g);
         if ((st & ~256u) == 0) {
             cand[atomicAdd(&cn, 1u)] = (uint32_t)(g - base);
         } else {
@@ -506,7 +586,120 @@ __global__ void __launch_bounds__(TRI_THREADS) k_triangulate(TriArgs a, CamPack 
     }
     __syncthreads();
     const uint32_t n = cn;
-    for (uint32_t i = t; i < n; i += TRI_THREADS) tri_one(a, cams, prm, base + cand[i]);
+    for (uint32_t i = t; i < n; i += TRI_THREADS) tri_one(src, a, cams, prm, base + cand[i]);
+}
+
+__global__ void __launch_bounds__(TRI_THREADS) k_triangulate(StoredViews src, GaussIO a, CamPack cams, tg_params prm)
+{
+    __shared__ uint32_t cand[TRI_SPAN];
+    __shared__ uint32_t cn;
+    tri_block(src, a, cams.cam, prm, (int64_t)blockIdx.x * TRI_SPAN, cand, cn);
+}
+
+// ---- fused per-view solve + multi-view update, batched over Gaussian sets
+// and frames (one launch per serving step).
+struct UpdSlotK {
+    const float4* rec;
+    const float* cov2d;
+    const ushort4* rect;
+    const tg_camera* cams;   // device [V]
+    const float* means_in;
+    const float* quats_in;
+    const float* scales_in;
+    const float* opacity_in;
+    int64_t N;
+    int32_t V;
+    int32_t scale_mode;
+};
+
+struct UpdFrameK {
+    const float4* acc;
+    float* means_out;
+    float* quats_out;
+    float* scales_out;
+    uint32_t* status;
+    int32_t slot;
+    int32_t blk0;            // first block of this frame in the launch
+};
+
+constexpr int UPD_MAX_ITEMS = TG_MAX_SLOTS * TG_MAX_FRAMES;
+
+struct UpdBatchK {
+    UpdSlotK slot[TG_MAX_SLOTS];
+    UpdFrameK fr[UPD_MAX_ITEMS];
+    int32_t n_fr;
+};
+
+__device__ __forceinline__ void update_item(const UpdSlotK& sl, const UpdFrameK& fr, const tg_camera* lcam,
+                                            const tg_params& prm, int64_t blk, uint32_t* cand, uint32_t& cn)
+{
+    RecordViews src{fr.acc, sl.rec, sl.cov2d, sl.rect, &prm};
+    GaussIO a{sl.means_in, sl.quats_in, sl.scales_in, sl.opacity_in, fr.means_out, fr.quats_out, fr.scales_out,
+              fr.status, sl.N, sl.V, sl.scale_mode};
+    tri_block(src, a, lcam, prm, blk * TRI_SPAN, cand, cn);
+}
+
+// One frame; cameras in the kernel arguments.
+__global__ void __launch_bounds__(TRI_THREADS) k_update_one(UpdSlotK sl, UpdFrameK fr, CamPack cams, tg_params prm)
+{
+    __shared__ uint32_t cand[TRI_SPAN];
+    __shared__ uint32_t cn;
+    update_item(sl, fr, cams.cam, prm, blockIdx.x, cand, cn);
+}
+
+// Several (Gaussian set, frame) items; each set's cameras are copied from
+// device memory into LDS by the block.
+__global__ void __launch_bounds__(TRI_THREADS) k_update_batch(UpdBatchK b, tg_params prm)
+{
+    __shared__ uint32_t cand[TRI_SPAN];
+    __shared__ uint32_t cn;
+    __shared__ tg_camera lcam[TG_MAX_VIEWS];
+    int k = 0;
+    while (k + 1 < b.n_fr && b.fr[k + 1].blk0 <= (int32_t)blockIdx.x) ++k;
+    const UpdFrameK& fr = b.fr[k];
+    const UpdSlotK& sl = b.slot[fr.slot];
+    {
+        const int nw = sl.V * (int)(sizeof(tg_camera) / 4);
+        const uint32_t* src = (const uint32_t*)sl.cams;
+        uint32_t* dst = (uint32_t*)lcam;
+        for (int i = threadIdx.x; i < nw; i += TRI_THREADS) dst[i] = src[i];
+    }
+    __syncthreads();
+    update_item(sl, fr, lcam, prm, (int64_t)blockIdx.x - fr.blk0, cand, cn);
+}
+
+tg_status check_gauss(const tg_gaussians* g, bool in) {
+    if (!g || !g->means || !g->quats || !g->scales || (in && !g->opacity)) return TG_ERR_INVALID_ARG;
+    if (in && (g->scale_mode < 0 || g->scale_mode > 1)) return TG_ERR_INVALID_ARG;
+    return TG_OK;
+}
+
+UpdSlotK slot_args(const tg_splats* s, const tg_gaussians* g_in, const tg_camera* cams_dev, int64_t N, int V) {
+    UpdSlotK k;
+    k.rec = (const float4*)s->rec;
+    k.cov2d = s->cov2d;
+    k.rect = (const ushort4*)s->rect;
+    k.cams = cams_dev;
+    k.means_in = g_in->means;
+    k.quats_in = g_in->quats;
+    k.scales_in = g_in->scales;
+    k.opacity_in = g_in->opacity;
+    k.N = N;
+    k.V = V;
+    k.scale_mode = g_in->scale_mode;
+    return k;
+}
+
+UpdFrameK frame_args(const float* acc, tg_gaussians* g_out, uint32_t* status, int slot, int blk0) {
+    UpdFrameK f;
+    f.acc = (const float4*)acc;
+    f.means_out = g_out->means;
+    f.quats_out = g_out->quats;
+    f.scales_out = g_out->scales;
+    f.status = status;
+    f.slot = slot;
+    f.blk0 = blk0;
+    return f;
 }
 
 }  // namespace
@@ -532,36 +725,72 @@ extern "C" tg_status tg_triangulate(const float* mu2d_new, const float* cov2d_ne
                                     const tg_camera* cams, int32_t V, const tg_params* p, tg_gaussians* g_out,
                                     uint32_t* status, void* stream)
 {
-    if (!mu2d_new || !cov2d_new || !vflags || !wn || !s || !g_in || !cams || !p || !g_out || N < 0 || V < 1)
+    if (!mu2d_new || !cov2d_new || !vflags || !wn || !s || !cams || !p || N < 0 || V < 1)
         return TG_ERR_INVALID_ARG;
     if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
-    if (!g_in->means || !g_in->quats || !g_in->scales || !g_in->opacity || !g_out->means || !g_out->quats ||
-        !g_out->scales)
-        return TG_ERR_INVALID_ARG;
-    if (g_in->scale_mode < 0 || g_in->scale_mode > 1) return TG_ERR_INVALID_ARG;
+    if (check_gauss(g_in, true) != TG_OK || check_gauss(g_out, false) != TG_OK) return TG_ERR_INVALID_ARG;
     if (((uintptr_t)mu2d_new & 7u) || ((uintptr_t)wn & 7u)) return TG_ERR_ALIGNMENT;
     if (N == 0) return TG_OK;
-    TriArgs a;
-    a.mu_new = (const float2*)mu2d_new;
-    a.cov_new = cov2d_new;
-    a.vflags = vflags;
-    a.wn = (const float2*)wn;
-    a.means_in = g_in->means;
-    a.quats_in = g_in->quats;
-    a.scales_in = g_in->scales;
-    a.opacity_in = g_in->opacity;
-    a.means_out = g_out->means;
-    a.quats_out = g_out->quats;
-    a.scales_out = g_out->scales;
-    a.status = status;
-    a.N = N;
-    a.V = V;
-    a.scale_mode = g_in->scale_mode;
+    StoredViews src{(const float2*)mu2d_new, cov2d_new, vflags, (const float2*)wn};
+    GaussIO a{g_in->means, g_in->quats, g_in->scales, g_in->opacity, g_out->means, g_out->quats, g_out->scales,
+              status, N, V, g_in->scale_mode};
     CamPack cp;
     for (int v = 0; v < V; ++v) cp.cam[v] = cams[v];
-    hipLaunchKernelGGL(k_triangulate, dim3((unsigned)((N + TRI_THREADS * TRI_ITEMS - 1) / (TRI_THREADS * TRI_ITEMS))),
-                       dim3(TRI_THREADS), 0, (hipStream_t)stream, a, cp,
-                       *p);
+    hipLaunchKernelGGL(k_triangulate, dim3((unsigned)((N + TRI_SPAN - 1) / TRI_SPAN)), dim3(TRI_THREADS), 0,
+                       (hipStream_t)stream, src, a, cp, *p);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}
+
+extern "C" tg_status tg_solve_triangulate(const float* acc, const tg_splats* s, const tg_gaussians* g_in, int64_t N,
+                                          const tg_camera* cams, int32_t V, const tg_params* p, tg_gaussians* g_out,
+                                          uint32_t* status, void* stream)
+{
+    if (!acc || !s || !cams || !p || N < 0 || V < 1) return TG_ERR_INVALID_ARG;
+    if (V > TG_MAX_VIEWS) return TG_ERR_UNSUPPORTED;
+    if (!s->rec || !s->cov2d || !s->rect) return TG_ERR_INVALID_ARG;
+    if (check_gauss(g_in, true) != TG_OK || check_gauss(g_out, false) != TG_OK) return TG_ERR_INVALID_ARG;
+    if (!aligned16(acc) || !aligned16(s->rec)) return TG_ERR_ALIGNMENT;
+    if (N == 0) return TG_OK;
+    if ((N + TRI_SPAN - 1) / TRI_SPAN > (int64_t)0x7FFFFFFF) return TG_ERR_UNSUPPORTED;
+    CamPack cp;
+    for (int v = 0; v < V; ++v) cp.cam[v] = cams[v];
+    const UpdSlotK sl = slot_args(s, g_in, nullptr, N, V);
+    const UpdFrameK fr = frame_args(acc, g_out, status, 0, 0);
+    hipLaunchKernelGGL(k_update_one, dim3((unsigned)((N + TRI_SPAN - 1) / TRI_SPAN)), dim3(TRI_THREADS), 0,
+                       (hipStream_t)stream, sl, fr, cp, *p);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}
+
+extern "C" tg_status tg_solve_triangulate_batch(const tg_upd_slot* slots, int32_t n_slots, const tg_params* p,
+                                                void* stream)
+{
+    if (!p || n_slots < 0 || (n_slots > 0 && !slots)) return TG_ERR_INVALID_ARG;
+    if (n_slots > TG_MAX_SLOTS) return TG_ERR_UNSUPPORTED;
+    UpdBatchK b;
+    b.n_fr = 0;
+    int64_t blocks = 0;
+    // every argument is checked before anything is launched
+    for (int k = 0; k < n_slots; ++k) {
+        const tg_upd_slot& u = slots[k];
+        if (!u.s || !u.g_in || !u.cams || u.N < 0 || u.V < 1) return TG_ERR_INVALID_ARG;
+        if (u.V > TG_MAX_VIEWS || u.F < 1 || u.F > TG_MAX_FRAMES) return TG_ERR_UNSUPPORTED;
+        if (!u.s->rec || !u.s->cov2d || !u.s->rect || check_gauss(u.g_in, true) != TG_OK) return TG_ERR_INVALID_ARG;
+        if (!aligned16(u.s->rec) || ((uintptr_t)u.cams & 3u)) return TG_ERR_ALIGNMENT;
+        b.slot[k] = slot_args(u.s, u.g_in, u.cams, u.N, u.V);
+        if (u.N == 0) continue;
+        const int64_t nb = (u.N + TRI_SPAN - 1) / TRI_SPAN;
+        for (int f = 0; f < u.F; ++f) {
+            if (!u.acc[f] || check_gauss(u.g_out[f], false) != TG_OK) return TG_ERR_INVALID_ARG;
+            if (!aligned16(u.acc[f])) return TG_ERR_ALIGNMENT;
+            b.fr[b.n_fr++] = frame_args(u.acc[f], u.g_out[f], u.status[f], k, (int32_t)blocks);
+            blocks += nb;
+            if (blocks > (int64_t)0x7FFFFFFF) return TG_ERR_UNSUPPORTED;
+        }
+    }
+    if (blocks == 0) return TG_OK;
+    hipLaunchKernelGGL(k_update_batch, dim3((unsigned)blocks), dim3(TRI_THREADS), 0, (hipStream_t)stream, b, *p);
     TG_CHECK_LAUNCH();
     return TG_OK;
 }

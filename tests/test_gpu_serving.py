@@ -1,9 +1,10 @@
-"""GPU tests of the continuous-batching server: clips of different size,
-view count and resolution arrive interleaved under a budget that holds two
-of them at a time; each frame's result in the mix equals its result alone
-(one cold frame through tg_preprocess .. tg_triangulate) and matches the
-oracle, within the end-to-end tolerance (positions 1e-3, rotations 0.05 deg,
-scales 1e-3 relative)."""
+"""GPU tests of libtg's continuous-batching server (tg_serve_*): clips of
+different size, view count and resolution arrive interleaved under an arena
+that holds two of them at a time; each frame's result in the mix (batched
+accumulate + fused update) equals its result alone (one cold frame through
+tg_preprocess .. tg_triangulate) and matches the oracle, within the
+end-to-end tolerance (positions 1e-3, rotations 0.05 deg, scales 1e-3
+relative, widened by the oracle's own FP32 sensitivity)."""
 from types import SimpleNamespace
 
 import numpy as np
@@ -12,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from helpers import check_end_to_end, compare_accumulators, dump, eigen_gap, log, rotation_angle_deg, sensitivity
+from helpers import SENS_K, check_end_to_end, dump, eigen_gap, log, rotation_angle_deg, sensitivity
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +35,7 @@ def _host(out, st, acc=None, mu=None, cov=None, vfl=None):
 @pytest.fixture(scope="module")
 def runs():
     from paper_2604_02586_amd import api
-    from paper_2604_02586_amd.serving import Server, frame_bytes
+    from paper_2604_02586_amd.serving import Server, stream_bytes
     dev = torch.device("cuda:0")
     clips = [synth.make_clip(**c) for c in CLIPS]
     gs = [api.GaussianTensors.from_scene(c.scene, dev) for c in clips]
@@ -49,49 +50,54 @@ def runs():
             torch.cuda.synchronize()
             alone[ci, f] = _host(out, mt.status, mt.acc, mt.mu_new, mt.cov_new, mt.vflags)
     log(f"alone: {len(alone)} frames")
-    # mix: a budget that holds two clips at once
-    probe = Server(budget_bytes=1 << 50)
-    need = []
-    for ci, (c, g) in enumerate(zip(clips, gs)):
-        cs = probe.open_clip(100 + ci, g, c.cams, 1)
-        need.append(cs.nbytes + frame_bytes(c.scene.n, len(c.cams), c.cams[0].H, c.cams[0].W))
-    # room for any two clips at once, never for all three
+    # mix: an arena that holds any two clips (resident set + one frame's
+    # working set) at once, never all three
+    need = [sum(stream_bytes(c.cams, c.scene.n)[:2]) for c in clips]
     budget = sum(need) - 1
-    srv = Server(budget_bytes=budget, keep_intermediate=True)
-    for ci, (c, g) in enumerate(zip(clips, gs)):
-        srv.open_clip(ci, g, c.cams, c.disp.shape[0])
+    assert all(need[i] + need[j] <= budget for i in range(3) for j in range(i + 1, 3))
+    srv = Server(budget_bytes=budget)
+    sids = [srv.open_clip(g, c.cams) for c, g in zip(clips, gs)]
     rng = np.random.default_rng(9)
     order = [(ci, f) for ci, c in enumerate(clips) for f in range(c.disp.shape[0])]
     rng.shuffle(order)
     nxt = {ci: 0 for ci in range(len(clips))}
     frames = {}
+    waited = 0
     while order:
         for k, (ci, f) in enumerate(order):
             if nxt[ci] == f:
                 break
         ci, f = order.pop(k)
         c = clips[ci]
-        frames[ci, f] = srv.submit(ci, f + 1, torch.as_tensor(c.disp[f]).pin_memory(),
+        frames[ci, f] = srv.submit(sids[ci], f, torch.as_tensor(c.disp[f]).pin_memory(),
                                    torch.as_tensor(c.vis[f]).pin_memory())
         nxt[ci] += 1
+        if nxt[ci] == c.disp.shape[0]:
+            srv.close(sids[ci])
         srv.poll()
+        waited = max(waited, srv.stats()["waiting_streams"])
     srv.drain()
+    srv.step()
     torch.cuda.synchronize()
     mix = {k: _host(*fr.result) for k, fr in frames.items()}
     for (ci, f), r in mix.items():
         dump(f"serve_mix_{ci}_{f}", r)
         dump(f"serve_alone_{ci}_{f}", alone[ci, f])
-    log(f"mix: {srv.steps} steps, {srv.slots_launched} slots, max admitted {srv.max_admitted}")
-    return clips, alone, mix, srv
+    st = srv.stats()
+    log(f"mix: {st}; most streams waiting for admission at once: {waited}")
+    return clips, alone, mix, (srv, st, frames, waited)
 
 
 def test_every_frame_finished_with_batching_and_queueing(runs):
-    clips, alone, mix, srv = runs
+    clips, alone, mix, (srv, st, frames, waited) = runs
     assert len(mix) == sum(c.disp.shape[0] for c in clips)
-    assert srv.sched.used == 0 and srv.sched.idle()
-    assert srv.max_admitted < len(clips)        # admission queued a clip
-    assert srv.steps < len(mix)                 # some step carried several frames
-    assert max(srv.frames_per_step) >= 2
+    assert all(fr.status == 0 and fr.done >= fr.arrival for fr in frames.values())
+    assert st["arena_used"] == 0 and st["admitted_streams"] == 0 and st["waiting_streams"] == 0
+    # the third clip waited for memory (admission reserves the binning
+    # workspace, released once the clip's bins are ready)
+    assert waited >= 1
+    assert st["steps"] < len(mix)               # some step carried several frames
+    assert st["arena_peak"] <= srv.arena.numel()
 
 
 def test_mix_matches_oracle(runs):
@@ -100,9 +106,6 @@ def test_mix_matches_oracle(runs):
         c = clips[ci]
         wl = SimpleNamespace(scene=c.scene, cams=c.cams)
         ref = oracle.motion_transfer(c.scene, c.cams, c.disp[f], c.vis[f])
-        nbad, ntot, info = compare_accumulators(m["acc"], ref["comp"])
-        log(f"clip {ci} frame {f}: accumulators {nbad}/{ntot} outside tolerance {info}")
-        assert nbad == 0, info
         check_end_to_end(f"clip {ci} frame {f}", wl, ref, m)
 
 
@@ -121,11 +124,11 @@ def test_mix_equals_alone(runs):
         assert diff.sum() <= max(2, 2e-3 * diff.size), diff.sum()
         both = (a["status"] & oracle.ST_POS).astype(bool) & (m["status"] & oracle.ST_POS).astype(bool)
         dpos = np.linalg.norm(a["means"][both].astype(np.float64) - m["means"][both], axis=-1)
-        assert np.all(dpos <= 1e-3 + 6 * sens["dp"][both])
+        assert np.all(dpos <= 1e-3 + 2 * SENS_K * sens["dp"][both])
         cov = (a["status"] & oracle.ST_COV).astype(bool) & (m["status"] & oracle.ST_COV).astype(bool)
         rot = cov & (eigen_gap(ref["tri"]["eig"]) >= 1e-2)
         ang = rotation_angle_deg(a["quats"][rot].astype(np.float64), m["quats"][rot].astype(np.float64))
-        assert np.all(ang <= 0.05 + 6 * sens["ang"][rot])
+        assert np.all(ang <= 0.05 + 2 * SENS_K * sens["ang"][rot])
         wide = int((dpos > 1e-3).sum() + (ang > 0.05).sum())
         assert wide <= max(2, 0.01 * max(1, both.sum())), wide
         log(f"clip {ci} frame {f}: status diff {diff.sum()}, max dpos {dpos.max() if dpos.size else 0:.2e}, "
