@@ -4,7 +4,8 @@
 One step = one cold frame of the whole hot path on one batch of synthetic
 input already resident in HBM:
     tg_preprocess -> tg_bin_sort -> (zero accumulators) -> tg_splat_accumulate
-    -> tg_solve_views -> tg_triangulate
+    -> tg_solve_triangulate (the per-view solves and the multi-view update in
+       one launch)
 for 1M Gaussians x 20 views x 1920x1080 (the paper-shaped "large" workload:
 large motions, 5% uniform outlier tracks, Bernoulli(0.9) track visibility).
 
@@ -384,7 +385,7 @@ def main():
     log(f"  pairs evaluated {e_eval}, contributing {e_contrib}, pixel steps {n_steps}, list refills {n_refill}")
 
     stream = torch.cuda.current_stream()
-    names = ["preprocess", "bin_sort", "zero_acc", "accumulate", "solve", "triangulate"]
+    names = ["preprocess", "bin_sort", "zero_acc", "accumulate", "solve_triangulate"]
 
     def step(ev=None):
         def mark(i):
@@ -399,16 +400,14 @@ def main():
         mark(3)
         api.splat_accumulate(mt.splats, mt.bins, N, mt.cams_host, disp, vis, mt.params, mt.acc)
         mark(4)
-        mt.solve()
+        mt.update(g, g_out)
         mark(5)
-        mt.triangulate(g, g_out)
-        mark(6)
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(args.steps)]
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -418,7 +417,7 @@ def main():
     t1 = time.perf_counter()
     assert int(mt.bins.overflow.item()) == 0, "pair capacity overflow during timing"
     ms = (t1 - t0) * 1e3 / args.steps
-    stage = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(6)] for k in range(args.steps)])
+    stage = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(len(names))] for k in range(args.steps)])
     stage_ms = {n: float(np.mean(stage[:, i])) for i, n in enumerate(names)}
     frame_ms = stage.sum(1)
     acc_ms = stage_ms["accumulate"]
@@ -442,8 +441,7 @@ def main():
                 m.bin_sort(check_overflow=False)
                 m.acc.zero_()
                 api.splat_accumulate(m.splats, m.bins, N, m.cams_host, disp, vis, m.params, m.acc)
-                m.solve()
-                m.triangulate(g, o)
+                m.update(g, o)
 
         torch.cuda.synchronize()
         for k in range(args.warmup * args.inflight):

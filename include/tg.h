@@ -580,6 +580,15 @@ tg_status tg_project_bwd(const tg_gaussians* g, const tg_splats* s, int64_t N, c
 tg_status tg_l1_loss_grad(const float* image, const float* target, int64_t n, float scale, float* grad,
                           float* loss_sum, void* stream);
 
+/* Chain rule by a device scalar: out[i] = in[i] * factor[0] (factor: device
+ * float, e.g. the upstream gradient of a scalar loss; out may equal in). */
+tg_status tg_scale_by(float* out, const float* in, int64_t n, const float* factor, void* stream);
+
+/* out[0] = c + sum_{i<k} w[i] x[i]: assembles a scalar objective from the
+ * sums the loss kernels accumulated (x: device [k]; w: host [k], k <= 8;
+ * out: device float). */
+tg_status tg_scalar_affine(float* out, const float* x, int32_t k, const float* w, float c, void* stream);
+
 /*
  * tg_ssim_loss_grad -- the structural-similarity term of the 3DGS objective
  * the refinement optimises (Sec. 4.6: (1 - lambda) L1 + lambda (1 - SSIM),

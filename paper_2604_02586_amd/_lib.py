@@ -125,6 +125,8 @@ def lib():
         "tg_raster_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),
         "tg_project_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P], st),
         "tg_l1_loss_grad": ([P, P, c_i64, c_f, P, P, P], st),
+        "tg_scale_by": ([P, P, c_i64, P, P], st),
+        "tg_scalar_affine": ([P, P, c_i32, P, c_f, P], st),
         "tg_ssim_loss_grad": ([P, P, c_i32, c_i32, c_i32, c_f, P, P, P, P, P], st),
         "tg_adam_step": ([P, P, P, P, c_i64, c_f, c_f, c_f, c_f, c_i32, P], st),
         "tg_adam_step_rows": ([P, P, P, P, c_i64, c_i32, c_i32, c_f, c_f, c_f, c_f, c_f, c_i32, P], st),
@@ -153,7 +155,7 @@ def exported_symbols():
                         "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_bin_sort_static", "tg_splat_accumulate",
                         "tg_splat_accumulate_batch", "tg_regularize", "tg_solve_views", "tg_triangulate",
                         "tg_solve_triangulate", "tg_solve_triangulate_batch", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
-                        "tg_project_bwd", "tg_l1_loss_grad", "tg_ssim_loss_grad",
+                        "tg_project_bwd", "tg_l1_loss_grad", "tg_scale_by", "tg_scalar_affine", "tg_ssim_loss_grad",
                         "tg_adam_step",
                         "tg_adam_step_rows", "tg_serve_create", "tg_serve_destroy", "tg_serve_now",
                         "tg_serve_open_stream", "tg_serve_submit", "tg_serve_close_stream", "tg_serve_step",

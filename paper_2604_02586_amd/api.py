@@ -409,6 +409,5 @@ class MotionTransfer:
     def run_warm(self, g: GaussianTensors, disp, vis, g_out: GaussianTensors):
         """Warm frame (splats and bins of the reference frame resident)."""
         self.accumulate(disp, vis)
-        self.solve()
-        self.triangulate(g, g_out)
+        self.update(g, g_out)
         return g_out

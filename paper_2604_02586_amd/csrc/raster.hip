@@ -714,6 +714,26 @@ tg_status raster_setup(const tg_splats* s, const tg_bins* bins, int64_t N, const
     return TG_OK;
 }
 
+// out = in * factor (factor a device scalar: the upstream gradient of a
+// loss, so the chain rule needs no host read)
+__global__ void __launch_bounds__(256) k_scale_by(float* __restrict__ out, const float* __restrict__ in, int64_t n,
+                                                  const float* __restrict__ factor) {
+    const float f = *factor;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = in[i] * f;
+}
+
+// out[0] = c + sum_i w_i x[i] for a few device scalars x.
+constexpr int AFFINE_MAX = 8;
+struct AffineW {
+    float w[AFFINE_MAX];
+};
+__global__ void k_scalar_affine(float* __restrict__ out, const float* __restrict__ x, int k, AffineW w, float c) {
+    float r = c;
+    for (int i = 0; i < k; ++i) r = fmaf(w.w[i], x[i], r);
+    *out = r;
+}
+
 }  // namespace
 
 extern "C" tg_status tg_raster_fwd(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams,
@@ -832,4 +852,25 @@ extern "C" tg_status tg_adam_step_rows(float* param, const float* grad, float* m
                                        float eps, int32_t step, void* stream)
 {
     return adam_launch(param, grad, m, v, n, row, head, lr_head, lr_tail, beta1, beta2, eps, step, stream);
+}
+
+extern "C" tg_status tg_scale_by(float* out, const float* in, int64_t n, const float* factor, void* stream)
+{
+    if (!out || !in || !factor || n < 0) return TG_ERR_INVALID_ARG;
+    if (n == 0) return TG_OK;
+    const int64_t blocks = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+    hipLaunchKernelGGL(k_scale_by, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, out, in, n, factor);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}
+
+extern "C" tg_status tg_scalar_affine(float* out, const float* x, int32_t k, const float* w, float c, void* stream)
+{
+    if (!out || k < 0 || (k > 0 && (!x || !w))) return TG_ERR_INVALID_ARG;
+    if (k > AFFINE_MAX) return TG_ERR_UNSUPPORTED;
+    AffineW aw;
+    for (int i = 0; i < AFFINE_MAX; ++i) aw.w[i] = i < k ? w[i] : 0.0f;
+    hipLaunchKernelGGL(k_scalar_affine, dim3(1), dim3(1), 0, (hipStream_t)stream, out, x, k, aw, c);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
 }

@@ -45,20 +45,56 @@ class RasterContext:
         self.image = torch.empty(*shp, 3, dtype=torch.float32, device=self.device)
         self.n_proc = torch.empty(*shp, dtype=torch.int32, device=self.device)
         self.grad2d = torch.empty(self.V, self.N, 9, dtype=torch.float32, device=self.device)
+        # forward count: a backward must follow its own forward (the buffers
+        # above are reused by every forward through this context)
+        self.gen = 0
+        # pair-count check without a host sync per iteration: each binning
+        # copies its count and overflow flag to pinned memory behind an
+        # event; the next forward reads the previous one (already finished)
+        self._check = torch.zeros(2, dtype=torch.int64).pin_memory()
+        self._check_ev = None
+        self._sized = False
 
     def _alloc_bins(self, capacity):
         self.bins = BinTensors.alloc(self.V, self.N, self.n_cells, capacity, self.device)
         self.ws = torch.empty(bin_sort_ws_bytes(self.N, self.cams, self.params, capacity), dtype=torch.uint8,
                               device=self.device)
 
+    def _lagged_check(self):
+        """Reads the previous binning's pair count (its event has long
+        completed by the next iteration); raises if it overflowed, after
+        growing the capacity for the next forward."""
+        if self._check_ev is None:
+            return
+        self._check_ev.synchronize()
+        self._check_ev = None
+        if int(self._check[1]):
+            need = int(self._check[0])
+            self._alloc_bins(int(need * 1.25) + 1024)
+            raise RuntimeError(f"pair-list overflow in the previous forward ({need} pairs, capacity too small): "
+                               "its image and gradient were incomplete; the capacity has been raised")
+
     def forward(self, g: GaussianTensors, check_overflow=True):
+        """Renders into self.image (valid until the next forward through this
+        context).  The first forward sizes the pair list with a host sync;
+        later ones check the previous forward's count without one."""
+        if check_overflow:
+            self._lagged_check()
         preprocess(g, self.cams, self.params, self.splats)
         bin_sort(self.splats, self.N, self.cams, self.params, self.bins, self.ws)
-        if check_overflow:
+        if check_overflow and not self._sized:
             torch.cuda.current_stream().synchronize()
-            if int(self.bins.overflow.item()):
-                self._alloc_bins(int(int(self.bins.n_pairs.item()) * 1.1) + 1024)
+            need = int(self.bins.n_pairs.item())
+            if int(self.bins.overflow.item()) or need * 1.25 > self.bins.capacity:
+                self._alloc_bins(int(need * 1.25) + 1024)
                 bin_sort(self.splats, self.N, self.cams, self.params, self.bins, self.ws)
+            self._sized = True
+        elif check_overflow:
+            self._check[0].copy_(self.bins.n_pairs[0], non_blocking=True)
+            self._check[1].copy_(self.bins.overflow[0].to(torch.int64), non_blocking=True)
+            self._check_ev = torch.cuda.Event()
+            self._check_ev.record(torch.cuda.current_stream())
+        self.gen += 1
         sc, bc = self.splats.c(), self.bins.c()
         check("tg_raster_fwd", lib().tg_raster_fwd(ctypes.byref(sc), ctypes.byref(bc), self.N, self.cams, self.V,
                                                    self.bg, ctypes.byref(self.params), _ptr(self.image), None,
@@ -86,12 +122,17 @@ class Rasterize(torch.autograd.Function):
         deg = int(round((sh.shape[1]) ** 0.5)) - 1
         g = GaussianTensors(means.contiguous(), quats.contiguous(), log_scales.contiguous(),
                             logit_opacity.contiguous(), sh.contiguous(), deg, 1, 1)
-        img = rc.forward(g).clone()
-        ctx.rc, ctx.g = rc, g
-        return img
+        img = rc.forward(g)
+        ctx.rc, ctx.g, ctx.gen = rc, g, rc.gen
+        # an alias of the context's image buffer (no copy), valid until the
+        # context's next forward
+        return img.detach()
 
     @staticmethod
     def backward(ctx, dimage):
+        if ctx.gen != ctx.rc.gen:
+            raise RuntimeError("this RasterContext ran another forward before this backward; its buffers hold the "
+                               "later render (use one RasterContext per render that is back-propagated)")
         g = ctx.g
         grads = GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.quats), torch.empty_like(g.scales),
                                 torch.empty_like(g.opacity), torch.empty_like(g.sh), g.sh_degree, 1, 1)
@@ -116,7 +157,15 @@ class L1Loss(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gl):
         (grad,) = ctx.saved_tensors
-        return grad * gl, None
+        return _chain(grad, gl), None
+
+
+def _chain(grad, gl):
+    """grad * gl with gl a device scalar (tg_scale_by; no host read)."""
+    out = torch.empty_like(grad)
+    gl = gl.reshape(1).to(torch.float32).contiguous()
+    check("tg_scale_by", lib().tg_scale_by(_ptr(out), _ptr(grad), grad.numel(), _ptr(gl), stream_ptr()))
+    return out
 
 
 class Loss3DGS(torch.autograd.Function):
@@ -145,13 +194,17 @@ class Loss3DGS(torch.autograd.Function):
                                                            ctypes.c_float(-lam / max(n, 1)), _ptr(grad),
                                                            _ptr(sums[1:]), _ptr(ws), ctypes.byref(wsb), st))
         ctx.save_for_backward(grad)
-        # sums = [(1 - lam) L1, sum of the SSIM map]
-        return sums[0] + lam * (1 - sums[1] / max(n, 1))
+        # sums = [(1 - lam) L1, sum of the SSIM map]; the objective is
+        # sums[0] + lam - (lam / n) sums[1]
+        loss = torch.empty(1, dtype=torch.float32, device=image.device)
+        w = (ctypes.c_float * 2)(1.0, -lam / max(n, 1))
+        check("tg_scalar_affine", lib().tg_scalar_affine(_ptr(loss), _ptr(sums), 2, w, ctypes.c_float(lam), st))
+        return loss[0]
 
     @staticmethod
     def backward(ctx, gl):
         (grad,) = ctx.saved_tensors
-        return grad * gl, None, None
+        return _chain(grad, gl), None, None
 
 
 def rasterize(means, quats, log_scales, logit_opacity, sh, rc):

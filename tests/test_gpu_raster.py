@@ -223,3 +223,50 @@ def test_full_size_sampled_pixels():
     torch.cuda.synchronize()
     for name, a, b in zip(["means", "quats", "log_scales", "logit_opacity", "sh"], gp, rp):
         _grad_compare(a.grad, b.grad, name)
+
+
+def test_backward_needs_its_own_forward():
+    """The context's buffers hold the latest render: a backward after another
+    forward through the same context raises instead of returning the later
+    render's gradient."""
+    from paper_2604_02586_amd.raster import L1Loss, RasterContext, rasterize
+    p, cams = _case("refine_fd", n=300, views=2, width=48, height=40, seed=23)
+    rc = RasterContext(cams, p["means"].shape[0])
+    gp = _gpu_params(p)
+    img1 = rasterize(*gp, rc)
+    loss1 = L1Loss.apply(img1, torch.zeros_like(img1))
+    img2 = rasterize(*gp, rc)
+    loss2 = L1Loss.apply(img2, torch.zeros_like(img2))
+    with pytest.raises(RuntimeError):
+        loss1.backward(retain_graph=True)
+    loss2.backward()
+    assert all(t.grad is not None and torch.isfinite(t.grad).all() for t in gp)
+
+
+def test_chain_rule_helpers():
+    """tg_scale_by (an upstream gradient read on the device) and
+    tg_scalar_affine (the objective assembled from the loss kernels' sums)."""
+    import ctypes
+
+    from paper_2604_02586_amd import _lib
+    from paper_2604_02586_amd.raster import L1Loss, _chain
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn(100003, device="cuda", generator=g)
+    f = torch.tensor([0.37], device="cuda")
+    out = _chain(x, f)
+    torch.cuda.synchronize()
+    # one FP32 product per element: identical to the same product on the host
+    np.testing.assert_array_equal(out.cpu().numpy(), x.cpu().numpy() * np.float32(0.37))
+    s = torch.tensor([1.5, -2.25, 4.0], device="cuda")
+    o = torch.empty(1, device="cuda")
+    w = (ctypes.c_float * 3)(0.5, 2.0, -0.125)
+    _lib.check("tg_scalar_affine", _lib.lib().tg_scalar_affine(o.data_ptr(), s.data_ptr(), 3, w, ctypes.c_float(0.75),
+                                                               None))
+    torch.cuda.synchronize()
+    assert float(o.item()) == 0.75 + 0.75 - 4.5 - 0.5
+    # the L1 gradient scaled by a non-unit upstream gradient
+    img = torch.rand(2, 8, 8, 3, device="cuda", requires_grad=True)
+    tgt = torch.rand(2, 8, 8, 3, device="cuda")
+    (3.0 * L1Loss.apply(img, tgt)).backward()
+    expect = 3.0 * torch.sign(img.detach() - tgt) / img.numel()
+    torch.testing.assert_close(img.grad, expect, rtol=1e-6, atol=0)
