@@ -63,22 +63,64 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t* ws
     return before + inc - x;
 }
 
-// Count pass: gathers each rank's tile rectangle (the one random access of
-// the emission), stores its coarse rectangle in rank order for the write
-// pass, and records the block's pair count -- or, for the direct placement
-// (HIST), the block's pair count per coarse bin of its view, as the column
-// hist[bin][block] of a bin-major matrix.
-template <bool HIST>
+// Coarse rectangles of every (view, Gaussian) packed in 16 bits (x0, x1 - 1,
+// y0, y1 - 1 in 4 bits each; 0x0001 when empty), for views of at most 16 x 16
+// coarse bins: 2 MB per view at 1M Gaussians, small enough for the count
+// pass's random gathers to stay in one XCD's L2 (8-byte tile rectangles are
+// 8 MB per view).
+constexpr uint16_t CRECT_EMPTY = 0x0001;
+
+__global__ void __launch_bounds__(256) k_pack_crect(const ushort4* __restrict__ rect, int64_t VN, int cshift,
+                                                    uint16_t* __restrict__ crect)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < VN; i += (int64_t)gridDim.x * 256) {
+        const ushort4 r = rect[i];
+        uint16_t p = CRECT_EMPTY;
+        if (r.z > r.x && r.w > r.y)
+            p = (uint16_t)((r.x >> cshift) | (((r.z - 1) >> cshift) << 4) | ((r.y >> cshift) << 8) |
+                           (((r.w - 1) >> cshift) << 12));
+        crect[i] = p;
+    }
+}
+
+__device__ __forceinline__ ushort4 unpack_crect(uint16_t p, uint32_t& cnt) {
+    const unsigned x0 = p & 15u, x1 = (p >> 4) & 15u, y0 = (p >> 8) & 15u, y1 = (p >> 12) & 15u;
+    if (x0 > x1) return make_ushort4(0, 0, 0, 0);   // empty
+    cnt += (x1 + 1 - x0) * (y1 + 1 - y0);
+    return make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)(x1 + 1), (unsigned short)(y1 + 1));
+}
+
+// Count pass: gathers each rank's coarse rectangle (the one random access of
+// the emission), stores it in rank order for the write pass, and records the
+// block's pair count -- or, for the direct placement (HIST), the block's pair
+// count per coarse bin of its view, as the column hist[bin][block] of a
+// bin-major matrix.  PACKED: the rectangles come from the 16-bit packed array
+// and the blocks are remapped so that each XCD takes a contiguous range of
+// views (launched as one dimension of nblk x V blocks, rounded up to 8).
+template <bool HIST, bool PACKED>
 __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__ order, const ushort4* __restrict__ rect,
-                                                    int64_t N, int cshift, int nblk, GridPack gp,
-                                                    ushort4* __restrict__ crs, uint32_t* __restrict__ counts,
+                                                    const uint16_t* __restrict__ crect, int64_t N, int V,
+                                                    int cshift, int nblk, GridPack gp, ushort4* __restrict__ crs,
+                                                    uint32_t* __restrict__ counts,
                                                     unsigned long long* __restrict__ n_pairs)
 {
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t hist[HIST ? DIRECT_BINS : 1];
-    const int v = blockIdx.y, t = threadIdx.x;
+    int v, blk;
+    if (PACKED) {
+        const int64_t b = blockIdx.x;
+        const int64_t per_xcd = (int64_t)gridDim.x >> 3;
+        const int64_t Lb = (b & 7) * per_xcd + (b >> 3);
+        if (Lb >= (int64_t)nblk * V) return;   // block-uniform
+        v = (int)(Lb / nblk);
+        blk = (int)(Lb - (int64_t)v * nblk);
+    } else {
+        v = blockIdx.y;
+        blk = blockIdx.x;
+    }
+    const int t = threadIdx.x;
     const int64_t vN = (int64_t)v * N;
-    const int64_t base = (int64_t)blockIdx.x * EMIT_RANKS + t;
+    const int64_t base = (int64_t)blk * EMIT_RANKS + t;
     const int cw = gp.cx[v], nbv = gp.cx[v] * gp.cy[v];
     if (HIST) {
         for (int c = t; c < nbv; c += 256) hist[c] = 0;
@@ -89,7 +131,12 @@ __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__
     for (int i = 0; i < EMIT_ITEMS; ++i) {
         const int64_t k = base + i * 256;
         if (k < N) {
-            const ushort4 c = coarse_rect(rect, vN, order[vN + k], N, cshift, cnt);
+            const uint32_t g = order[vN + k];
+            ushort4 c;
+            if (PACKED)
+                c = g < (uint64_t)N ? unpack_crect(crect[vN + g], cnt) : make_ushort4(0, 0, 0, 0);
+            else
+                c = coarse_rect(rect, vN, g, N, cshift, cnt);
             crs[vN + k] = c;
             if (HIST)
                 for (int y = c.y; y < c.w; ++y)
@@ -100,9 +147,9 @@ __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__
     (void)block_excl_scan_u32(cnt, wsum, total);
     if (HIST) {
         for (int c = t; c < nbv; c += 256)
-            counts[(int64_t)(gp.cell_off[v] + c) * nblk + blockIdx.x] = hist[c];
+            counts[(int64_t)(gp.cell_off[v] + c) * nblk + blk] = hist[c];
     } else if (t == 0) {
-        counts[(int64_t)v * nblk + blockIdx.x] = total;
+        counts[(int64_t)v * nblk + blk] = total;
     }
     if (t == 0 && total) atomicAdd(n_pairs, (unsigned long long)total);
 }
@@ -494,9 +541,28 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
         // direct placement: per-(bin, block) counts, one scan, then each
         // block sorts its pairs by bin in LDS and writes the final lists
         uint32_t* mat = L.pk_a;   // [ncell][nblk], free on this path
-        hipLaunchKernelGGL(k_emit_count<true>, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order,
-                           (const ushort4*)sp->rect, N, bp.cshift, nblk, bp.gp, crs, mat,
-                           (unsigned long long*)bins->n_pairs);
+        int max_cx = 0, max_cy = 0;
+        for (int v = 0; v < V; ++v) {
+            max_cx = std::max(max_cx, bp.gp.cx[v]);
+            max_cy = std::max(max_cy, bp.gp.cy[v]);
+        }
+        if (max_cx <= 16 && max_cy <= 16) {
+            // packed coarse rectangles in the depth sort's second ping-pong
+            // pair (free after the sort; 2 B of its 8 B per (view, Gaussian))
+            uint16_t* crect = (uint16_t*)L.dk_b;
+            const int64_t VN = (int64_t)V * N;
+            const int64_t pgrid = std::min<int64_t>((VN + 255) / 256, 65536);
+            hipLaunchKernelGGL(k_pack_crect, dim3((unsigned)pgrid), dim3(256), 0, s, (const ushort4*)sp->rect, VN,
+                               bp.cshift, crect);
+            const int64_t per_xcd = ((int64_t)nblk * V + 7) / 8;
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_count<true, true>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0,
+                               s, bins->order, (const ushort4*)sp->rect, (const uint16_t*)crect, N, V, bp.cshift,
+                               nblk, bp.gp, crs, mat, (unsigned long long*)bins->n_pairs);
+        } else {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_count<true, false>), dim3((unsigned)nblk, V), dim3(256), 0, s,
+                               bins->order, (const ushort4*)sp->rect, (const uint16_t*)nullptr, N, V, bp.cshift,
+                               nblk, bp.gp, crs, mat, (unsigned long long*)bins->n_pairs);
+        }
         hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,
                            bins->capacity, bins->overflow);
         // with no overflow the total fits the capacity (< 2^32): u32 offsets
@@ -510,9 +576,9 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
     }
     // general path: keys (coarse bin | Gaussian id) written in rank order,
     // then a stable radix sort over the bin bits
-    hipLaunchKernelGGL(k_emit_count<false>, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order,
-                       (const ushort4*)sp->rect, N, bp.cshift, nblk, bp.gp, crs, L.counts,
-                       (unsigned long long*)bins->n_pairs);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_count<false, false>), dim3((unsigned)nblk, V), dim3(256), 0, s,
+                       bins->order, (const ushort4*)sp->rect, (const uint16_t*)nullptr, N, V, bp.cshift, nblk, bp.gp,
+                       crs, L.counts, (unsigned long long*)bins->n_pairs);
     hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,
                        bins->capacity, bins->overflow);
     // with no overflow the total fits the capacity (< 2^32), so u32 offsets
@@ -612,7 +678,7 @@ extern "C" tg_status tg_bin_expand(const tg_splats* sp, const tg_bins* bins, int
     hipLaunchKernelGGL(k_expand, dim3((unsigned)T), dim3(64), 0, s, (const ushort4*)sp->rect, bins->cell_ids,
                        (const uint2*)bins->cell_ranges, bins->overflow, N, V, bp.gp, bp.cshift, counts, nullptr,
                        nullptr, (int64_t)0, 0);
-    hipMemcpyAsync(starts, counts, (size_t)T * 4, hipMemcpyDeviceToDevice, s);
+    if (hipMemcpyAsync(starts, counts, (size_t)T * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return TG_ERR_DEVICE;
     tg_exclusive_scan_u32(starts, T, scr, s);
     hipLaunchKernelGGL(k_ranges_from_starts, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, starts, counts, T,
                        (uint2*)tile_ranges, capacity, n_out);

@@ -44,40 +44,165 @@ __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t d, bool active) {
     }
 }
 
-template <bool FEW>
+// Whether the last pass of an LSD sort is the identity for a segment, from
+// what the first histogram pass gathered (seginfo[4 seg + 0..3]: AND, OR and
+// the largest lower bits -- the bits below the top digit within the sorted
+// range -- of the keys that are not all ones, and how many keys are all
+// ones, the "culled" sentinel of depth keys).  The last pass sorts by the top
+// digit alone, after the earlier passes have sorted by the lower bits (stable
+// throughout).  It changes nothing when every ordinary key has one top digit
+// d and the sentinels either share it or follow every ordinary key already:
+// their lower bits are all ones, so that holds when no ordinary key's lower
+// bits are all ones too.
+__device__ __forceinline__ bool top_constant(const uint32_t* __restrict__ seginfo, int seg, int bit0,
+                                             int top_shift) {
+    const uint32_t kand = seginfo[4 * seg], kor = seginfo[4 * seg + 1];
+    const uint32_t maxlow = seginfo[4 * seg + 2], nsent = seginfo[4 * seg + 3];
+    if (kand > kor) return true;                         // no ordinary key: all keys equal
+    if ((((kand ^ kor) >> top_shift) & 255u) != 0u) return false;
+    if (nsent == 0u) return true;
+    const uint32_t d = (kor >> top_shift) & 255u, ds = (0xFFFFFFFFu >> top_shift) & 255u;
+    const uint32_t lowmask = (1u << (top_shift - bit0)) - 1u;
+    return d == ds || maxlow < lowmask;
+}
+
+constexpr int MODE_ANDOR = 1;     // first pass: AND/OR of the keys into seginfo
+constexpr int MODE_SKIP = 2;      // last pass: nothing to do when the top digit is constant
+constexpr int MODE_REDIRECT = 4;  // pass before the last: write the final outputs when it is
+
+// Combines the per-block summaries of the first pass (four words per block:
+// AND, OR, largest low part, sentinel count) into the segment's summary.
+// One block per segment; plain stores from every block and one reduction
+// here, since one-word global atomics from thousands of blocks on the same
+// few cache lines serialise.
+__global__ void __launch_bounds__(256) k_seginfo_reduce(const uint32_t* __restrict__ part, int nblk,
+                                                        uint32_t* __restrict__ seginfo) {
+    __shared__ uint32_t red[4][256 / TG_WAVE];
+    const int seg = blockIdx.x, t = threadIdx.x, w = t >> 6, l = t & 63;
+    const uint4* pp = (const uint4*)(part + (int64_t)seg * nblk * 4);
+    uint32_t kand = 0xFFFFFFFFu, kor = 0u, kmax = 0u, nsent = 0u;
+    for (int b = t; b < nblk; b += 256) {
+        const uint4 v = pp[b];
+        kand &= v.x;
+        kor |= v.y;
+        kmax = max(kmax, v.z);
+        nsent += v.w;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        kand &= (uint32_t)__shfl_xor((int)kand, o, 64);
+        kor |= (uint32_t)__shfl_xor((int)kor, o, 64);
+        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o, 64));
+        nsent += (uint32_t)__shfl_xor((int)nsent, o, 64);
+    }
+    if (l == 0) {
+        red[0][w] = kand;
+        red[1][w] = kor;
+        red[2][w] = kmax;
+        red[3][w] = nsent;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int i = 1; i < 256 / TG_WAVE; ++i) {
+            kand &= red[0][i];
+            kor |= red[1][i];
+            kmax = max(kmax, red[2][i]);
+            nsent += red[3][i];
+        }
+        seginfo[4 * seg] = kand;
+        seginfo[4 * seg + 1] = kor;
+        seginfo[4 * seg + 2] = kmax;
+        seginfo[4 * seg + 3] = nsent;
+    }
+}
+
+// Folds one key into the per-thread summary of ordinary keys and sentinels.
+__device__ __forceinline__ void summary_add(uint32_t k, int bit0, uint32_t lowmask, uint32_t& kand, uint32_t& kor,
+                                            uint32_t& kmax, uint32_t& nsent) {
+    // selects, not branches: the sentinel (all ones) is the identity of AND
+    const bool sent = k == 0xFFFFFFFFu;
+    kand &= k;
+    kor |= sent ? 0u : k;
+    kmax = max(kmax, sent ? 0u : (k >> bit0) & lowmask);
+    nsent += sent ? 1u : 0u;
+}
+
+template <bool FEW, bool SUM>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __restrict__ keys, int64_t seg_len,
                                                              const int64_t* __restrict__ dev_count, int shift,
-                                                             uint32_t* __restrict__ ghist, int nblk)
+                                                             uint32_t* __restrict__ ghist, int nblk,
+                                                             uint32_t* __restrict__ seginfo, int mode, int bit0,
+                                                             int top_shift)
 {
     // one sub-histogram per wave (fewer LDS atomic collisions), keys loaded
-    // as uint4 where the block's range is whole and aligned
+    // as uint4 where the block's range is whole and aligned.  With SUM,
+    // seginfo is the [nseg][nblk] array of per-block summaries (uint4 each)
     __shared__ uint32_t h[SORT_WAVES][256];
+    __shared__ uint32_t bsum[4];
     const int seg = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+    if ((mode & MODE_SKIP) && top_constant(seginfo, seg, bit0, top_shift)) return;   // block-uniform
     const int w = t >> 6, l = t & 63;
     for (int i = t; i < SORT_WAVES * 256; i += SORT_THREADS) (&h[0][0])[i] = 0;
+    if (t == 0) {
+        bsum[0] = 0xFFFFFFFFu;
+        bsum[1] = bsum[2] = bsum[3] = 0u;
+    }
     __syncthreads();
     const int64_t n = seg_count(seg_len, dev_count);
     const int64_t base = (int64_t)b * SORT_TILE;
     const uint32_t* kp = keys + (int64_t)seg * seg_len;
+    const uint32_t lowmask = (1u << (top_shift - bit0)) - 1u;
+    uint32_t kand = 0xFFFFFFFFu, kor = 0u, kmax = 0u, nsent = 0u;
     if (base + SORT_TILE <= n && (((uintptr_t)(kp + base)) & 15u) == 0) {
         const uint4* k4 = (const uint4*)(kp + base);
+        uint4 kk[SORT_ITEMS / 4];   // every load in flight before the first use
+#pragma unroll
+        for (int r = 0; r < SORT_ITEMS / 4; ++r) kk[r] = k4[r * SORT_THREADS + t];
 #pragma unroll
         for (int r = 0; r < SORT_ITEMS / 4; ++r) {
-            const uint4 k = k4[r * SORT_THREADS + t];
+            const uint4 k = kk[r];
             hist_add<FEW>(h[w], (k.x >> shift) & 255u, true);
             hist_add<FEW>(h[w], (k.y >> shift) & 255u, true);
             hist_add<FEW>(h[w], (k.z >> shift) & 255u, true);
             hist_add<FEW>(h[w], (k.w >> shift) & 255u, true);
+            if constexpr (SUM) {
+                summary_add(k.x, bit0, lowmask, kand, kor, kmax, nsent);
+                summary_add(k.y, bit0, lowmask, kand, kor, kmax, nsent);
+                summary_add(k.z, bit0, lowmask, kand, kor, kmax, nsent);
+                summary_add(k.w, bit0, lowmask, kand, kor, kmax, nsent);
+            }
         }
     } else if (base < n) {
 #pragma unroll 4
         for (int r = 0; r < SORT_ITEMS; ++r) {
             int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
             const bool in = idx < n;
-            hist_add<FEW>(h[w], in ? (kp[idx] >> shift) & 255u : 0u, in);
+            const uint32_t k = in ? kp[idx] : 0u;
+            hist_add<FEW>(h[w], in ? (k >> shift) & 255u : 0u, in);
+            if (SUM && in) summary_add(k, bit0, lowmask, kand, kor, kmax, nsent);
+        }
+    }
+    if (SUM) {
+        // across the wave first (butterfly), then across the block's waves;
+        // one plain 16-byte store of the block's summary (identity for a
+        // block past the end of a counted segment)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            kand &= (uint32_t)__shfl_xor((int)kand, o, 64);
+            kor |= (uint32_t)__shfl_xor((int)kor, o, 64);
+            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o, 64));
+            nsent += (uint32_t)__shfl_xor((int)nsent, o, 64);
+        }
+        if (l == 0) {
+            atomicAnd(&bsum[0], kand);
+            atomicOr(&bsum[1], kor);
+            atomicMax(&bsum[2], kmax);
+            atomicAdd(&bsum[3], nsent);
         }
     }
     __syncthreads();
+    if (SUM && t == 0)
+        ((uint4*)seginfo)[(int64_t)seg * nblk + b] = make_uint4(bsum[0], bsum[1], bsum[2], bsum[3]);
     uint32_t c = 0;
 #pragma unroll
     for (int ww = 0; ww < SORT_WAVES; ++ww) c += h[ww][t];
@@ -165,8 +290,17 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(uint32_t* __restrict
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t seg_len, const int64_t* __restrict__ dev_count, int shift,
-    const uint32_t* __restrict__ goff, int nblk)
+    const uint32_t* __restrict__ goff, int nblk, const uint32_t* __restrict__ seginfo, int mode, int bit0,
+    int top_shift, uint32_t* __restrict__ kalt, uint32_t* __restrict__ valt)
 {
+    if (mode & (MODE_SKIP | MODE_REDIRECT)) {
+        // block-uniform: the segment's summary decides
+        if (top_constant(seginfo, blockIdx.y, bit0, top_shift)) {
+            if (mode & MODE_SKIP) return;
+            kout = kalt;
+            vout = valt;
+        }
+    }
     __shared__ uint32_t woff[SORT_WAVES][256];
     __shared__ uint32_t gdelta[256];     // global start of the digit minus its block-local start
     __shared__ uint32_t wtot[SORT_WAVES];
@@ -267,7 +401,8 @@ size_t tg_sort_scratch_bytes(int64_t seg_len, int nseg) {
     int64_t nblk = (seg_len + SORT_TILE - 1) / SORT_TILE;
     int64_t L = 256 * nblk;
     int64_t nchunk = (L + SCAN_TILE - 1) / SCAN_TILE;
-    return (size_t)nseg * (size_t)(L + nchunk + 64) * sizeof(uint32_t);
+    // histograms, scan sums, segment summaries, per-block summaries
+    return ((size_t)nseg * (size_t)(L + nchunk + 64) + 4 * (size_t)nseg * (size_t)nblk + 4) * sizeof(uint32_t);
 }
 
 // Sorts nseg segments of seg_len keys (or one segment of *dev_count keys) by
@@ -284,6 +419,24 @@ tg_status tg_radix_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, 
     const int nchunk = (int)((L + SCAN_TILE - 1) / SCAN_TILE);
     uint32_t* hist = (uint32_t*)scratch;
     uint32_t* sums = hist + (int64_t)nseg * L;
+    // A summary of each segment's keys (first pass): when the last pass is
+    // the identity for a segment (the sign and exponent bits of depth keys
+    // within a factor of two, the high bits of few bins) the pass before it
+    // writes the final outputs and the last pass does nothing for that
+    // segment (decided on the device)
+    uint32_t* seginfo = sums + (int64_t)nseg * nchunk;
+    const int64_t part_off = ((int64_t)nseg * (L + nchunk + 4) + 3) & ~(int64_t)3;   // 16-byte aligned
+    uint32_t* part = hist + part_off;
+    const int top_shift = bit0 + 8 * (passes - 1);
+    bool skip_top = passes >= 2 && top_shift < 32;
+    if (skip_top) {
+        // the redirected pass must not write a buffer it reads
+        const int q = passes - 2;
+        const void* in_k = q == 0 ? (const void*)kin : (((q - 1) & 1) ? (const void*)kb : (const void*)ka);
+        const void* in_v = q == 0 ? (const void*)vin : (((q - 1) & 1) ? (const void*)vb : (const void*)va);
+        for (const void* f : {(const void*)kfinal, (const void*)vfinal})
+            if (f && (f == in_k || f == in_v)) skip_top = false;
+    }
     const uint32_t* ck = kin;
     const uint32_t* cv = vin;
     for (int p = 0; p < passes; ++p) {
@@ -292,19 +445,33 @@ tg_status tg_radix_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, 
         uint32_t* ov = last ? vfinal : ((p & 1) ? vb : va);
         if (!last && !ok) return TG_ERR_INVALID_ARG;
         const int shift = bit0 + 8 * p;
+        int mode = 0;
+        if (skip_top) {
+            if (p == 0) mode |= MODE_ANDOR;
+            if (last) mode |= MODE_SKIP;
+            if (p == passes - 2) mode |= MODE_REDIRECT;
+        }
         // the top digit of a sort (the high exponent bits of depth keys, or
         // the high bits of the bin numbers) takes few distinct values
         if (last)
-            hipLaunchKernelGGL(k_radix_hist<true>, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, seg_len,
-                               dev_count, shift, hist, nblk);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_radix_hist<true, false>), dim3(nblk, nseg), dim3(SORT_THREADS), 0,
+                               s, ck, seg_len, dev_count, shift, hist, nblk, seginfo, mode & MODE_SKIP, bit0,
+                               top_shift);
+        else if (mode & MODE_ANDOR)
+        {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_radix_hist<false, true>), dim3(nblk, nseg), dim3(SORT_THREADS), 0,
+                               s, ck, seg_len, dev_count, shift, hist, nblk, part, mode, bit0, top_shift);
+            hipLaunchKernelGGL(k_seginfo_reduce, dim3(nseg), dim3(256), 0, s, part, nblk, seginfo);
+        }
         else
-            hipLaunchKernelGGL(k_radix_hist<false>, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, seg_len,
-                               dev_count, shift, hist, nblk);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_radix_hist<false, false>), dim3(nblk, nseg), dim3(SORT_THREADS), 0,
+                               s, ck, seg_len, dev_count, shift, hist, nblk, seginfo, 0, bit0, top_shift);
         hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
         hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(SCAN_THREADS), 0, s, sums, nchunk);
         hipLaunchKernelGGL(k_scan_down, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, cv, ok,
-                           (last && !vfinal) ? nullptr : ov, seg_len, dev_count, shift, hist, nblk);
+                           (last && !vfinal) ? nullptr : ov, seg_len, dev_count, shift, hist, nblk, seginfo,
+                           mode & (MODE_SKIP | MODE_REDIRECT), bit0, top_shift, kfinal, vfinal);
         TG_CHECK_LAUNCH();
         ck = ok;
         cv = ov;

@@ -88,3 +88,67 @@ def test_overflow_then_retry():
     mt.bin_sort(check_overflow=True)   # re-sizes from the reported count
     torch.cuda.synchronize()
     assert _check(wl, mt) == need
+
+
+def _axis_cams(W=256, H=192, f=500.0):
+    # identity rotation and no depth offset: the depth key is the bits of mu_z
+    return [synth.Camera(R=np.eye(3, dtype=np.float32), t=np.array([tx, 0.0, 0.0], np.float32), fx=f, fy=f,
+                         cx=(W - 1) / 2, cy=(H - 1) / 2, W=W, H=H) for tx in (0.0, 0.3)]
+
+
+def _axis_scene(rng, zs):
+    n = zs.size
+    u = rng.uniform(-0.15, 0.15, (n, 2)).astype(np.float32)
+    means = np.concatenate([u * zs[:, None], zs[:, None]], 1).astype(np.float32)
+    sc = synth.random_gaussians(rng, n)
+    return synth.Scene(means=means, quats=sc.quats, scales=sc.scales, opacity=sc.opacity, rgb=sc.rgb)
+
+
+DEPTH_CASES = {
+    # one top key byte (0x40) and culled sentinels, no ordinary key whose low
+    # 24 bits are all ones: the last radix pass is skipped
+    "one_top_digit": lambda rng: rng.uniform(4.0, 7.9, 6000),
+    # the same plus depths whose low 24 bits are all ones (7.99999952 =
+    # 0x40FFFFFF), which tie with the sentinel below the top byte: the last
+    # pass must run
+    "tie_with_sentinel": lambda rng: np.concatenate([rng.uniform(4.0, 7.9, 6000),
+                                                     np.full(7, np.float32(7.99999952))]),
+    # two top bytes (0x40, 0x41): the last pass must run
+    "two_top_digits": lambda rng: rng.uniform(4.0, 12.0, 6000),
+}
+
+
+@pytest.mark.parametrize("case", list(DEPTH_CASES))
+def test_depth_order_with_culled_sentinels(case):
+    """Depth keys crafted around the radix sort's skipped last pass: valid
+    keys with one or two top bytes, culled Gaussians (behind the near plane,
+    key 0xFFFFFFFF) mixed in at random indices; the order of the valid ones
+    bit-exact and every culled one after them, by index."""
+    from paper_2604_02586_amd import api
+    rng = np.random.default_rng(61)
+    zs = DEPTH_CASES[case](rng).astype(np.float32)
+    culled = rng.random(zs.size) < 0.1
+    culled[6000:] = False              # the crafted depths stay valid
+    zs[culled] = np.float32(0.1)
+    perm = rng.permutation(zs.size)
+    zs, culled = zs[perm], culled[perm]
+    scene = _axis_scene(rng, zs)
+    cams = _axis_cams()
+    wl = synth.Workload(name=case, scene=scene, cams=cams, motion=None,
+                        disp=np.zeros((2, 192, 256, 2), np.float32), vis=np.ones((2, 192, 256), np.uint8))
+    dev = torch.device("cuda:0")
+    mt = api.MotionTransfer(cams, scene.n, dev)
+    mt.preprocess(api.GaussianTensors.from_scene(scene, dev))
+    mt.bin_sort()
+    torch.cuda.synchronize()
+    key = mt.splats.key.cpu().numpy().view(np.uint32)
+    if case == "tie_with_sentinel":
+        assert ((key != 0xFFFFFFFF) & ((key & 0xFFFFFF) == 0xFFFFFF)).sum() == 2 * 7
+    geom = oracle.geometry(scene, cams)
+    order = mt.bins.order.cpu().numpy().view(np.uint32)
+    for v, o in enumerate(oracle.depth_order(geom)):
+        np.testing.assert_array_equal(order[v, :o.size], o)
+        tail = np.nonzero(~geom.valid[v].astype(bool))[0].astype(np.uint32)
+        np.testing.assert_array_equal(order[v, o.size:], tail)
+    log(f"[{case}] {int(culled.sum())} culled; depth order bit-exact")
+    _check(wl, mt)
