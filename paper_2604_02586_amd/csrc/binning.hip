@@ -70,16 +70,35 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t* ws
 // 8 MB per view).
 constexpr uint16_t CRECT_EMPTY = 0x0001;
 
+__device__ __forceinline__ uint32_t pack_crect(uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1, int cshift) {
+    if (!(x1 > x0 && y1 > y0)) return CRECT_EMPTY;
+    return (x0 >> cshift) | (((x1 - 1) >> cshift) << 4) | ((y0 >> cshift) << 8) | (((y1 - 1) >> cshift) << 12);
+}
+
+// VEC: four rectangles (two 16-byte loads) to one 8-byte store per thread
+// (rect 16-byte aligned); the scalar form handles the rest.
+template <bool VEC>
 __global__ void __launch_bounds__(256) k_pack_crect(const ushort4* __restrict__ rect, int64_t VN, int cshift,
                                                     uint16_t* __restrict__ crect)
 {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < VN; i += (int64_t)gridDim.x * 256) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i0 = 0;
+    if (VEC) {
+        const int64_t nq = VN >> 2;
+        const uint4* r4 = (const uint4*)rect;
+        for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nq; q += stride) {
+            const uint4 a = r4[2 * q], b = r4[2 * q + 1];
+            const uint32_t p0 = pack_crect(a.x & 0xFFFFu, a.x >> 16, a.y & 0xFFFFu, a.y >> 16, cshift);
+            const uint32_t p1 = pack_crect(a.z & 0xFFFFu, a.z >> 16, a.w & 0xFFFFu, a.w >> 16, cshift);
+            const uint32_t p2 = pack_crect(b.x & 0xFFFFu, b.x >> 16, b.y & 0xFFFFu, b.y >> 16, cshift);
+            const uint32_t p3 = pack_crect(b.z & 0xFFFFu, b.z >> 16, b.w & 0xFFFFu, b.w >> 16, cshift);
+            ((uint2*)crect)[q] = make_uint2(p0 | (p1 << 16), p2 | (p3 << 16));
+        }
+        i0 = nq << 2;
+    }
+    for (int64_t i = i0 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < VN; i += stride) {
         const ushort4 r = rect[i];
-        uint16_t p = CRECT_EMPTY;
-        if (r.z > r.x && r.w > r.y)
-            p = (uint16_t)((r.x >> cshift) | (((r.z - 1) >> cshift) << 4) | ((r.y >> cshift) << 8) |
-                           (((r.w - 1) >> cshift) << 12));
-        crect[i] = p;
+        crect[i] = (uint16_t)pack_crect(r.x, r.y, r.z, r.w, cshift);
     }
 }
 
@@ -91,7 +110,8 @@ __device__ __forceinline__ ushort4 unpack_crect(uint16_t p, uint32_t& cnt) {
 }
 
 // Count pass: gathers each rank's coarse rectangle (the one random access of
-// the emission), stores it in rank order for the write pass, and records the
+// the emission), stores it in rank order for the write pass (unless PACKED:
+// the placement then gathers the 2-byte form again from L2), and records the
 // block's pair count -- or, for the direct placement (HIST), the block's pair
 // count per coarse bin of its view, as the column hist[bin][block] of a
 // bin-major matrix.  PACKED: the rectangles come from the 16-bit packed array
@@ -127,20 +147,33 @@ __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__
         __syncthreads();
     }
     uint32_t cnt = 0;
+    if (PACKED) {
+        // every id, then every gather, in flight before the first use
+        uint32_t g[EMIT_ITEMS];
+        uint16_t pk[EMIT_ITEMS];
 #pragma unroll
-    for (int i = 0; i < EMIT_ITEMS; ++i) {
-        const int64_t k = base + i * 256;
-        if (k < N) {
-            const uint32_t g = order[vN + k];
-            ushort4 c;
-            if (PACKED)
-                c = g < (uint64_t)N ? unpack_crect(crect[vN + g], cnt) : make_ushort4(0, 0, 0, 0);
-            else
-                c = coarse_rect(rect, vN, g, N, cshift, cnt);
-            crs[vN + k] = c;
+        for (int i = 0; i < EMIT_ITEMS; ++i) g[i] = base + i * 256 < N ? order[vN + base + i * 256] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) pk[i] = g[i] < (uint64_t)N ? crect[vN + g[i]] : CRECT_EMPTY;
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) {
+            const ushort4 c = unpack_crect(pk[i], cnt);
             if (HIST)
                 for (int y = c.y; y < c.w; ++y)
                     for (int x = c.x; x < c.z; ++x) atomicAdd(&hist[y * cw + x], 1u);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) {
+            const int64_t k = base + i * 256;
+            if (k < N) {
+                const uint32_t g = order[vN + k];
+                const ushort4 c = coarse_rect(rect, vN, g, N, cshift, cnt);
+                crs[vN + k] = c;
+                if (HIST)
+                    for (int y = c.y; y < c.w; ++y)
+                        for (int x = c.x; x < c.z; ++x) atomicAdd(&hist[y * cw + x], 1u);
+            }
         }
     }
     uint32_t total;
@@ -162,14 +195,15 @@ __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__
 // pair keys.  Within a window, wave w ranks items [w*1024, w*1024+1024) in
 // rounds of 64 consecutive items by ballot matching on the bin (stable), the
 // window is placed bin-major in LDS and then written out as contiguous runs.
+template <bool PACKED>
 __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__ order, const ushort4* __restrict__ crs,
-                                                    int64_t N, GridPack gp, int nblk,
-                                                    const uint32_t* __restrict__ offsets,
+                                                    const uint16_t* __restrict__ crect, int64_t N, int V, GridPack gp,
+                                                    int nblk, const uint32_t* __restrict__ offsets,
                                                     uint32_t* __restrict__ cell_ids,
                                                     const int32_t* __restrict__ overflow)
 {
     // 24 KB: the rank-major transpose of ids and rectangles, then the
-    // window's ids (16 KB) and bins (4 KB)
+    // window's ids (8 KB) and bins (2 KB)
     __shared__ uint4 lds[EMIT_RANKS * 12 / 16];
     __shared__ uint32_t sid[DIRECT_WIN];        // window sorted by bin
     __shared__ uint8_t sbin[DIRECT_WIN];
@@ -178,21 +212,35 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
     __shared__ uint32_t gofs[DIRECT_BINS];      // global position minus window position, per bin
     __shared__ uint32_t wsum[4];
     if (*overflow) return;   // block-uniform: the caller re-sizes and retries
-    const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, lane = t & 63;
+    int v, blk;
+    if (PACKED) {
+        // each XCD takes a contiguous range of views (its L2 holds their
+        // packed rectangles), as in the count pass
+        const int64_t b = blockIdx.x;
+        const int64_t per_xcd = (int64_t)gridDim.x >> 3;
+        const int64_t Lb = (b & 7) * per_xcd + (b >> 3);
+        if (Lb >= (int64_t)nblk * V) return;   // block-uniform
+        v = (int)(Lb / nblk);
+        blk = (int)(Lb - (int64_t)v * nblk);
+    } else {
+        v = blockIdx.y;
+        blk = blockIdx.x;
+    }
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int64_t vN = (int64_t)v * N;
-    const int64_t rbase = (int64_t)blockIdx.x * EMIT_RANKS;
+    const int64_t rbase = (int64_t)blk * EMIT_RANKS;
     uint32_t* sg = (uint32_t*)lds;
     ushort4* sc = (ushort4*)(lds + EMIT_RANKS / 4);
 #pragma unroll
     for (int i = 0; i < EMIT_ITEMS; ++i) {
         const int j = i * 256 + t;
         const bool in = rbase + j < N;
-        sg[j] = in ? order[vN + rbase + j] : 0u;
-        sc[j] = in ? crs[vN + rbase + j] : make_ushort4(0, 0, 0, 0);
+        sg[j] = in ? order[vN + rbase + j] : 0xFFFFFFFFu;
+        if (!PACKED) sc[j] = in ? crs[vN + rbase + j] : make_ushort4(0, 0, 0, 0);
     }
     const int cw = gp.cx[v], nbv = gp.cx[v] * gp.cy[v];
     for (int c = t; c < nbv; c += 256)
-        boff[c] = offsets[(int64_t)(gp.cell_off[v] + c) * nblk + blockIdx.x];
+        boff[c] = offsets[(int64_t)(gp.cell_off[v] + c) * nblk + blk];
     __syncthreads();
     uint32_t gid[EMIT_ITEMS];
     ushort4 cr[EMIT_ITEMS];
@@ -202,19 +250,101 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
         gid[4] = b.x; gid[5] = b.y; gid[6] = b.z; gid[7] = b.w;
     }
     uint32_t mine = 0;
+    uint16_t pkr[EMIT_ITEMS];
+    if (PACKED) {
+        // ranks past the end and out-of-range ids hold no pairs
 #pragma unroll
-    for (int i = 0; i < EMIT_ITEMS; ++i) {
-        cr[i] = sc[EMIT_ITEMS * t + i];
-        mine += (uint32_t)((cr[i].z - cr[i].x) * (cr[i].w - cr[i].y));
+        for (int i = 0; i < EMIT_ITEMS; ++i) pkr[i] = gid[i] < (uint64_t)N ? crect[vN + gid[i]] : CRECT_EMPTY;
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) cr[i] = unpack_crect(pkr[i], mine);
+    } else {
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) {
+            cr[i] = sc[EMIT_ITEMS * t + i];
+            mine += (uint32_t)((cr[i].z - cr[i].x) * (cr[i].w - cr[i].y));
+        }
     }
     uint32_t total;
     const uint32_t before = block_excl_scan_u32(mine, wsum, total);
-    uint32_t* wid = (uint32_t*)lds;                          // [DIRECT_WIN]
-    uint8_t* wbin = (uint8_t*)(lds + DIRECT_WIN / 4);        // [DIRECT_WIN]
+    // PACKED keeps the ids and packed rectangles of every rank, and each
+    // thread's first pair, in LDS for the balanced expansion below:
+    // [0, 8 KB) ids by rank, [8, 12) rectangles by rank, [12, 13) starts,
+    // then the window (ids 8 KB, bins 2 KB).  Otherwise the window reuses
+    // the transpose area.
+    constexpr int P_PK = EMIT_RANKS / 4, P_TST = P_PK + EMIT_RANKS / 8, P_WID = P_TST + 256 / 4;
+    constexpr int P_WBIN = P_WID + DIRECT_WIN / 4;
+    static_assert(P_WBIN + DIRECT_WIN / 16 <= EMIT_RANKS * 12 / 16, "LDS layout of the packed placement");
+    uint16_t* pkl = (uint16_t*)(lds + P_PK);
+    uint32_t* tst = (uint32_t*)(lds + P_TST);
+    uint32_t* wid = PACKED ? (uint32_t*)(lds + P_WID) : (uint32_t*)lds;               // [DIRECT_WIN]
+    uint8_t* wbin = PACKED ? (uint8_t*)(lds + P_WBIN) : (uint8_t*)(lds + DIRECT_WIN / 4);   // [DIRECT_WIN]
+    if (PACKED) {
+        // (the ids by rank in sg stay where the load phase put them)
+        const uint4 pv = make_uint4(pkr[0] | ((uint32_t)pkr[1] << 16), pkr[2] | ((uint32_t)pkr[3] << 16),
+                                    pkr[4] | ((uint32_t)pkr[5] << 16), pkr[6] | ((uint32_t)pkr[7] << 16));
+        ((uint4*)pkl)[t] = pv;
+        tst[t] = before;
+    }
     const uint64_t lt = lanemask_lt();
     for (uint32_t w0 = 0; w0 < total; w0 += DIRECT_WIN) {
-        __syncthreads();   // registers hold this thread's data; LDS is free
-        {
+        __syncthreads();   // the previous window's LDS is free
+        if (PACKED) {
+            // Balanced expansion: thread t writes window pairs [8t, 8t + 8)
+            // (pair order = rank order, then bin rows, then columns): find
+            // the owning thread (the last whose first pair is <= p0; equal
+            // starts belong to threads with no pairs before it), walk its
+            // ranks to the pair, then step through pairs and ranks.  Every
+            // lane does the same few steps, instead of each lane looping
+            // over its own rectangles (as long as the largest of the wave).
+            const uint32_t lim = total - w0 < DIRECT_WIN ? total - w0 : DIRECT_WIN;
+            const uint32_t q0 = (uint32_t)t * (DIRECT_WIN / 256);
+            if (q0 < lim) {
+                const uint32_t p0 = w0 + q0;
+                int lo = 0;
+#pragma unroll
+                for (int step = 128; step > 0; step >>= 1)
+                    if (tst[lo + step] <= p0) lo += step;
+                int r = lo * EMIT_ITEMS;
+                uint32_t off = p0 - tst[lo];
+                uint32_t pk = pkl[r];
+                uint32_t np = 0;
+                unpack_crect((uint16_t)pk, np);
+                while (off >= np) {   // ends inside the owner's ranks
+                    off -= np;
+                    pk = pkl[++r];
+                    np = 0;
+                    unpack_crect((uint16_t)pk, np);
+                }
+                uint32_t x0 = pk & 15u, x1 = (pk >> 4) & 15u, y1 = (pk >> 12) & 15u;
+                const uint32_t wdt = x1 + 1 - x0;
+                // off < 256 and wdt <= 16: the reciprocal's error cannot
+                // cross an integer ((off + 1/2) / wdt is >= 1/32 away from one)
+                uint32_t dy = (uint32_t)(((float)off + 0.5f) * __builtin_amdgcn_rcpf((float)wdt));
+                uint32_t x = x0 + (off - dy * wdt), y = ((pk >> 8) & 15u) + dy;
+                uint32_t gcur = sg[r];
+                const uint32_t qn = lim - q0 < (uint32_t)(DIRECT_WIN / 256) ? lim - q0 : (uint32_t)(DIRECT_WIN / 256);
+                for (uint32_t j = 0; j < qn; ++j) {
+                    wid[q0 + j] = gcur;
+                    wbin[q0 + j] = (uint8_t)(y * cw + x);
+                    if (j + 1 == qn) break;
+                    if (++x > x1) {
+                        x = x0;
+                        if (++y > y1) {
+                            // next rank with pairs (one exists: more pairs follow)
+                            do {
+                                pk = pkl[++r];
+                            } while ((pk & 15u) > ((pk >> 4) & 15u));
+                            x0 = pk & 15u;
+                            x1 = (pk >> 4) & 15u;
+                            y1 = (pk >> 12) & 15u;
+                            x = x0;
+                            y = (pk >> 8) & 15u;
+                            gcur = sg[r];
+                        }
+                    }
+                }
+            }
+        } else {
             uint32_t pidx = before;
 #pragma unroll
             for (int i = 0; i < EMIT_ITEMS; ++i) {
@@ -236,13 +366,7 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
             const uint32_t idx = (uint32_t)(w * (DIRECT_WIN / 4) + r * 64 + lane);
             const bool act = idx < nwin;
             const uint32_t d = act ? wbin[idx] : 0u;
-            uint64_t m = ballot64(act);
-#pragma unroll
-            for (int bit = 0; bit < 8; ++bit) {
-                const bool set = (d >> bit) & 1u;
-                const uint64_t bb = ballot64(act && set);
-                m &= set ? bb : ~bb;
-            }
+            const uint64_t m = match_digit8(d, act);
             const uint32_t rk = (uint32_t)__popcll(m & lt);
             const uint32_t b0 = act ? cnt[w][d] : 0u;
             lrank[r] = b0 + rk;
@@ -541,6 +665,8 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
         // direct placement: per-(bin, block) counts, one scan, then each
         // block sorts its pairs by bin in LDS and writes the final lists
         uint32_t* mat = L.pk_a;   // [ncell][nblk], free on this path
+        uint16_t* crect = nullptr;
+        bool packed = false;
         int max_cx = 0, max_cy = 0;
         for (int v = 0; v < V; ++v) {
             max_cx = std::max(max_cx, bp.gp.cx[v]);
@@ -549,15 +675,21 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
         if (max_cx <= 16 && max_cy <= 16) {
             // packed coarse rectangles in the depth sort's second ping-pong
             // pair (free after the sort; 2 B of its 8 B per (view, Gaussian))
-            uint16_t* crect = (uint16_t*)L.dk_b;
+            crect = (uint16_t*)L.dk_b;
             const int64_t VN = (int64_t)V * N;
-            const int64_t pgrid = std::min<int64_t>((VN + 255) / 256, 65536);
-            hipLaunchKernelGGL(k_pack_crect, dim3((unsigned)pgrid), dim3(256), 0, s, (const ushort4*)sp->rect, VN,
-                               bp.cshift, crect);
+            const bool vec = (((uintptr_t)sp->rect) & 15u) == 0;
+            const int64_t pgrid = std::min<int64_t>(((vec ? VN / 4 : VN) + 255) / 256, 65536);
+            if (vec)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pack_crect<true>), dim3((unsigned)std::max<int64_t>(pgrid, 1)),
+                                   dim3(256), 0, s, (const ushort4*)sp->rect, VN, bp.cshift, crect);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pack_crect<false>), dim3((unsigned)pgrid), dim3(256), 0, s,
+                                   (const ushort4*)sp->rect, VN, bp.cshift, crect);
             const int64_t per_xcd = ((int64_t)nblk * V + 7) / 8;
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_count<true, true>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0,
                                s, bins->order, (const ushort4*)sp->rect, (const uint16_t*)crect, N, V, bp.cshift,
                                nblk, bp.gp, crs, mat, (unsigned long long*)bins->n_pairs);
+            packed = true;
         } else {
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_count<true, false>), dim3((unsigned)nblk, V), dim3(256), 0, s,
                                bins->order, (const ushort4*)sp->rect, (const uint16_t*)nullptr, N, V, bp.cshift,
@@ -567,8 +699,16 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
                            bins->capacity, bins->overflow);
         // with no overflow the total fits the capacity (< 2^32): u32 offsets
         tg_exclusive_scan_u32(mat, nmat, (uint32_t*)L.scratch, s);
-        hipLaunchKernelGGL(k_emit_place, dim3((unsigned)nblk, V), dim3(256), 0, s, bins->order, (const ushort4*)crs,
-                           N, bp.gp, nblk, mat, bins->cell_ids, bins->overflow);
+        if (packed) {
+            const int64_t per_xcd = ((int64_t)nblk * V + 7) / 8;
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_place<true>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s,
+                               bins->order, (const ushort4*)nullptr, (const uint16_t*)crect, N, V, bp.gp, nblk, mat,
+                               bins->cell_ids, bins->overflow);
+        } else {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_place<false>), dim3((unsigned)nblk, V), dim3(256), 0, s,
+                               bins->order, (const ushort4*)crs, (const uint16_t*)nullptr, N, V, bp.gp, nblk, mat,
+                               bins->cell_ids, bins->overflow);
+        }
         hipLaunchKernelGGL(k_bin_ranges, dim3((unsigned)((bp.ncell + 255) / 256)), dim3(256), 0, s, mat, nblk,
                            bp.ncell, bins->n_pairs, bins->capacity, (uint2*)bins->cell_ranges);
         TG_CHECK_LAUNCH();

@@ -9,11 +9,18 @@
 
 namespace {
 
-constexpr int SORT_THREADS = 256;
+// 8192 keys per block: a digit's run in the scatter's output averages 32
+// keys (128 bytes, one cache line) for uniform digits; 4096-key tiles wrote
+// 64-byte runs that straddle lines, about 1.6x the algorithmic write bytes.
+// The scatter's LDS (64 KB of keys and values) still fits two blocks, 16
+// waves, per CU.
+constexpr int SORT_THREADS = 512;
 constexpr int SORT_ITEMS = 16;
-constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // 4096 keys per block
-constexpr int SORT_WAVES = SORT_THREADS / TG_WAVE;      // 4
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // 8192 keys per block
+constexpr int SORT_WAVES = SORT_THREADS / TG_WAVE;      // 8
 constexpr int WAVE_ITEMS = SORT_TILE / SORT_WAVES;      // 1024 keys per wave
+constexpr int DIGIT_WAVES = 256 / TG_WAVE;              // waves owning one digit per thread
+static_assert(SORT_THREADS >= 256, "one thread per digit");
 
 // Active length of a segment: fixed, or read from the device (single
 // dynamic segment), 0 when the device count exceeds the capacity.
@@ -203,10 +210,12 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __r
     __syncthreads();
     if (SUM && t == 0)
         ((uint4*)seginfo)[(int64_t)seg * nblk + b] = make_uint4(bsum[0], bsum[1], bsum[2], bsum[3]);
-    uint32_t c = 0;
+    if (t < 256) {
+        uint32_t c = 0;
 #pragma unroll
-    for (int ww = 0; ww < SORT_WAVES; ++ww) c += h[ww][t];
-    ghist[((int64_t)seg * 256 + t) * nblk + b] = c;
+        for (int ww = 0; ww < SORT_WAVES; ++ww) c += h[ww][t];
+        ghist[((int64_t)seg * 256 + t) * nblk + b] = c;
+    }
 }
 
 // ---- exclusive scan of a [nseg][L] u32 array (three kernels) ------------
@@ -281,7 +290,7 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(uint32_t* __restrict
 }
 
 // ---- stable scatter --------------------------------------------------------
-// Items of a block: wave w owns keys [w*1024, (w+1)*1024) of the block's 4096,
+// Items of a block: wave w owns keys [w*1024, (w+1)*1024) of the block's 8192,
 // visited in 16 rounds of 64 consecutive keys, so order within the block is
 // (wave, round, lane) = input order.  Each key is first placed at its stable
 // rank inside the block (digit-major) in LDS; the block then writes the LDS
@@ -331,27 +340,33 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
     }
     __syncthreads();
     {
-        // thread t owns digit t: block-local start of the digit (exclusive
-        // scan of the digit totals), then each wave's start inside it
+        // thread t < 256 owns digit t: block-local start of the digit
+        // (exclusive scan of the digit totals), then each wave's start
+        // inside it
         uint32_t c[SORT_WAVES], tot = 0;
+        uint32_t inc = 0;
+        if (t < 256) {
 #pragma unroll
-        for (int ww = 0; ww < SORT_WAVES; ++ww) {
-            c[ww] = woff[ww][t];
-            tot += c[ww];
+            for (int ww = 0; ww < SORT_WAVES; ++ww) {
+                c[ww] = woff[ww][t];
+                tot += c[ww];
+            }
+            inc = wave_scan_add_u32(tot);   // wave-uniform branch: waves 0..3
+            if (l == 63) wtot[w] = inc;
         }
-        const uint32_t inc = wave_scan_add_u32(tot);
-        if (l == 63) wtot[w] = inc;
         __syncthreads();
-        uint32_t start = inc - tot;
+        if (t < 256) {
+            uint32_t start = inc - tot;
 #pragma unroll
-        for (int ww = 0; ww < SORT_WAVES; ++ww)
-            if (ww < w) start += wtot[ww];
-        gdelta[t] = goff[((int64_t)seg * 256 + t) * nblk + b] - start;
-        uint32_t run = start;
+            for (int ww = 0; ww < DIGIT_WAVES; ++ww)
+                if (ww < w) start += wtot[ww];
+            gdelta[t] = goff[((int64_t)seg * 256 + t) * nblk + b] - start;
+            uint32_t run = start;
 #pragma unroll
-        for (int ww = 0; ww < SORT_WAVES; ++ww) {
-            woff[ww][t] = run;
-            run += c[ww];
+            for (int ww = 0; ww < SORT_WAVES; ++ww) {
+                woff[ww][t] = run;
+                run += c[ww];
+            }
         }
     }
     __syncthreads();
@@ -361,13 +376,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
         int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
         bool active = idx < n;
         uint32_t d = (k[r] >> shift) & 255u;
-        uint64_t m = ballot64(active);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            bool set = (d >> bit) & 1u;
-            uint64_t bb = ballot64(active && set);
-            m &= set ? bb : ~bb;
-        }
+        const uint64_t m = match_digit8(d, active);
         if (active) {
             uint32_t rank = (uint32_t)__popcll(m & lt);
             uint32_t pos = woff[w][d] + rank;       // < nvalid for a consistent histogram

@@ -30,6 +30,25 @@ __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u,
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
+// Lanes (among those where act holds) whose 8-bit value d equals this
+// lane's: the stable-rank primitive of the sorts (rank = popcount of the
+// result below this lane).  Eight ballots of the value's bits; each lane
+// keeps the lanes that agree with it on a bit with one XNOR and one AND per
+// mask half (against the bit spread over the word), instead of a per-lane
+// select between a ballot and its complement.
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d, bool act) {
+    const uint64_t a = __ballot(act);
+    uint32_t mlo = (uint32_t)a, mhi = (uint32_t)(a >> 32);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const uint32_t sm = (uint32_t)(((int32_t)(d << (31 - bit))) >> 31);   // all ones where set
+        const uint64_t bb = __ballot(sm != 0u);
+        mlo &= ~((uint32_t)bb ^ sm);
+        mhi &= ~((uint32_t)(bb >> 32) ^ sm);
+    }
+    return ((uint64_t)mhi << 32) | mlo;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     int l = lane_id();
     return l == 0 ? 0ull : (~0ull >> (64 - l));
