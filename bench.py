@@ -43,10 +43,18 @@ HBM_PEAK = 8.0e12
 # counters, count (5 more products) -- see the design notes
 OPS_PER_EVAL = 16
 OPS_PER_CONTRIB = 24
-# the survey's single figure: 40 lane-ops per contributing pair (16 for the
-# alpha evaluation, 24 for the weight, transmittance and moments), nothing for
+# the headline rule: 40 lane-ops per contributing pair (16 for the alpha
+# evaluation, 24 for the weight, transmittance and moments), nothing for
 # pairs that are evaluated and do not contribute
-OPS_PER_CONTRIB_SURVEY = 40
+OPS_PER_CONTRIB_HEADLINE = 40
+# refinement rasteriser, same counting: forward -- alpha evaluation (16) per
+# evaluated pair, weight, transmittance and three colour sums (6) per
+# contributing pair; backward -- alpha again (16) per evaluated pair, and per
+# contributing pair the transmittance (2), dL/dalpha over three channels with
+# the reciprocal of 1 - alpha (16), the colour behind (3), colour (3) and
+# opacity (2) gradients and the power-gradient moments (7): 33
+RASTER_FWD_EVAL, RASTER_FWD_CONTRIB = 16, 6
+RASTER_BWD_EVAL, RASTER_BWD_CONTRIB = 16, 33
 
 
 def log(msg):
@@ -317,7 +325,72 @@ def refine_bench(dev, iters=100, warmup=3):
                     f"iterations_per_s{key}": iters / t, f"loss_first{key}": losses[0],
                     f"loss_last{key}": losses[-1]})
         log(f"  refine [{recipe}] {t * 1e3 / iters:.2f} ms/iteration, loss {losses[0]:.5f} -> {losses[-1]:.5f}")
+    out["roofline"] = raster_roofline(rc, fresh(), target)
     return out
+
+
+def raster_roofline(rc, params, target, reps=10):
+    """Pair counts of one counted forward + backward at the refinement
+    workload, then each raster kernel alone, timed with HIP events on the
+    stream it is launched on (torch's current stream)."""
+    import ctypes
+
+    import torch
+
+    from paper_2604_02586_amd._lib import check, lib
+    from paper_2604_02586_amd.api import _ptr, stream_ptr
+    from paper_2604_02586_amd.raster import L1Loss, rasterize
+
+    rc.count_pairs(True)
+    img = rasterize(*params, rc)
+    loss = L1Loss.apply(img, target)
+    loss.backward()
+    torch.cuda.synchronize()
+    f_ev, f_co, b_steps, b_ev, b_co = (int(x) for x in rc.pair_counts.cpu())
+    rc.count_pairs(False)
+    # the last forward's splats, bins and n_proc are in place: replay the
+    # kernels alone (the backward adds into grad2d, which nothing reads here)
+    dimage = torch.sign(rc.image - target).contiguous()
+    sc, bc = rc.splats.c(), rc.bins.c()
+    L = lib()
+
+    def fwd():
+        check("tg_raster_fwd", L.tg_raster_fwd(ctypes.byref(sc), ctypes.byref(bc), rc.N, rc.cams, rc.V, rc.bg,
+                                               ctypes.byref(rc.params), _ptr(rc.image), None, _ptr(rc.n_proc),
+                                               stream_ptr()))
+
+    def bwd():
+        check("tg_raster_bwd", L.tg_raster_bwd(ctypes.byref(sc), ctypes.byref(bc), rc.N, rc.cams, rc.V,
+                                               _ptr(rc.image), _ptr(dimage), _ptr(rc.n_proc),
+                                               ctypes.byref(rc.params), _ptr(rc.grad2d), stream_ptr()))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_f, ms_b = timed(fwd), timed(bwd)
+    ops_f = RASTER_FWD_EVAL * f_ev + RASTER_FWD_CONTRIB * f_co
+    ops_b = RASTER_BWD_EVAL * b_ev + RASTER_BWD_CONTRIB * b_co
+    res = {}
+    for name, ms, ops, rule, extra in (
+            ("tg_raster_fwd", ms_f, ops_f, f"{RASTER_FWD_EVAL} per evaluated + {RASTER_FWD_CONTRIB} per contributing pair",
+             {"pairs_evaluated": f_ev, "pairs_contributing": f_co}),
+            ("tg_raster_bwd", ms_b, ops_b, f"{RASTER_BWD_EVAL} per evaluated + {RASTER_BWD_CONTRIB} per contributing pair",
+             {"pixel_steps": b_steps, "pairs_evaluated": b_ev, "pairs_contributing": b_co,
+              "lanes_per_step": b_ev / max(b_steps, 1), "contributing_per_step": b_co / max(b_steps, 1)})):
+        achieved = ops / (ms * 1e-3)
+        res[name] = {"bound": "alu", "avg_ms": ms, "algorithmic_ops": ops, "ops_rule": rule,
+                     "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "T lane-ops/s",
+                     "frac": achieved / VALU_PEAK, **extra}
+        log(f"  {name}: {ms:.3f} ms, {achieved / 1e12:.2f} T lane-ops/s = {achieved / VALU_PEAK:.3f} of peak; {extra}")
+    return res
 
 
 def main():
@@ -530,7 +603,7 @@ def main():
         torch.cuda.synchronize()
         warm = (time.perf_counter() - tw) * 1e3 / args.steps
 
-    alg_ops = OPS_PER_CONTRIB_SURVEY * e_contrib
+    alg_ops = OPS_PER_CONTRIB_HEADLINE * e_contrib
     achieved = alg_ops / (acc_ms * 1e-3)
     own_ops = OPS_PER_EVAL * e_eval + OPS_PER_CONTRIB * e_contrib
     # algorithmic bytes per frame: parameters in and out, tracks, accumulators
@@ -565,7 +638,7 @@ def main():
                      "peak": VALU_PEAK / 1e12, "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK,
                      "traffic": measured_traffic(), "traffic_unit": "B per launch",
                      "algorithmic_ops": alg_ops,
-                     "ops_rule": f"{OPS_PER_CONTRIB_SURVEY} lane-ops per contributing (pixel, Gaussian) pair",
+                     "ops_rule": f"{OPS_PER_CONTRIB_HEADLINE} lane-ops per contributing (pixel, Gaussian) pair",
                      "avg_ms": acc_ms,
                      "frac_evaluated_rule": own_ops / (acc_ms * 1e-3) / VALU_PEAK,
                      "evaluated_rule": f"{OPS_PER_EVAL} per evaluated + {OPS_PER_CONTRIB} per contributing pair",

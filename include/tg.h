@@ -255,6 +255,8 @@ tg_status tg_bin_sort_static(const tg_splats* s, int64_t N, const tg_camera* cam
  * depth-ordered list entries visited up to each pixel's termination, after
  * exact culling of Gaussians whose alpha stays below alpha_min on the whole
  * tile; a pixel step evaluates one pixel against up to 64 Gaussians.
+ * Counting is a diagnostic: each wave adds its counts with atomics on the
+ * same words, which serialise, so a counted launch runs about twice as long.
  */
 tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins, int64_t N,
                               const tg_camera* cams, int32_t V, const float* disp,
@@ -555,6 +557,19 @@ tg_status tg_raster_fwd(const tg_splats* s, const tg_bins* bins, int64_t N, cons
                         void* stream);
 
 /*
+ * tg_raster_fwd_counted -- tg_raster_fwd that also adds, to stats (device
+ * int64 [2], nullable), the (pixel, Gaussian) pairs evaluated (the pixel,
+ * not yet terminated, tests the tile-list entry) and contributing (the entry
+ * passes every test of Sec. 3.1 and is composited).  Same outputs as
+ * tg_raster_fwd.  A diagnostic: every wave adds its counts with atomics on
+ * the same two words, which serialise, so a counted launch runs several
+ * times longer than tg_raster_fwd; time the plain call.
+ */
+tg_status tg_raster_fwd_counted(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams,
+                                int32_t V, const float* bg, const tg_params* p, float* image, float* t_final,
+                                int32_t* n_proc, int64_t* stats, void* stream);
+
+/*
  * tg_raster_bwd -- gradients of a loss w.r.t. the 2D splats, given dL/dimage
  * and the forward's image and n_proc.  grad2d: device [V,N,9], zeroed by the
  * caller, receives (adds) per (view, Gaussian): dL/dmu_x, dL/dmu_y, dL/dconic
@@ -564,6 +579,19 @@ tg_status tg_raster_fwd(const tg_splats* s, const tg_bins* bins, int64_t N, cons
 tg_status tg_raster_bwd(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams, int32_t V,
                         const float* image, const float* dl_dimage, const int32_t* n_proc, const tg_params* p,
                         float* grad2d, void* stream);
+
+/*
+ * tg_raster_bwd_counted -- tg_raster_bwd that also adds, to stats (device
+ * int64 [3], nullable): pixel steps (one pixel against one batch of up to 64
+ * Gaussians of the tile's list), pairs evaluated (entries the forward
+ * processed for the pixel) and pairs contributing (entries that reach the
+ * pixel and carry gradient terms).  Same outputs as tg_raster_bwd; a
+ * diagnostic, slower than tg_raster_bwd for the same reason as
+ * tg_raster_fwd_counted.
+ */
+tg_status tg_raster_bwd_counted(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams,
+                                int32_t V, const float* image, const float* dl_dimage, const int32_t* n_proc,
+                                const tg_params* p, float* grad2d, int64_t* stats, void* stream);
 
 /*
  * tg_project_bwd -- chain rule from the 2D splat gradients (grad2d) through

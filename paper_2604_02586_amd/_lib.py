@@ -123,6 +123,8 @@ def lib():
         "tg_bin_expand": ([P, P, c_i64, P, c_i32, P, P, P, c_i64, P, P, P, P], st),
         "tg_raster_fwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),
         "tg_raster_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P], st),
+        "tg_raster_fwd_counted": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P, P], st),
+        "tg_raster_bwd_counted": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P, P], st),
         "tg_project_bwd": ([P, P, c_i64, P, c_i32, P, P, P, P], st),
         "tg_l1_loss_grad": ([P, P, c_i64, c_f, P, P, P], st),
         "tg_scale_by": ([P, P, c_i64, P, P], st),
@@ -155,6 +157,7 @@ def exported_symbols():
                         "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_bin_sort_static", "tg_splat_accumulate",
                         "tg_splat_accumulate_batch", "tg_regularize", "tg_solve_views", "tg_triangulate",
                         "tg_solve_triangulate", "tg_solve_triangulate_batch", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
+                        "tg_raster_fwd_counted", "tg_raster_bwd_counted",
                         "tg_project_bwd", "tg_l1_loss_grad", "tg_scale_by", "tg_scalar_affine", "tg_ssim_loss_grad",
                         "tg_adam_step",
                         "tg_adam_step_rows", "tg_serve_create", "tg_serve_destroy", "tg_serve_now",

@@ -43,14 +43,27 @@ struct RasterArgs {
     float bg0, bg1, bg2;
 };
 
+// Sum over the wave of a per-lane count (a pixel's count is far below
+// 2^26, so 64 of them fit 32 bits).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    return v;
+}
+
 // Filtered list entry staged in LDS: scaled conic (log2 units), centre,
 // opacity, colour.
 struct Entry {
     float mx, my, ca, cb, cc, op, r, g, b;
 };
 
+// STATS: adds (pairs evaluated, pairs contributing) to stats[0..1]; a
+// pair is evaluated when the pixel, not yet terminated, tests the entry,
+// and contributes when it passes every test and is composited.
+template <bool STATS>
 __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, float* __restrict__ image,
-                                                    float* __restrict__ t_final, int32_t* __restrict__ n_proc)
+                                                    float* __restrict__ t_final, int32_t* __restrict__ n_proc,
+                                                    unsigned long long* __restrict__ stats)
 {
     __shared__ Entry E[256];
     __shared__ uint32_t C[512];    // candidates passing the rectangle test
@@ -75,6 +88,7 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     bool done = !inside;
     int32_t nproc = -1;
+    uint32_t n_ev = 0, n_co = 0;
     uint32_t idx = 0;  // filtered index of the current batch start
     uint32_t pos = rg.x;
     uint32_t cn = 0;   // candidates waiting in C (block-uniform)
@@ -149,6 +163,7 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
         if (!done) {
             for (uint32_t e = 0; e < nhit; ++e) {
                 const Entry en = E[e];
+                if (STATS) ++n_ev;
                 const float ux = fx - en.mx, uy = fy - en.my;
                 const float p2 = ux * (en.ca * ux + en.cb * uy) + en.cc * uy * uy;
                 if (p2 > 0.0f) continue;
@@ -161,6 +176,7 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
                     break;
                 }
                 const float wgt = al * T;
+                if (STATS) ++n_co;
                 cr += en.r * wgt;
                 cg += en.g * wgt;
                 cb += en.b * wgt;
@@ -169,6 +185,13 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
         }
         idx += nhit;
         if (__syncthreads_and(done ? 1 : 0)) break;
+    }
+    if (STATS) {
+        const uint64_t ev = wave_sum_u64(n_ev), co = wave_sum_u64(n_co);
+        if (lane == 0) {
+            atomicAdd(stats, (unsigned long long)ev);
+            atomicAdd(stats + 1, (unsigned long long)co);
+        }
     }
     if (!inside) return;
     if (nproc < 0) nproc = (int32_t)idx;
@@ -183,9 +206,15 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
 // ------------------------------------------------------------------ backward
 constexpr int QCAP = 128;
 
+// STATS: adds (pixel steps, pairs evaluated, pairs contributing) to
+// stats[0..2]; a step is one pixel against one batch of 64 lanes, a pair is
+// evaluated when the forward processed it for that pixel and contributes
+// when it reaches the pixel (the lanes that carry gradient terms).
+template <bool STATS>
 __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, const float* __restrict__ image,
                                                    const float* __restrict__ dimage,
-                                                   const int32_t* __restrict__ n_proc, float* __restrict__ grad2d)
+                                                   const int32_t* __restrict__ n_proc, float* __restrict__ grad2d,
+                                                   unsigned long long* __restrict__ stats)
 {
     __shared__ uint32_t qi[QCAP];
     __shared__ uint32_t cq[QCAP];   // candidates passing the rectangle test
@@ -237,6 +266,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
     int qn = 0, cn = 0;
     uint32_t pos = rg.x;
     uint32_t bstart = 0;  // filtered index of the batch's first entry
+    uint64_t n_st = 0, n_ev = 0, n_co = 0;   // wave-uniform
 
     while ((alive[0] | alive[1] | alive[2] | alive[3]) != 0ull) {
         // two stages, as in the forward's order: the rectangle test streams
@@ -339,6 +369,11 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 const uint32_t nfw = (uint32_t)np - bstart;
                 const uint64_t fwm = nfw >= 64u ? ~0ull : ((1ull << nfw) - 1ull);
                 const uint64_t vm = ballot64(p2 <= 0.0f) & ballot64(al >= amin) & fwm;
+                if (STATS) {
+                    n_st += 1;
+                    n_ev += (uint64_t)(nfw < (uint32_t)nb ? nfw : (uint32_t)nb);
+                    n_co += (uint64_t)__popcll(vm);
+                }
                 if (vm == 0ull) continue;   // no lane reaches the pixel: nothing changes
                 const bool valid = __builtin_amdgcn_inverse_ballot_w64(vm);
                 float P = valid ? 1.0f - al : 1.0f;
@@ -398,6 +433,11 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
             unsafeAtomicAdd(dst + 8, g_b);
         }
         bstart += (uint32_t)nb;
+    }
+    if (STATS && lane0) {
+        atomicAdd(stats, (unsigned long long)n_st);
+        atomicAdd(stats + 1, (unsigned long long)n_ev);
+        atomicAdd(stats + 2, (unsigned long long)n_co);
     }
 }
 
@@ -736,9 +776,9 @@ __global__ void k_scalar_affine(float* __restrict__ out, const float* __restrict
 
 }  // namespace
 
-extern "C" tg_status tg_raster_fwd(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams,
-                                   int32_t V, const float* bg, const tg_params* p, float* image, float* t_final,
-                                   int32_t* n_proc, void* stream)
+extern "C" tg_status tg_raster_fwd_counted(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams,
+                                           int32_t V, const float* bg, const tg_params* p, float* image,
+                                           float* t_final, int32_t* n_proc, int64_t* stats, void* stream)
 {
     RasterArgs a;
     GridPack gp;
@@ -749,8 +789,41 @@ extern "C" tg_status tg_raster_fwd(const tg_splats* s, const tg_bins* bins, int6
     a.bg1 = bg ? bg[1] : 0.f;
     a.bg2 = bg ? bg[2] : 0.f;
     if (N == 0) return TG_OK;
-    hipLaunchKernelGGL(k_raster_fwd, dim3((unsigned)(a.blocks_per_xcd * 8)), dim3(256), 0, (hipStream_t)stream, a,
-                       gp, image, t_final, n_proc);
+    if (stats)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_raster_fwd<true>), dim3((unsigned)(a.blocks_per_xcd * 8)), dim3(256), 0,
+                           (hipStream_t)stream, a, gp, image, t_final, n_proc, (unsigned long long*)stats);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_raster_fwd<false>), dim3((unsigned)(a.blocks_per_xcd * 8)), dim3(256),
+                           0, (hipStream_t)stream, a, gp, image, t_final, n_proc, (unsigned long long*)nullptr);
+    TG_CHECK_LAUNCH();
+    return TG_OK;
+}
+
+extern "C" tg_status tg_raster_fwd(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams,
+                                   int32_t V, const float* bg, const tg_params* p, float* image, float* t_final,
+                                   int32_t* n_proc, void* stream)
+{
+    return tg_raster_fwd_counted(s, bins, N, cams, V, bg, p, image, t_final, n_proc, nullptr, stream);
+}
+
+extern "C" tg_status tg_raster_bwd_counted(const tg_splats* s, const tg_bins* bins, int64_t N, const tg_camera* cams,
+                                           int32_t V, const float* image, const float* dl_dimage,
+                                           const int32_t* n_proc, const tg_params* p, float* grad2d, int64_t* stats,
+                                           void* stream)
+{
+    RasterArgs a;
+    GridPack gp;
+    tg_status st = raster_setup(s, bins, N, cams, V, p, &a, &gp);
+    if (st != TG_OK) return st;
+    if (!image || !dl_dimage || !n_proc || !grad2d) return TG_ERR_INVALID_ARG;
+    if (N == 0) return TG_OK;
+    if (stats)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_raster_bwd<true>), dim3((unsigned)(a.blocks_per_xcd * 8)), dim3(64), 0,
+                           (hipStream_t)stream, a, gp, image, dl_dimage, n_proc, grad2d, (unsigned long long*)stats);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_raster_bwd<false>), dim3((unsigned)(a.blocks_per_xcd * 8)), dim3(64), 0,
+                           (hipStream_t)stream, a, gp, image, dl_dimage, n_proc, grad2d,
+                           (unsigned long long*)nullptr);
     TG_CHECK_LAUNCH();
     return TG_OK;
 }
@@ -759,16 +832,7 @@ extern "C" tg_status tg_raster_bwd(const tg_splats* s, const tg_bins* bins, int6
                                    int32_t V, const float* image, const float* dl_dimage, const int32_t* n_proc,
                                    const tg_params* p, float* grad2d, void* stream)
 {
-    RasterArgs a;
-    GridPack gp;
-    tg_status st = raster_setup(s, bins, N, cams, V, p, &a, &gp);
-    if (st != TG_OK) return st;
-    if (!image || !dl_dimage || !n_proc || !grad2d) return TG_ERR_INVALID_ARG;
-    if (N == 0) return TG_OK;
-    hipLaunchKernelGGL(k_raster_bwd, dim3((unsigned)(a.blocks_per_xcd * 8)), dim3(64), 0, (hipStream_t)stream, a,
-                       gp, image, dl_dimage, n_proc, grad2d);
-    TG_CHECK_LAUNCH();
-    return TG_OK;
+    return tg_raster_bwd_counted(s, bins, N, cams, V, image, dl_dimage, n_proc, p, grad2d, nullptr, stream);
 }
 
 extern "C" tg_status tg_project_bwd(const tg_gaussians* g, const tg_splats* s, int64_t N, const tg_camera* cams,

@@ -54,6 +54,14 @@ class RasterContext:
         self._check = torch.zeros(2, dtype=torch.int64).pin_memory()
         self._check_ev = None
         self._sized = False
+        # optional device int64 [5]: the forward adds (pairs evaluated, pairs
+        # contributing), the backward (pixel steps, pairs evaluated, pairs
+        # contributing) -- see count_pairs
+        self.pair_counts = None
+
+    def count_pairs(self, on=True):
+        """Switch the pair counters of the rasteriser on (zeroed) or off."""
+        self.pair_counts = torch.zeros(5, dtype=torch.int64, device=self.device) if on else None
 
     def _alloc_bins(self, capacity):
         self.bins = BinTensors.alloc(self.V, self.N, self.n_cells, capacity, self.device)
@@ -96,18 +104,29 @@ class RasterContext:
             self._check_ev.record(torch.cuda.current_stream())
         self.gen += 1
         sc, bc = self.splats.c(), self.bins.c()
-        check("tg_raster_fwd", lib().tg_raster_fwd(ctypes.byref(sc), ctypes.byref(bc), self.N, self.cams, self.V,
-                                                   self.bg, ctypes.byref(self.params), _ptr(self.image), None,
-                                                   _ptr(self.n_proc), stream_ptr()))
+        if self.pair_counts is not None:
+            check("tg_raster_fwd_counted", lib().tg_raster_fwd_counted(
+                ctypes.byref(sc), ctypes.byref(bc), self.N, self.cams, self.V, self.bg, ctypes.byref(self.params),
+                _ptr(self.image), None, _ptr(self.n_proc), _ptr(self.pair_counts), stream_ptr()))
+        else:
+            check("tg_raster_fwd", lib().tg_raster_fwd(ctypes.byref(sc), ctypes.byref(bc), self.N, self.cams, self.V,
+                                                       self.bg, ctypes.byref(self.params), _ptr(self.image), None,
+                                                       _ptr(self.n_proc), stream_ptr()))
         return self.image
 
     def backward(self, g: GaussianTensors, dimage: torch.Tensor, grads: GaussianTensors):
         self.grad2d.zero_()
         sc, bc = self.splats.c(), self.bins.c()
         dimage = dimage.contiguous()
-        check("tg_raster_bwd", lib().tg_raster_bwd(ctypes.byref(sc), ctypes.byref(bc), self.N, self.cams, self.V,
-                                                   _ptr(self.image), _ptr(dimage), _ptr(self.n_proc),
-                                                   ctypes.byref(self.params), _ptr(self.grad2d), stream_ptr()))
+        if self.pair_counts is not None:
+            check("tg_raster_bwd_counted", lib().tg_raster_bwd_counted(
+                ctypes.byref(sc), ctypes.byref(bc), self.N, self.cams, self.V, _ptr(self.image), _ptr(dimage),
+                _ptr(self.n_proc), ctypes.byref(self.params), _ptr(self.grad2d), _ptr(self.pair_counts[2:]),
+                stream_ptr()))
+        else:
+            check("tg_raster_bwd", lib().tg_raster_bwd(ctypes.byref(sc), ctypes.byref(bc), self.N, self.cams, self.V,
+                                                       _ptr(self.image), _ptr(dimage), _ptr(self.n_proc),
+                                                       ctypes.byref(self.params), _ptr(self.grad2d), stream_ptr()))
         gc, grc = g.c(), grads.c()
         check("tg_project_bwd", lib().tg_project_bwd(ctypes.byref(gc), ctypes.byref(sc), self.N, self.cams, self.V,
                                                      _ptr(self.grad2d), ctypes.byref(self.params), ctypes.byref(grc),

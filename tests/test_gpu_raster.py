@@ -270,3 +270,44 @@ def test_chain_rule_helpers():
     (3.0 * L1Loss.apply(img, tgt)).backward()
     expect = 3.0 * torch.sign(img.detach() - tgt) / img.numel()
     torch.testing.assert_close(img.grad, expect, rtol=1e-6, atol=0)
+
+
+def test_pair_counters_are_consistent_and_change_nothing():
+    """The counted forward/backward give the same image, n_proc and splat
+    gradients as the plain ones, and their counts agree exactly: the
+    backward evaluates the n_proc entries each pixel processed (sum of
+    n_proc), the forward also tests each terminating entry (at most one more
+    per pixel), and both passes count the same contributing pairs (alpha is
+    formed bit-identically in both)."""
+    from paper_2604_02586_amd.raster import L1Loss, RasterContext, rasterize
+    kw = dict(CASES["denser"])
+    p, cams = _case(kw.pop("name"), **kw)
+    rc = RasterContext(cams, p["means"].shape[0], bg=_bg())
+    tgt = torch.rand(rc.V, rc.H, rc.W, 3, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+
+    def run(counted):
+        rc.count_pairs(counted)
+        prm = _gpu_params(p)
+        img = rasterize(*prm, rc)
+        loss = L1Loss.apply(img, tgt)
+        loss.backward()
+        torch.cuda.synchronize()
+        out = (img.detach().clone(), rc.n_proc.clone(), rc.grad2d.clone(), [x.grad.clone() for x in prm])
+        counts = None if rc.pair_counts is None else [int(v) for v in rc.pair_counts.cpu()]
+        return out, counts
+
+    (img0, np0, g2d0, gr0), _ = run(False)
+    (img1, np1, g2d1, gr1), counts = run(True)
+    assert torch.equal(img0, img1) and torch.equal(np0, np1)
+    f_ev, f_co, b_steps, b_ev, b_co = counts
+    total_np = int(np1.to(torch.int64).sum())
+    npix = rc.V * rc.H * rc.W
+    print(f"[raster counts] fwd evaluated {f_ev} contributing {f_co}; bwd steps {b_steps} evaluated {b_ev} "
+          f"contributing {b_co}; sum n_proc {total_np}")
+    assert b_ev == total_np
+    assert total_np <= f_ev <= total_np + npix
+    assert f_co == b_co and 0 < f_co <= total_np
+    assert b_steps > 0 and b_ev <= 64 * b_steps
+    # atomics make the gradients' summation order vary: equal to FP32 rounding
+    scale = float(g2d0.abs().max())
+    assert float((g2d0 - g2d1).abs().max()) <= 1e-5 * scale
