@@ -274,6 +274,7 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
     constexpr int P_PK = EMIT_RANKS / 4, P_TST = P_PK + EMIT_RANKS / 8, P_WID = P_TST + 256 / 4;
     constexpr int P_WBIN = P_WID + DIRECT_WIN / 4;
     static_assert(P_WBIN + DIRECT_WIN / 16 <= EMIT_RANKS * 12 / 16, "LDS layout of the packed placement");
+    static_assert(DIRECT_WIN / 256 == 8, "the balanced expansion stages 8 pairs per thread");
     uint16_t* pkl = (uint16_t*)(lds + P_PK);
     uint32_t* tst = (uint32_t*)(lds + P_TST);
     uint32_t* wid = PACKED ? (uint32_t*)(lds + P_WID) : (uint32_t*)lds;               // [DIRECT_WIN]
@@ -323,9 +324,19 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
                 uint32_t x = x0 + (off - dy * wdt), y = ((pk >> 8) & 15u) + dy;
                 uint32_t gcur = sg[r];
                 const uint32_t qn = lim - q0 < (uint32_t)(DIRECT_WIN / 256) ? lim - q0 : (uint32_t)(DIRECT_WIN / 256);
-                for (uint32_t j = 0; j < qn; ++j) {
-                    wid[q0 + j] = gcur;
-                    wbin[q0 + j] = (uint8_t)(y * cw + x);
+                // the thread's 8 pairs go out as two 16-byte and one 8-byte
+                // LDS store (8 scattered words per lane would hit the same
+                // banks 16 ways); slots past qn hold junk the ranking never
+                // reads (it stops at the window's pair count)
+                uint32_t ids[DIRECT_WIN / 256];
+                uint32_t bins2[2] = {0u, 0u};
+#pragma unroll
+                for (int j = 0; j < DIRECT_WIN / 256; ++j) ids[j] = 0u;
+#pragma unroll
+                for (uint32_t j = 0; j < (uint32_t)(DIRECT_WIN / 256); ++j) {
+                    if (j >= qn) break;
+                    ids[j] = gcur;
+                    bins2[j >> 2] |= (y * cw + x) << (8 * (j & 3));
                     if (j + 1 == qn) break;
                     if (++x > x1) {
                         x = x0;
@@ -343,6 +354,9 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
                         }
                     }
                 }
+                ((uint4*)wid)[q0 / 4] = make_uint4(ids[0], ids[1], ids[2], ids[3]);
+                ((uint4*)wid)[q0 / 4 + 1] = make_uint4(ids[4], ids[5], ids[6], ids[7]);
+                ((uint2*)wbin)[q0 / 8] = make_uint2(bins2[0], bins2[1]);
             }
         } else {
             uint32_t pidx = before;

@@ -289,6 +289,57 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(uint32_t* __restrict
     }
 }
 
+// Exclusive scan of each segment's [L] u32 array in one block of
+// SCAN_THREADS per segment (L <= SCAN_THREADS * ITEMS): thread t scans its
+// ITEMS consecutive words in registers (16-byte loads), one block scan of
+// the thread totals, then writes back.  Replaces the three-kernel scan when
+// the segments are small (the radix histograms of per-view depth sorts).
+template <int ITEMS>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_seg(uint32_t* __restrict__ data, int64_t L)
+{
+    static_assert(ITEMS % 4 == 0, "16-byte chunks");
+    __shared__ uint32_t tot;
+    uint32_t* d = data + (int64_t)blockIdx.x * L;
+    const int64_t i0 = (int64_t)threadIdx.x * ITEMS;
+    uint32_t v[ITEMS];
+#pragma unroll
+    for (int q = 0; q < ITEMS / 4; ++q) {
+        const int64_t i = i0 + 4 * q;
+        uint4 x = make_uint4(0u, 0u, 0u, 0u);
+        if (i + 4 <= L) {
+            x = *(const uint4*)(d + i);
+        } else {
+            if (i < L) x.x = d[i];
+            if (i + 1 < L) x.y = d[i + 1];
+            if (i + 2 < L) x.z = d[i + 2];
+        }
+        v[4 * q] = x.x;
+        v[4 * q + 1] = x.y;
+        v[4 * q + 2] = x.z;
+        v[4 * q + 3] = x.w;
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t x = v[j];
+        v[j] = sum;
+        sum += x;
+    }
+    const uint32_t base = block_excl_scan(sum, &tot);
+#pragma unroll
+    for (int q = 0; q < ITEMS / 4; ++q) {
+        const int64_t i = i0 + 4 * q;
+        const uint4 x = make_uint4(v[4 * q] + base, v[4 * q + 1] + base, v[4 * q + 2] + base, v[4 * q + 3] + base);
+        if (i + 4 <= L) {
+            *(uint4*)(d + i) = x;
+        } else {
+            if (i < L) d[i] = x.x;
+            if (i + 1 < L) d[i + 1] = x.y;
+            if (i + 2 < L) d[i + 2] = x.z;
+        }
+    }
+}
+
 // ---- stable scatter --------------------------------------------------------
 // Items of a block: wave w owns keys [w*1024, (w+1)*1024) of the block's 8192,
 // visited in 16 rounds of 64 consecutive keys, so order within the block is
@@ -475,9 +526,17 @@ tg_status tg_radix_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, 
         else
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_radix_hist<false, false>), dim3(nblk, nseg), dim3(SORT_THREADS), 0,
                                s, ck, seg_len, dev_count, shift, hist, nblk, seginfo, 0, bit0, top_shift);
-        hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
-        hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(SCAN_THREADS), 0, s, sums, nchunk);
-        hipLaunchKernelGGL(k_scan_down, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
+        if (L <= (int64_t)SCAN_THREADS * 16) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<16>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L);
+        } else if (L <= (int64_t)SCAN_THREADS * 32) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<32>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L);
+        } else if (L <= (int64_t)SCAN_THREADS * 64) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<64>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L);
+        } else {
+            hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
+            hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(SCAN_THREADS), 0, s, sums, nchunk);
+            hipLaunchKernelGGL(k_scan_down, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
+        }
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblk, nseg), dim3(SORT_THREADS), 0, s, ck, cv, ok,
                            (last && !vfinal) ? nullptr : ov, seg_len, dev_count, shift, hist, nblk, seginfo,
                            mode & (MODE_SKIP | MODE_REDIRECT), bit0, top_shift, kfinal, vfinal);
