@@ -221,8 +221,9 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
     // per pixel: the colour still to come (final colour minus the front
     // already composited) with the running transmittance, and dL/dC
     __shared__ float4 RT[256];   // remaining colour (r, g, b), T
-    __shared__ float4 GF[256];   // dL/dC, unused
-    __shared__ float CFt[16], RFt[4];   // column / row offsets as floats
+    // dL/dC per channel: three word arrays keep the wave's LDS at 8 KB (five
+    // waves per SIMD; a float4 array would hold a dead word per pixel)
+    __shared__ float GFr[256], GFg[256], GFb[256];
     if (*a.overflow) return;
     const int64_t b = blockIdx.x;
     const int64_t L = (b & 7) * a.blocks_per_xcd + (b >> 3);
@@ -241,8 +242,6 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
 
     uint64_t alive[4];
     int npg[4];  // n_proc of pixel g*64 + lane
-    if (lane < 16) CFt[lane] = (float)lane;
-    if (lane < 4) RFt[lane] = (float)lane;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int j = g * 64 + lane;
@@ -257,7 +256,9 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
             np = n_proc[pi];
         }
         RT[j] = cf;
-        GF[j] = gf;
+        GFr[j] = gf.x;
+        GFg[j] = gf.y;
+        GFb[j] = gf.z;
         npg[g] = np;
         alive[g] = ballot64(in && np > 0);
     }
@@ -342,12 +343,10 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
         // per lane: sums over pixels of dpow u (s_x, s_y) and dpow u u^T
         // (s_xx, s_xy, s_yy), and the opacity and colour gradients
         float s_x = 0.f, s_y = 0.f, s_xx = 0.f, s_xy = 0.f, s_yy = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f;
-        const float fx0 = (float)px0;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             uint64_t m = alive[g];
             uint64_t dead = 0;
-            const float fy0 = (float)(py0 + 4 * g);
             while (m) {
                 const int j = __builtin_ctzll(m);
                 m &= m - 1;
@@ -355,10 +354,10 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 const int np = __builtin_amdgcn_readlane(npg[g], j);
                 if ((uint32_t)np <= bstart + (uint32_t)nb) dead |= 1ull << j;  // last batch for this pixel
                 const float4 rt = RT[pj];
-                const float4 gf = GF[pj];
-                // pixel coordinates exactly as the forward forms them (integer
-                // sums are exact in FP32), so alpha is bit-identical
-                const float ux = (fx0 + CFt[j & 15]) - mx, uy = (fy0 + RFt[j >> 4]) - my;
+                const float3 gf = make_float3(GFr[pj], GFg[pj], GFb[pj]);
+                // the pixel coordinate converted from the integer, as the
+                // forward forms it, so alpha is bit-identical
+                const float ux = (float)(px0 + (j & 15)) - mx, uy = (float)(py0 + 4 * g + (j >> 4)) - my;
                 const float p2 = ux * (ca * ux + cb * uy) + cc * uy * uy;
                 const float ex = __builtin_amdgcn_exp2f(p2);
                 const float e2 = op * ex;
