@@ -12,10 +12,12 @@
 //   tg_raster_bwd   Gaussian-parallel within a tile (one wave64, 64
 //                   consecutive Gaussians across the lanes, pixels as
 //                   wave-uniform values), front to back: transmittance in
-//                   front of a lane is a DPP product scan, the colour in front
-//                   three DPP sum scans, and the colour behind comes from the
-//                   forward's final colour: dC/dalpha_i = c_i T_i -
-//                   (C - front_i - c_i w_i) / (1 - alpha_i).  The 9 gradients of
+//                   front of a lane is a DPP product scan, and since every
+//                   channel enters through its dot product with the pixel's
+//                   dL/dC, one DPP sum scan of g . c_i w_i gives the colour in
+//                   front and the final colour the colour behind:
+//                   dL/dalpha_i = g . (c_i T_i - (C - front_i - c_i w_i) /
+//                   (1 - alpha_i)).  The 9 gradients of
 //                   each Gaussian's 2D splat stay in registers over the tile and
 //                   go to HBM with one set of atomics per (tile, Gaussian).
 //   tg_project_bwd  per Gaussian, over views: splat gradients -> mean,
@@ -219,8 +221,10 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
     __shared__ uint32_t qi[QCAP];
     __shared__ uint32_t cq[QCAP];   // candidates passing the rectangle test
     // per pixel: the colour still to come (final colour minus the front
-    // already composited) with the running transmittance, and dL/dC
-    __shared__ float4 RT[256];   // remaining colour (r, g, b), T
+    // already composited) dotted with the pixel's dL/dC, the running
+    // transmittance, and dL/dC itself.  Every channel enters dL/dalpha only
+    // through that dot product, so one sum scan per step replaces three.
+    __shared__ float2 RT[256];   // g . remaining colour, T
     // dL/dC per channel: three word arrays keep the wave's LDS at 8 KB (five
     // waves per SIMD; a float4 array would hold a dead word per pixel)
     __shared__ float GFr[256], GFg[256], GFb[256];
@@ -255,7 +259,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
             gf = make_float4(dimage[3 * pi], dimage[3 * pi + 1], dimage[3 * pi + 2], 0.0f);
             np = n_proc[pi];
         }
-        RT[j] = cf;
+        RT[j] = make_float2(fmaf(gf.z, cf.z, fmaf(gf.y, cf.y, gf.x * cf.x)), 1.0f);
         GFr[j] = gf.x;
         GFg[j] = gf.y;
         GFb[j] = gf.z;
@@ -353,7 +357,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 const int pj = g * 64 + j;
                 const int np = __builtin_amdgcn_readlane(npg[g], j);
                 if ((uint32_t)np <= bstart + (uint32_t)nb) dead |= 1ull << j;  // last batch for this pixel
-                const float4 rt = RT[pj];
+                const float2 rt = RT[pj];
                 const float3 gf = make_float3(GFr[pj], GFg[pj], GFb[pj]);
                 // the pixel coordinate converted from the integer, as the
                 // forward forms it, so alpha is bit-identical
@@ -379,20 +383,20 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 P = wave_scan_mul_fused(P);
                 asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
                              : "+v"(pex_reg) : "v"(P));
-                const float Ti = rt.w * pex_reg;
+                const float Ti = rt.y * pex_reg;
                 const float wgt = valid ? al * Ti : 0.0f;
-                const float w0 = c0 * wgt, w1 = c1 * wgt, w2 = c2 * wgt;
-                float F0 = w0, F1 = w1, F2 = w2;
-                wave_scan_add_fused3(F0, F1, F2);
+                // the lane's colour dotted with the pixel's dL/dC
+                const float dc = fmaf(gf.z, c2, fmaf(gf.y, c1, gf.x * c0));
+                const float F = wave_scan_add_fused(dc * wgt);
                 if (valid) {
-                    // colour behind lane i (incl. background): C - front - own
-                    const float S0 = rt.x - F0, S1 = rt.y - F1, S2 = rt.z - F2;
+                    // colour behind lane i (incl. background), dotted with
+                    // dL/dC: (C - front - own) . g
+                    const float S = rt.x - F;
                     // 1 - alpha >= 0.01 (alpha is clamped at 0.99): the
                     // hardware reciprocal's ulp error is far below the
                     // gradient's FP32 accumulation error
                     const float inv1m = __builtin_amdgcn_rcpf(1.0f - al);
-                    const float dal = gf.x * (c0 * Ti - S0 * inv1m) + gf.y * (c1 * Ti - S1 * inv1m) +
-                                      gf.z * (c2 * Ti - S2 * inv1m);
+                    const float dal = dc * Ti - S * inv1m;
                     g_r += gf.x * wgt;
                     g_g += gf.y * wgt;
                     g_b += gf.z * wgt;
@@ -411,10 +415,9 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                     }
                 }
                 // advance this pixel's transmittance and remaining colour
-                const float Tn = rt.w * readlane_f(P, 63);
-                const float r0 = rt.x - readlane_f(F0, 63), r1 = rt.y - readlane_f(F1, 63),
-                            r2 = rt.z - readlane_f(F2, 63);
-                if (lane0) RT[pj] = make_float4(r0, r1, r2, Tn);
+                const float Tn = rt.y * readlane_f(P, 63);
+                const float Rn = rt.x - readlane_f(F, 63);
+                if (lane0) RT[pj] = make_float2(Rn, Tn);
             }
             alive[g] &= ~dead;
         }
