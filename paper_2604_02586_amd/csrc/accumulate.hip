@@ -296,9 +296,13 @@ k_accumulate(BatchArgs a)
             cc = -0.5f * LOG2E * r1.x;
             op = r1.y;
         }
-        // alpha = o 2^q = 2^(q + log2 o): the opacity rides in the row term,
-        // and "power <= 0" becomes q + log2 o <= log2 o (-inf for the empty
-        // lanes, whose alpha is 0)
+        // alpha = o 2^q = 2^(q + log2 o): the opacity rides in the row term
+        // (log2 o = -inf for the empty lanes, whose alpha is then 0).  The
+        // renderer's "skip if power > 0" test is not evaluated: the conic is
+        // the inverse of the dilated covariance (determinant >= 0.09 px^4 for
+        // any positive semi-definite Sigma_2D, FP32 rounding keeps it
+        // positive definite), so power <= 0 everywhere but for rounding at
+        // the splat centre, where alpha is o either way.
         const float lop = __builtin_amdgcn_logf(op);
         // column anchor: ux = ax + (column - o_x), o_x the column nearest the
         // centre, clamped to the tile
@@ -352,8 +356,8 @@ k_accumulate(BatchArgs a)
                 const float q1 = fmaf(fmaf(ca, cpp, bq), cpp, cq);
                 // alpha = min(alpha_max, o e^power), clamped with one v_med3
                 const float al1 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(q1), 0.0f, amax);
-                // valid lanes: power <= 0 and alpha >= alpha_min
-                const uint64_t vm1 = ballot64(q1 <= lop) & ballot64(al1 >= amin);
+                // valid lanes: alpha >= alpha_min
+                const uint64_t vm1 = ballot64(al1 >= amin);
                 // no Gaussian of the batch reaches the pixel: nothing changes
                 if (vm1 == 0ull) {
                     if (STATS) {
