@@ -391,30 +391,30 @@ k_accumulate(BatchArgs a)
                 // statistics of Eq. 4 for the lanes that contribute, per frame
                 // whose track at this pixel is visible: one exec mask, no
                 // separate tests (the wave-wide reads come first)
-                uint32_t fl1 = 0;
-                uint64_t gate;
-                if constexpr (FM == 1) {
-                    gate = ((visg >> j1) & 1ull) ? cm1 : 0ull;
-                } else {
-                    fl1 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j1);
-                    gate = (fl1 & VISM) ? cm1 : 0ull;
-                }
                 asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
                              : "+v"(pex_reg) : "v"(P1));
-                float2 td[FM];
                 if constexpr (FM == 1) {
-                    td[0] = make_float2(readlane_f(Xrow, c1), readlane_f(Yrow, c1));
+                    // one frame: a scalar bit test of the pixel's visibility
+                    // (a wave-uniform branch, no selects), then the
+                    // contributing lanes
+                    if ((visg >> j1) & 1ull) {
+                        const float2 td = make_float2(readlane_f(Xrow, c1), readlane_f(Yrow, c1));
+                        if (__builtin_amdgcn_inverse_ballot_w64(cm1)) {
+                            const float wgt = al1 * (T1 * pex_reg);
+                            const float wc = wgt * cpp;
+                            sums_add(sm[0], wgt, wc, cpp, td.x, td.y, (statg >> j1) & 1ull, al1);
+                        }
+                    }
                 } else {
+                    const uint32_t fl1 = (uint32_t)__builtin_amdgcn_readlane((int)flg[g], j1);
+                    const uint64_t gate = (fl1 & VISM) ? cm1 : 0ull;
+                    float2 td[FM];
 #pragma unroll
                     for (int f = 0; f < FM; ++f)
                         td[f] = make_float2(readlane_f(dxg[f][g], j1), readlane_f(dyg[f][g], j1));
-                }
-                if (__builtin_amdgcn_inverse_ballot_w64(gate)) {
-                    const float wgt = al1 * (T1 * pex_reg);
-                    const float wc = wgt * cpp;
-                    if constexpr (FM == 1) {
-                        sums_add(sm[0], wgt, wc, cpp, td[0].x, td[0].y, (statg >> j1) & 1ull, al1);
-                    } else {
+                    if (__builtin_amdgcn_inverse_ballot_w64(gate)) {
+                        const float wgt = al1 * (T1 * pex_reg);
+                        const float wc = wgt * cpp;
 #pragma unroll
                         for (int f = 0; f < FM; ++f)
                             if ((fl1 >> f) & 1u)
