@@ -77,7 +77,10 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
     TileCoord tc;
     if (!tile_of(L, a.cshift, a.V, gp, &tc)) return;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    const int px = tc.tx * TG_TILE + (t & 15), py = tc.ty * TG_TILE + (t >> 4);
+    // wave w takes the 8x8 quadrant w of the tile: compact pixel blocks have
+    // more alike list depths than 16x4 strips, and a wave runs as long as its
+    // slowest pixel
+    const int px = tc.tx * TG_TILE + 8 * (w & 1) + (lane & 7), py = tc.ty * TG_TILE + 8 * (w >> 1) + (lane >> 3);
     const bool inside = px < a.W && py < a.H;
     const float fx = (float)px, fy = (float)py;
     const uint2 rg = a.ranges[tc.gcell];
