@@ -121,7 +121,7 @@ template <bool HIST, bool PACKED>
 __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__ order, const ushort4* __restrict__ rect,
                                                     const uint16_t* __restrict__ crect, int64_t N, int V,
                                                     int cshift, int nblk, GridPack gp, ushort4* __restrict__ crs,
-                                                    uint32_t* __restrict__ counts,
+                                                    uint16_t* __restrict__ prk, uint32_t* __restrict__ counts,
                                                     unsigned long long* __restrict__ n_pairs)
 {
     __shared__ uint32_t wsum[4];
@@ -155,6 +155,11 @@ __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__
         for (int i = 0; i < EMIT_ITEMS; ++i) g[i] = base + i * 256 < N ? order[vN + base + i * 256] : 0xFFFFFFFFu;
 #pragma unroll
         for (int i = 0; i < EMIT_ITEMS; ++i) pk[i] = g[i] < (uint64_t)N ? crect[vN + g[i]] : CRECT_EMPTY;
+        // the gathered rectangles in rank order (coalesced): the placement
+        // reads them back instead of gathering again
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i)
+            if (base + i * 256 < N) prk[vN + base + i * 256] = pk[i];
 #pragma unroll
         for (int i = 0; i < EMIT_ITEMS; ++i) {
             const ushort4 c = unpack_crect(pk[i], cnt);
@@ -195,6 +200,8 @@ __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__
 // pair keys.  Within a window, wave w ranks items [w*1024, w*1024+1024) in
 // rounds of 64 consecutive items by ballot matching on the bin (stable), the
 // window is placed bin-major in LDS and then written out as contiguous runs.
+// The rectangles come in rank order: 8-byte coarse rectangles (crs), or with
+// PACKED the 16-bit packed ones the count pass stored (crect, [V*N]).
 template <bool PACKED>
 __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__ order, const ushort4* __restrict__ crs,
                                                     const uint16_t* __restrict__ crect, int64_t N, int V, GridPack gp,
@@ -252,9 +259,19 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
     uint32_t mine = 0;
     uint16_t pkr[EMIT_ITEMS];
     if (PACKED) {
-        // ranks past the end and out-of-range ids hold no pairs
+        // the count pass stored each rank's packed rectangle in rank order;
+        // ranks past the end hold no pairs
+        const int64_t r0 = rbase + EMIT_ITEMS * t;
+        if (r0 + EMIT_ITEMS <= N && ((vN + r0) & 7) == 0) {
+            const uint4 q = *(const uint4*)(crect + vN + r0);
+            pkr[0] = (uint16_t)q.x; pkr[1] = (uint16_t)(q.x >> 16);
+            pkr[2] = (uint16_t)q.y; pkr[3] = (uint16_t)(q.y >> 16);
+            pkr[4] = (uint16_t)q.z; pkr[5] = (uint16_t)(q.z >> 16);
+            pkr[6] = (uint16_t)q.w; pkr[7] = (uint16_t)(q.w >> 16);
+        } else {
 #pragma unroll
-        for (int i = 0; i < EMIT_ITEMS; ++i) pkr[i] = gid[i] < (uint64_t)N ? crect[vN + gid[i]] : CRECT_EMPTY;
+            for (int i = 0; i < EMIT_ITEMS; ++i) pkr[i] = r0 + i < N ? crect[vN + r0 + i] : CRECT_EMPTY;
+        }
 #pragma unroll
         for (int i = 0; i < EMIT_ITEMS; ++i) cr[i] = unpack_crect(pkr[i], mine);
     } else {
@@ -680,6 +697,7 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
         // block sorts its pairs by bin in LDS and writes the final lists
         uint32_t* mat = L.pk_a;   // [ncell][nblk], free on this path
         uint16_t* crect = nullptr;
+        uint16_t* prk = nullptr;
         bool packed = false;
         int max_cx = 0, max_cy = 0;
         for (int v = 0; v < V; ++v) {
@@ -700,14 +718,17 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pack_crect<false>), dim3((unsigned)pgrid), dim3(256), 0, s,
                                    (const ushort4*)sp->rect, VN, bp.cshift, crect);
             const int64_t per_xcd = ((int64_t)nblk * V + 7) / 8;
+            // packed rectangles in rank order for the placement: the depth
+            // sort's first ping-pong key array (free once the order is out)
+            prk = (uint16_t*)L.dk_a;
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_count<true, true>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0,
                                s, bins->order, (const ushort4*)sp->rect, (const uint16_t*)crect, N, V, bp.cshift,
-                               nblk, bp.gp, crs, mat, (unsigned long long*)bins->n_pairs);
+                               nblk, bp.gp, crs, prk, mat, (unsigned long long*)bins->n_pairs);
             packed = true;
         } else {
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_count<true, false>), dim3((unsigned)nblk, V), dim3(256), 0, s,
                                bins->order, (const ushort4*)sp->rect, (const uint16_t*)nullptr, N, V, bp.cshift,
-                               nblk, bp.gp, crs, mat, (unsigned long long*)bins->n_pairs);
+                               nblk, bp.gp, crs, (uint16_t*)nullptr, mat, (unsigned long long*)bins->n_pairs);
         }
         hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,
                            bins->capacity, bins->overflow);
@@ -716,7 +737,7 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
         if (packed) {
             const int64_t per_xcd = ((int64_t)nblk * V + 7) / 8;
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_place<true>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s,
-                               bins->order, (const ushort4*)nullptr, (const uint16_t*)crect, N, V, bp.gp, nblk, mat,
+                               bins->order, (const ushort4*)nullptr, (const uint16_t*)prk, N, V, bp.gp, nblk, mat,
                                bins->cell_ids, bins->overflow);
         } else {
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_place<false>), dim3((unsigned)nblk, V), dim3(256), 0, s,
@@ -732,7 +753,7 @@ extern "C" tg_status tg_bin_sort(const tg_splats* sp, int64_t N, const tg_camera
     // then a stable radix sort over the bin bits
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_emit_count<false, false>), dim3((unsigned)nblk, V), dim3(256), 0, s,
                        bins->order, (const ushort4*)sp->rect, (const uint16_t*)nullptr, N, V, bp.cshift, nblk, bp.gp,
-                       crs, L.counts, (unsigned long long*)bins->n_pairs);
+                       crs, (uint16_t*)nullptr, L.counts, (unsigned long long*)bins->n_pairs);
     hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, s, (const unsigned long long*)bins->n_pairs,
                        bins->capacity, bins->overflow);
     // with no overflow the total fits the capacity (< 2^32), so u32 offsets
