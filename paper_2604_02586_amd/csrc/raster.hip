@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_raster_fwd(RasterArgs a, GridPack gp, f
                 const Entry en = E[e];
                 if (STATS) ++n_ev;
                 const float ux = fx - en.mx, uy = fy - en.my;
-                const float p2 = ux * (en.ca * ux + en.cb * uy) + en.cc * uy * uy;
+                const float p2 = raster_power(ux, uy, en.ca, en.cb, en.cc);
                 if (p2 > 0.0f) continue;
                 const float al = __builtin_amdgcn_fmed3f(en.op * __builtin_amdgcn_exp2f(p2), 0.0f, a.alpha_max);
                 if (al < a.alpha_min) continue;
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
                 // the pixel coordinate converted from the integer, as the
                 // forward forms it, so alpha is bit-identical
                 const float ux = (float)(px0 + (j & 15)) - mx, uy = (float)(py0 + 4 * g + (j >> 4)) - my;
-                const float p2 = ux * (ca * ux + cb * uy) + cc * uy * uy;
+                const float p2 = raster_power(ux, uy, ca, cb, cc);
                 const float ex = __builtin_amdgcn_exp2f(p2);
                 const float e2 = op * ex;
                 const float al = __builtin_amdgcn_fmed3f(e2, 0.0f, amax);

@@ -173,6 +173,18 @@ __device__ __forceinline__ float wave_scan_add_fused(float x) {
     return x;
 }
 
+// Exponent of alpha in log2 units at pixel offset (ux, uy) for a
+// log2-prescaled conic (ca, cb, cc): ux (ca ux + cb uy) + cc uy^2.  The
+// forward and backward rasterisers both call this one function, with the
+// fused multiply-adds written out and contraction otherwise off, so the
+// backward's replay of the forward's alpha decisions is bit-identical
+// whatever the compiler does with the surrounding code.
+__device__ __forceinline__ float raster_power(float ux, float uy, float ca, float cb, float cc) {
+#pragma clang fp contract(off)
+    const float t = __builtin_fmaf(ca, ux, cb * uy);
+    return __builtin_fmaf(ux, t, (cc * uy) * uy);
+}
+
 // Smallest value over the rectangle [x0,x1] x [y0,y1] of the positive-definite
 // form q(p) = a dx^2 + 2 b dx dy + c dy^2, (dx, dy) = p - (mx, my): zero when the
 // centre is inside, otherwise the least of the four edge minima (each a 1D

@@ -311,3 +311,25 @@ def test_pair_counters_are_consistent_and_change_nothing():
     # atomics make the gradients' summation order vary: equal to FP32 rounding
     scale = float(g2d0.abs().max())
     assert float((g2d0 - g2d1).abs().max()) <= 1e-5 * scale
+
+
+def test_full_size_backward_replays_forward_decisions():
+    """At the refinement workload's shape (500k Gaussians, 16 views of
+    1352x1014, about 6e8 contributing pairs) the backward must replay the
+    forward's alpha decisions exactly: the counted passes agree to the pair
+    (contributing pairs equal, backward evaluations = sum of n_proc)."""
+    from paper_2604_02586_amd.raster import L1Loss, RasterContext, rasterize
+    wl = synth.make_refine_workload("refine")
+    rc = RasterContext(wl.cams, wl.meta["n"], bg=_bg())
+    rc.count_pairs(True)
+    prm = _gpu_params(wl.gt)
+    img = rasterize(*prm, rc)
+    loss = L1Loss.apply(img, torch.zeros_like(img))
+    loss.backward()
+    torch.cuda.synchronize()
+    f_ev, f_co, b_steps, b_ev, b_co = (int(v) for v in rc.pair_counts.cpu())
+    total_np = int(rc.n_proc.to(torch.int64).sum())
+    print(f"[raster counts full] fwd {f_ev} / {f_co}; bwd {b_steps} steps, {b_ev} / {b_co}; sum n_proc {total_np}")
+    assert f_co == b_co
+    assert b_ev == total_np
+    assert total_np <= f_ev <= total_np + rc.V * rc.H * rc.W
