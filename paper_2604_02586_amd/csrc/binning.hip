@@ -238,16 +238,35 @@ __global__ void __launch_bounds__(256) k_emit_place(const uint32_t* __restrict__
     const int64_t rbase = (int64_t)blk * EMIT_RANKS;
     uint32_t* sg = (uint32_t*)lds;
     ushort4* sc = (ushort4*)(lds + EMIT_RANKS / 4);
-#pragma unroll
-    for (int i = 0; i < EMIT_ITEMS; ++i) {
-        const int j = i * 256 + t;
-        const bool in = rbase + j < N;
-        sg[j] = in ? order[vN + rbase + j] : 0xFFFFFFFFu;
-        if (!PACKED) sc[j] = in ? crs[vN + rbase + j] : make_ushort4(0, 0, 0, 0);
-    }
     const int cw = gp.cx[v], nbv = gp.cx[v] * gp.cy[v];
-    for (int c = t; c < nbv; c += 256)
-        boff[c] = offsets[(int64_t)(gp.cell_off[v] + c) * nblk + blk];
+    {
+        // every load in flight before the first LDS store (a load followed by
+        // its store, item by item, waits out each round trip)
+        uint32_t og[EMIT_ITEMS];
+        ushort4 oc[PACKED ? 1 : EMIT_ITEMS];
+        const uint32_t bo = t < nbv ? offsets[(int64_t)(gp.cell_off[v] + t) * nblk + blk] : 0u;
+        if (rbase + EMIT_RANKS <= N) {
+#pragma unroll
+            for (int i = 0; i < EMIT_ITEMS; ++i) og[i] = order[vN + rbase + i * 256 + t];
+            if (!PACKED) {
+#pragma unroll
+                for (int i = 0; i < EMIT_ITEMS; ++i) oc[i] = crs[vN + rbase + i * 256 + t];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < EMIT_ITEMS; ++i) {
+                const bool in = rbase + i * 256 + t < N;
+                og[i] = in ? order[vN + rbase + i * 256 + t] : 0xFFFFFFFFu;
+                if (!PACKED) oc[i] = in ? crs[vN + rbase + i * 256 + t] : make_ushort4(0, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) {
+            sg[i * 256 + t] = og[i];
+            if (!PACKED) sc[i * 256 + t] = oc[i];
+        }
+        if (t < nbv) boff[t] = bo;   // nbv <= DIRECT_BINS = 256 = the block size
+    }
     __syncthreads();
     uint32_t gid[EMIT_ITEMS];
     ushort4 cr[EMIT_ITEMS];

@@ -377,18 +377,30 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(
     const int64_t so = (int64_t)seg * seg_len;
     const bool with_v = vout != nullptr;
     uint32_t k[SORT_ITEMS], val[SORT_ITEMS];
+    // every key and value load in flight before the first use (a load
+    // followed by its LDS atomic item by item waits out 16 round trips)
+    const int64_t i0 = base + w * WAVE_ITEMS + l;
+    if (nvalid == SORT_TILE) {
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        int64_t idx = base + w * WAVE_ITEMS + r * TG_WAVE + l;
-        if (idx < n) {
-            k[r] = kin[so + idx];
-            val[r] = vin ? vin[so + idx] : (uint32_t)idx;
-            atomicAdd(&woff[w][(k[r] >> shift) & 255u], 1u);
+        for (int r = 0; r < SORT_ITEMS; ++r) k[r] = kin[so + i0 + r * TG_WAVE];
+        if (vin) {
+#pragma unroll
+            for (int r = 0; r < SORT_ITEMS; ++r) val[r] = vin[so + i0 + r * TG_WAVE];
         } else {
-            k[r] = 0;
-            val[r] = 0;
+#pragma unroll
+            for (int r = 0; r < SORT_ITEMS; ++r) val[r] = (uint32_t)(i0 + r * TG_WAVE);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < SORT_ITEMS; ++r) {
+            const int64_t idx = i0 + r * TG_WAVE;
+            k[r] = idx < n ? kin[so + idx] : 0u;
+            val[r] = idx < n ? (vin ? vin[so + idx] : (uint32_t)idx) : 0u;
         }
     }
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r)
+        if (i0 + r * TG_WAVE < n) atomicAdd(&woff[w][(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     {
         // thread t < 256 owns digit t: block-local start of the digit
