@@ -222,6 +222,16 @@ struct StoredViews {
         t = wn[o];
         return vflags[o];
     }
+    // the same in two halves: the loads (issued ahead), then the use
+    struct Rec {
+        float2 t;
+        uint8_t f;
+    };
+    __device__ __forceinline__ Rec fetch(int64_t o) const { return Rec{wn[o], vflags[o]}; }
+    __device__ __forceinline__ uint8_t screen_rec(const Rec& r, float2& t) const {
+        t = r.t;
+        return r.f;
+    }
     __device__ __forceinline__ uint8_t view(int64_t o, float2& t, float2& mu) const {
         const uint8_t f = screen(o, t);
         if (f == 1) mu = mu_new[o];
@@ -252,6 +262,19 @@ struct RecordViews {
     __device__ __forceinline__ uint8_t screen(int64_t o, float2& t) const {
         double th[6];
         return solve(o, t, th);
+    }
+    // the same in two halves: the record's loads (issued ahead), then the solve
+    struct Rec {
+        float4 a0, a1, a2, a3;
+        ushort4 r;
+    };
+    __device__ __forceinline__ Rec fetch(int64_t o) const {
+        return Rec{acc[4 * o], acc[4 * o + 1], acc[4 * o + 2], acc[4 * o + 3], rect[o]};
+    }
+    __device__ __forceinline__ uint8_t screen_rec(const Rec& q, float2& t) const {
+        double th[6];
+        t = make_float2(q.a0.x, q.a3.x);
+        return solve_record(q.a0, q.a1, q.a2, q.a3, !(q.r.z > q.r.x && q.r.w > q.r.y), *prm, th);
     }
     __device__ __forceinline__ uint8_t view(int64_t o, float2& t, float2& mu) const {
         double th[6];
@@ -518,21 +541,10 @@ __device__ __forceinline__ void tri_one(const Src& src, const GaussIO& a, const 
     if (a.status) a.status[g] = st;
 }
 
-// The totals that decide whether Gaussian g is a candidate at all (views
-// solved, accumulated alpha, pixels); a non-candidate is copied and done.
-template <class Src>
-__device__ __forceinline__ uint32_t tri_light(const Src& src, const GaussIO& a, const tg_params& prm, int64_t g) {
-    int nv = 0;
-    bool nonfinite = false;
-    double sw = 0.0, nt = 0.0;
-    for (int v = 0; v < a.V; ++v) {
-        float2 t;
-        const uint8_t f = src.screen((int64_t)v * a.N + g, t);
-        sw += (double)t.x;
-        nt += (double)t.y;
-        if (f == 1) ++nv;
-        if (f & 32) nonfinite = true;
-    }
+// Status from the totals that decide whether a Gaussian is a candidate at
+// all (views solved, accumulated alpha, pixels); a non-candidate is copied
+// and done.
+__device__ __forceinline__ uint32_t light_status(int nv, double sw, double nt, bool nonfinite, const tg_params& prm) {
     uint32_t st = nonfinite ? 256u : 0u;
     if (nv < prm.views_min) st |= 4;
     if (!(sw >= prm.wsum_total_min)) st |= 8;
@@ -547,6 +559,7 @@ __device__ __forceinline__ uint32_t tri_light(const Src& src, const GaussIO& a, 
 constexpr int TRI_THREADS = 256;
 constexpr int TRI_ITEMS = 8;
 constexpr int TRI_SPAN = TRI_THREADS * TRI_ITEMS;
+constexpr int TRI_GROUP = 4;   // records in flight together in the screen
 
 template <class Src>
 __device__ __forceinline__ void tri_block(const Src& src, const GaussIO& a, const tg_camera* cams,
@@ -555,10 +568,50 @@ __device__ __forceinline__ void tri_block(const Src& src, const GaussIO& a, cons
     const int t = threadIdx.x;
     if (t == 0) cn = 0;
     __syncthreads();
+    // Screen: views outer, the thread's Gaussians inner in groups of
+    // TRI_GROUP, so the group's records of one view are in flight together
+    // (a view loop per Gaussian waits out one round trip per record).  The
+    // totals add in view order, as one Gaussian's loop would.
+    int nv[TRI_ITEMS];
+    bool nonfinite[TRI_ITEMS];
+    double sw[TRI_ITEMS], nt[TRI_ITEMS];
+#pragma unroll
+    for (int it = 0; it < TRI_ITEMS; ++it) {
+        nv[it] = 0;
+        nonfinite[it] = false;
+        sw[it] = 0.0;
+        nt[it] = 0.0;
+    }
+    for (int v = 0; v < a.V; ++v) {
+#pragma unroll
+        for (int i0 = 0; i0 < TRI_ITEMS; i0 += TRI_GROUP) {
+            typename Src::Rec r[TRI_GROUP];
+            // unconditional loads (past N: the last Gaussian's, unused), so
+            // they issue together
+#pragma unroll
+            for (int j = 0; j < TRI_GROUP; ++j) {
+                const int64_t g = base + (int64_t)(i0 + j) * TRI_THREADS + t;
+                r[j] = src.fetch((int64_t)v * a.N + (g < a.N ? g : a.N - 1));
+            }
+#pragma unroll
+            for (int j = 0; j < TRI_GROUP; ++j) {
+                const int64_t g = base + (int64_t)(i0 + j) * TRI_THREADS + t;
+                if (g < a.N) {
+                    float2 tt;
+                    const uint8_t f = src.screen_rec(r[j], tt);
+                    sw[i0 + j] += (double)tt.x;
+                    nt[i0 + j] += (double)tt.y;
+                    if (f == 1) ++nv[i0 + j];
+                    if (f & 32) nonfinite[i0 + j] = true;
+                }
+            }
+        }
+    }
+#pragma unroll
     for (int it = 0; it < TRI_ITEMS; ++it) {
         const int64_t g = base + (int64_t)it * TRI_THREADS + t;
         if (g >= a.N) break;
-        uint32_t st = tri_light(src, a, prm, g);
+        uint32_t st = light_status(nv[it], sw[it], nt[it], nonfinite[it], prm);
         if ((st & ~256u) == 0) {
             cand[atomicAdd(&cn, 1u)] = (uint32_t)(g - base);
         } else {
