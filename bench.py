@@ -3,7 +3,7 @@
 
 One step = one cold frame of the whole hot path on one batch of synthetic
 input already resident in HBM:
-    tg_preprocess -> tg_bin_sort -> (zero accumulators) -> tg_splat_accumulate
+    tg_preprocess -> tg_bin_sort -> tg_acc_zero -> tg_splat_accumulate
     -> tg_solve_triangulate (the per-view solves and the multi-view update in
        one launch)
 for 1M Gaussians x 20 views x 1920x1080 (the paper-shaped "large" workload:
@@ -469,7 +469,7 @@ def main():
         mark(1)
         mt.bin_sort(check_overflow=False)
         mark(2)
-        mt.acc.zero_()
+        api.acc_zero(mt.acc)
         mark(3)
         api.splat_accumulate(mt.splats, mt.bins, N, mt.cams_host, disp, vis, mt.params, mt.acc)
         mark(4)
@@ -512,8 +512,7 @@ def main():
             with torch.cuda.stream(streams[i]):
                 m.preprocess(g)
                 m.bin_sort(check_overflow=False)
-                m.acc.zero_()
-                api.splat_accumulate(m.splats, m.bins, N, m.cams_host, disp, vis, m.params, m.acc)
+                m.accumulate(disp, vis)
                 m.update(g, o)
 
         torch.cuda.synchronize()
@@ -566,7 +565,7 @@ def main():
 
         def clip_step():
             for a in accs:
-                a.zero_()
+                api.acc_zero(a)
             api.splat_accumulate_batch(
                 [dict(splats=mt.splats, bins=mt.bins, n=N, cams=mt.cams_host, disp=disps[i:i + 4], vis=[vis] * 4,
                       acc=accs[i:i + 4]) for i in (0, 4)], mt.params)

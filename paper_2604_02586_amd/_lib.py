@@ -111,6 +111,7 @@ def lib():
         "tg_num_cells": ([P, c_i32, c_i64, P], c_i64),
         "tg_num_tiles": ([P, c_i32], c_i64),
         "tg_preprocess": ([P, c_i64, P, c_i32, P, P, P], st),
+        "tg_acc_zero": ([P, c_i64, P], st),
         "tg_bin_sort": ([P, c_i64, P, c_i32, P, P, P, P, P], st),
         "tg_bin_sort_static": ([P, c_i64, P, c_i32, P, P, P], st),
         "tg_splat_accumulate": ([P, P, c_i64, P, c_i32, P, P, P, P, P, P, P], st),
@@ -154,7 +155,7 @@ def lib():
 
 def exported_symbols():
     return [n for n in ("tg_abi_version", "tg_status_string", "tg_default_params", "tg_num_cells",
-                        "tg_num_tiles", "tg_preprocess", "tg_bin_sort", "tg_bin_sort_static", "tg_splat_accumulate",
+                        "tg_num_tiles", "tg_preprocess", "tg_acc_zero", "tg_bin_sort", "tg_bin_sort_static", "tg_splat_accumulate",
                         "tg_splat_accumulate_batch", "tg_regularize", "tg_solve_views", "tg_triangulate",
                         "tg_solve_triangulate", "tg_solve_triangulate_batch", "tg_bin_expand", "tg_raster_fwd", "tg_raster_bwd",
                         "tg_raster_fwd_counted", "tg_raster_bwd_counted",

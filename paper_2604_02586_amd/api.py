@@ -123,6 +123,13 @@ def preprocess(g: GaussianTensors, cams, params, out: SplatTensors, stream=None)
                                                ctypes.byref(oc), stream_ptr(stream)))
 
 
+def acc_zero(acc: torch.Tensor, stream=None):
+    """tg_acc_zero over every record of `acc` ([..., 16] float32)."""
+    if acc.dtype != torch.float32 or acc.numel() % 16:
+        raise ValueError("acc must be float32 records of 16")
+    check("tg_acc_zero", lib().tg_acc_zero(_ptr(acc), acc.numel() // 16, stream_ptr(stream)))
+
+
 def bin_sort_ws_bytes(n, cams, params, capacity) -> int:
     cams = cams if isinstance(cams, ctypes.Array) else _lib.cameras(cams)
     sc = _lib.Splats()
@@ -368,7 +375,7 @@ class MotionTransfer:
                 bin_sort(self.splats, self.N, self.cams_host, self.params, self.bins, self.ws)
 
     def accumulate(self, disp, vis=None, t_final=False, stats=False):
-        self.acc.zero_()
+        acc_zero(self.acc)
         if t_final and self.t_final is None:
             self.t_final = torch.empty(self.V, self.H, self.W, dtype=torch.float32, device=self.device)
         if stats:

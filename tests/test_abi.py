@@ -70,6 +70,11 @@ def test_host_side_validation(L):
     g.scale_mode = 3
     s.rec = ctypes.c_void_p(0x10000)
     assert L.tg_preprocess(ctypes.byref(g), 10, cams, 2, ctypes.byref(p), ctypes.byref(s), None) == 1
+    # accumulator clearing: negative counts, null or misaligned records
+    assert L.tg_acc_zero(fake, -1, None) == 1
+    assert L.tg_acc_zero(None, 5, None) == 1
+    assert L.tg_acc_zero(ctypes.c_void_p(0x10004), 5, None) == 2
+    assert L.tg_acc_zero(None, 0, None) == 0
     # too many views for binning
     big = _cams(33)
     b = _lib.Bins()

@@ -54,3 +54,16 @@ def test_solve_views_parity(pair):
 
 def test_end_to_end_parity(pair):
     check_end_to_end(*pair)
+
+
+
+@pytest.mark.parametrize("records", [0, 1001, 3_000_000])
+def test_acc_zero_clears_every_record(records):
+    import torch
+    from paper_2604_02586_amd import api
+    log(f"[acc_zero records={records}]")
+    a = torch.full((records + 1, 16), float("nan"), dtype=torch.float32, device="cuda:0")
+    api.acc_zero(a[:records])
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(a[:records].view(torch.int32)).item()) == 0
+    assert bool(torch.isnan(a[records]).all())      # the record past the end is untouched
