@@ -249,10 +249,12 @@ tg_status tg_bin_sort_static(const tg_splats* s, int64_t N, const tg_camera* cam
  * disp: device [V,H,W,2] float32 (x' - x in pixels).  vis: device [V,H,W]
  * uint8 or NULL (all visible).  All views must share one resolution.
  * acc: device [V,N,16] float32, zeroed by the caller (results are added).
- * t_final: device [V,H,W] or NULL: final transmittance per pixel.
+ * t_final: device [V,H,W] or NULL: final transmittance per pixel.  With
+ * t_final NULL, a pixel whose track is hidden (vis 0) is not visited at all:
+ * it adds to no sum, and only t_final would need its transmittance.
  * stats: device int64 [4] or NULL: adds (pairs evaluated, pairs
  * contributing, pixel steps, list refill rounds) over the launch.  Evaluated pairs count the
- * depth-ordered list entries visited up to each pixel's termination, after
+ * depth-ordered list entries visited up to each visited pixel's termination, after
  * exact culling of Gaussians whose alpha stays below alpha_min on the whole
  * tile; a pixel step evaluates one pixel against up to 64 Gaussians.
  * Counting is a diagnostic: each wave adds its counts with atomics on the

@@ -173,6 +173,7 @@ k_accumulate(BatchArgs a)
     // pixel state: pixel j = g*64 + lane -> (px0 + (j&15), py0 + (j>>4));
     // flags of pixel j: bit f = track visible in frame f, bit 8+f = static
     // in frame f
+    constexpr uint32_t VISM = (1u << FM) - 1u;   // track-visible bits of the frames
     uint64_t alive[4];
     uint32_t flg[4];
     // tracks of pixel g*64 + lane per frame (in registers for several frames,
@@ -211,14 +212,15 @@ k_accumulate(BatchArgs a)
         }
         if constexpr (FM > 1) PR[j].x = 1.0f;
         flg[g] = fl;
-        alive[g] = ballot64(in);
+        // a pixel whose track is hidden in every frame adds to no sum, so
+        // unless its final transmittance is asked for it is never visited
+        alive[g] = ballot64(in && (S.t_final != nullptr || (fl & VISM) != 0u));
     }
     uint64_t n_eval = 0, n_contrib = 0, n_iter = 0, n_refill = 0;
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min;
     const float log_amin = __logf(amin);
     const uint64_t ltmask = lanemask_lt();
     const bool lane0 = lane == 0;
-    constexpr uint32_t VISM = (1u << FM) - 1u;
     float pex_reg = 1.0f;   // lane 0 is never written by the wave shift below
     int qn = 0, cn = 0;
     uint32_t pos = rg.x;

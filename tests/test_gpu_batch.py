@@ -64,8 +64,11 @@ def batch():
         for f in range(c.disp.shape[0]):
             acc = torch.zeros_like(sl["acc"][f])
             st = torch.zeros(4, dtype=torch.int64, device=dev)
+            # with t_final every pixel is visited, as in the batch (which
+            # asks for t_final), so the pair counts compare one to one
             api.splat_accumulate(mt.splats, mt.bins, c.scene.n, mt.cams_host, sl["disp"][f].contiguous(),
-                                 sl["vis"][f].contiguous(), mt.params, acc, stats=st)
+                                 sl["vis"][f].contiguous(), mt.params, acc,
+                                 t_final=torch.zeros_like(sl["t_final"]), stats=st)
             if f == 0:
                 single_stats += st
             accs.append(acc)

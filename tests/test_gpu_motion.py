@@ -67,3 +67,39 @@ def test_acc_zero_clears_every_record(records):
     torch.cuda.synchronize()
     assert int(torch.count_nonzero(a[:records].view(torch.int32)).item()) == 0
     assert bool(torch.isnan(a[records]).all())      # the record past the end is untouched
+
+
+def test_hidden_track_pixels_skipped_without_t_final():
+    """Without t_final, pixels whose track is hidden are never visited: the
+    accumulators are the same (up to the order of the FP32 atomics) and the
+    counters drop by those pixels' work."""
+    import torch
+    from paper_2604_02586_amd import api
+    dev = torch.device("cuda:0")
+    log("[hidden-track pixels]")
+    wl = _workload("ragged")
+    vis = (np.random.default_rng(3).random(np.asarray(wl.vis).shape) < 0.9).astype(np.uint8)
+    hidden = float((vis == 0).mean())
+    assert hidden > 0.05, hidden
+    g = api.GaussianTensors.from_scene(wl.scene, dev)
+    mt = api.MotionTransfer(wl.cams, wl.scene.n, dev)
+    d = torch.as_tensor(wl.disp).to(dev).contiguous()
+    vv = torch.as_tensor(vis).to(dev).contiguous()
+    mt.preprocess(g)
+    mt.bin_sort()
+    mt.accumulate(d, vv, t_final=True, stats=True)
+    torch.cuda.synchronize()
+    acc_t, st_t = mt.acc.cpu().numpy(), mt.stats.cpu().numpy().copy()
+    mt.accumulate(d, vv, t_final=False, stats=True)
+    torch.cuda.synchronize()
+    acc_n, st_n = mt.acc.cpu().numpy(), mt.stats.cpu().numpy().copy()
+    scale = np.abs(acc_t).max(axis=(0, 1)) + 1e-30
+    assert (np.abs(acc_n - acc_t) <= 1e-5 * scale).all()
+    log(f"  hidden {hidden:.3f}; evaluated {st_t[0]} -> {st_n[0]}, pixel steps {st_t[2]} -> {st_n[2]}")
+    assert st_n[0] < st_t[0] and st_n[1] < st_t[1] and st_n[2] < st_t[2]
+    # with every track visible, every pixel is visited again: the same walk
+    # as with t_final (termination does not depend on visibility)
+    mt.accumulate(d, None, t_final=False, stats=True)
+    torch.cuda.synchronize()
+    st_a = mt.stats.cpu().numpy()
+    assert st_a[0] == st_t[0] and st_a[1] == st_t[1] and st_a[2] == st_t[2], (st_a, st_t)
