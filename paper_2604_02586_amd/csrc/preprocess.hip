@@ -12,6 +12,14 @@
 
 namespace {
 
+// Per-view constants of the Jacobian clamp (the half field of view times
+// j_clamp), formed once on the host with the same IEEE operations the
+// kernel would use (no contraction), so the results are unchanged.
+struct ClampPack {
+    float limx[TG_MAX_VIEWS], limy[TG_MAX_VIEWS];
+    double dlx[TG_MAX_VIEWS], dly[TG_MAX_VIEWS];
+};
+
 struct SplatOut {
     float4* rec;
     float* cov2d;
@@ -67,7 +75,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ means, const float* __restrict__ quats,
     const float* __restrict__ scales, const float* __restrict__ opac,
     const float* __restrict__ sh, int scale_mode, int opacity_mode,
-    int64_t N, int V, int64_t out_view0, CamPack cams, tg_params prm, SplatOut out)
+    int64_t N, int V, int64_t out_view0, CamPack cams, ClampPack clampk, tg_params prm, SplatOut out)
 {
 #pragma clang fp contract(off)
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -154,8 +162,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
             float ux = px / pz, uy = py / pz;
             float mx = c.fx * ux + c.cx;
             float my = c.fy * uy + c.cy;
-            float limx = prm.j_clamp * ((0.5f * (float)c.width) / c.fx);
-            float limy = prm.j_clamp * ((0.5f * (float)c.height) / c.fy);
+            const float limx = clampk.limx[v], limy = clampk.limy[v];
             float tx = fminf(limx, fmaxf(-limx, ux));
             float ty = fminf(limy, fmaxf(-limy, uy));
             float j00 = c.fx / pz, j02 = -(c.fx * tx) / pz;
@@ -207,8 +214,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
                         // (each result is rounded to FP32 once afterwards)
                         const double idz = 1.0 / dpz;
                         double dtx = dpx * idz, dty = dpy * idz;
-                        double dlx = (double)prm.j_clamp * (0.5 * c.width / (double)c.fx);
-                        double dly = (double)prm.j_clamp * (0.5 * c.height / (double)c.fy);
+                        const double dlx = clampk.dlx[v], dly = clampk.dly[v];
                         dtx = fmin(dlx, fmax(-dlx, dtx));
                         dty = fmin(dly, fmax(-dly, dty));
                         double J00 = c.fx * idz, J02 = -c.fx * dtx * idz;
@@ -300,12 +306,21 @@ extern "C" tg_status tg_preprocess(const tg_gaussians* g, int64_t N, const tg_ca
     for (int v0 = 0; v0 < V; v0 += TG_MAX_VIEWS) {
         int nv = V - v0 < TG_MAX_VIEWS ? V - v0 : TG_MAX_VIEWS;
         CamPack cp;
-        for (int i = 0; i < nv; ++i) cp.cam[i] = cams[v0 + i];
+        ClampPack cl;
+        for (int i = 0; i < nv; ++i) {
+#pragma clang fp contract(off)
+            const tg_camera& c = cams[v0 + i];
+            cp.cam[i] = c;
+            cl.limx[i] = p->j_clamp * ((0.5f * (float)c.width) / c.fx);
+            cl.limy[i] = p->j_clamp * ((0.5f * (float)c.height) / c.fy);
+            cl.dlx[i] = (double)p->j_clamp * (0.5 * c.width / (double)c.fx);
+            cl.dly[i] = (double)p->j_clamp * (0.5 * c.height / (double)c.fy);
+        }
         const int deg = (g->sh && out->colors) ? g->sh_degree : -1;
 #define TG_PRE_LAUNCH(D)                                                                                        \
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_preprocess<D>), dim3((unsigned)blocks), dim3(threads), 0, s, g->means, \
                        g->quats, g->scales, g->opacity, g->sh, g->scale_mode, g->opacity_mode, N, nv, (int64_t)v0, \
-                       cp, *p, so)
+                       cp, cl, *p, so)
         switch (deg) {
             case 0: TG_PRE_LAUNCH(0); break;
             case 1: TG_PRE_LAUNCH(1); break;
