@@ -242,6 +242,12 @@ struct StoredViews {
         co[1] = cov_new[3 * o + 1];
         co[2] = cov_new[3 * o + 2];
     }
+    // view() and, for a solved view, cov() at once
+    __device__ __forceinline__ uint8_t view_cov(int64_t o, float2& t, float2& mu, float co[3]) const {
+        const uint8_t f = view(o, t, mu);
+        if (f == 1) cov(o, co);
+        return f;
+    }
 };
 
 // Per-view results solved on the fly from the accumulator records (the
@@ -291,13 +297,30 @@ struct RecordViews {
         solve(o, t, th);
         moved_cov(th, cov2d[3 * o], cov2d[3 * o + 1], cov2d[3 * o + 2], co);
     }
+    // view() and, for a solved view, cov() from the same solve
+    __device__ __forceinline__ uint8_t view_cov(int64_t o, float2& t, float2& mu, float co[3]) const {
+        double th[6];
+        const uint8_t f = solve(o, t, th);
+        if (f == 1) {
+            const float4 rc = rec[2 * o];
+            mu = moved_centre(th, rc.x, rc.y);
+            moved_cov(th, cov2d[3 * o], cov2d[3 * o + 1], cov2d[3 * o + 2], co);
+        }
+        return f;
+    }
 };
 
+// Solved views whose Sigma' the DLT loop keeps in LDS for the covariance
+// loop (views past these are solved again there): 20 x 3 floats x 256
+// threads = 60 KB per block, so the two blocks a CU holds (252 VGPRs) fit.
+constexpr int TRI_COV_SLOTS = 20;
+
 // The full multi-view update of Gaussian g from the per-view results of
-// `src`; cams holds the V cameras.
+// `src`; cams holds the V cameras.  covs: this thread's LDS slots, slot k
+// component c at covs[(3 * k + c) * stride].
 template <class Src>
 __device__ __forceinline__ void tri_one(const Src& src, const GaussIO& a, const tg_camera* cams,
-                                        const tg_params& prm, int64_t g)
+                                        const tg_params& prm, int64_t g, float* covs, int stride)
 {
     const float om0 = a.means_in[3 * g], om1 = a.means_in[3 * g + 1], om2 = a.means_in[3 * g + 2];
     const float oq0 = a.quats_in[4 * g], oq1 = a.quats_in[4 * g + 1], oq2 = a.quats_in[4 * g + 2],
@@ -319,11 +342,16 @@ __device__ __forceinline__ void tri_one(const Src& src, const GaussIO& a, const 
         const int64_t o = (int64_t)v * a.N + g;
         // culled views accumulate nothing, so their totals are zero
         float2 t, mu;
-        const uint8_t f = src.view(o, t, mu);
+        float co[3];
+        const uint8_t f = nv < TRI_COV_SLOTS ? src.view_cov(o, t, mu, co) : src.view(o, t, mu);
         sw += (double)t.x;
         nt += (double)t.y;
         if (f & 32) st |= 256;
         if (f != 1) continue;
+        if (nv < TRI_COV_SLOTS) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) covs[(3 * nv + c) * stride] = co[c];
+        }
         ++nv;
         solved |= 1u << v;
         const tg_camera& c = cams[v];
@@ -378,7 +406,8 @@ __device__ __forceinline__ void tri_one(const Src& src, const GaussIO& a, const 
             for (int i = 0; i < 36; ++i) AtA[i] = 0.0;
 #pragma unroll
             for (int i = 0; i < 6; ++i) Atb[i] = 0.0;
-            for (uint32_t m = solved; m; m &= m - 1) {
+            int k = 0;   // solved views so far, in view order
+            for (uint32_t m = solved; m; m &= m - 1, ++k) {
                 const int v = __builtin_ctz(m);
                 const int64_t o = (int64_t)v * a.N + g;
                 const tg_camera& c = cams[v];
@@ -400,7 +429,12 @@ __device__ __forceinline__ void tri_one(const Src& src, const GaussIO& a, const 
                     T1[j] = J11 * c.R[3 + j] + J12 * c.R[6 + j];
                 }
                 float co[3];
-                src.cov(o, co);
+                if (k < TRI_COV_SLOTS) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) co[e] = covs[(3 * k + e) * stride];
+                } else {
+                    src.cov(o, co);
+                }
                 const double rhs[3] = {co[0], co[1], co[2]};
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
@@ -565,7 +599,8 @@ constexpr int TRI_GROUP = 4;   // records in flight together in the screen
 
 template <class Src>
 __device__ __forceinline__ void tri_block(const Src& src, const GaussIO& a, const tg_camera* cams,
-                                          const tg_params& prm, int64_t base, uint32_t* cand, uint32_t& cn)
+                                          const tg_params& prm, int64_t base, uint32_t* cand, uint32_t& cn,
+                                          float* covs)
 {
     const int t = threadIdx.x;
     if (t == 0) cn = 0;
@@ -641,14 +676,15 @@ __device__ __forceinline__ void tri_block(const Src& src, const GaussIO& a, cons
     }
     __syncthreads();
     const uint32_t n = cn;
-    for (uint32_t i = t; i < n; i += TRI_THREADS) tri_one(src, a, cams, prm, base + cand[i]);
+    for (uint32_t i = t; i < n; i += TRI_THREADS) tri_one(src, a, cams, prm, base + cand[i], covs + t, TRI_THREADS);
 }
 
 __global__ void __launch_bounds__(TRI_THREADS) k_triangulate(StoredViews src, GaussIO a, CamPack cams, tg_params prm)
 {
     __shared__ uint32_t cand[TRI_SPAN];
     __shared__ uint32_t cn;
-    tri_block(src, a, cams.cam, prm, (int64_t)blockIdx.x * TRI_SPAN, cand, cn);
+    __shared__ float covs[TRI_COV_SLOTS * 3 * TRI_THREADS];
+    tri_block(src, a, cams.cam, prm, (int64_t)blockIdx.x * TRI_SPAN, cand, cn, covs);
 }
 
 // ---- fused per-view solve + multi-view update, batched over Gaussian sets
@@ -686,12 +722,13 @@ struct UpdBatchK {
 };
 
 __device__ __forceinline__ void update_item(const UpdSlotK& sl, const UpdFrameK& fr, const tg_camera* lcam,
-                                            const tg_params& prm, int64_t blk, uint32_t* cand, uint32_t& cn)
+                                            const tg_params& prm, int64_t blk, uint32_t* cand, uint32_t& cn,
+                                            float* covs)
 {
     RecordViews src{fr.acc, sl.rec, sl.cov2d, sl.rect, &prm};
     GaussIO a{sl.means_in, sl.quats_in, sl.scales_in, sl.opacity_in, fr.means_out, fr.quats_out, fr.scales_out,
               fr.status, sl.N, sl.V, sl.scale_mode};
-    tri_block(src, a, lcam, prm, blk * TRI_SPAN, cand, cn);
+    tri_block(src, a, lcam, prm, blk * TRI_SPAN, cand, cn, covs);
 }
 
 // One frame; cameras in the kernel arguments.
@@ -699,7 +736,8 @@ __global__ void __launch_bounds__(TRI_THREADS) k_update_one(UpdSlotK sl, UpdFram
 {
     __shared__ uint32_t cand[TRI_SPAN];
     __shared__ uint32_t cn;
-    update_item(sl, fr, cams.cam, prm, blockIdx.x, cand, cn);
+    __shared__ float covs[TRI_COV_SLOTS * 3 * TRI_THREADS];
+    update_item(sl, fr, cams.cam, prm, blockIdx.x, cand, cn, covs);
 }
 
 // Several (Gaussian set, frame) items; each set's cameras are copied from
@@ -709,6 +747,7 @@ __global__ void __launch_bounds__(TRI_THREADS) k_update_batch(UpdBatchK b, tg_pa
     __shared__ uint32_t cand[TRI_SPAN];
     __shared__ uint32_t cn;
     __shared__ tg_camera lcam[TG_MAX_VIEWS];
+    __shared__ float covs[TRI_COV_SLOTS * 3 * TRI_THREADS];
     int k = 0;
     while (k + 1 < b.n_fr && b.fr[k + 1].blk0 <= (int32_t)blockIdx.x) ++k;
     const UpdFrameK& fr = b.fr[k];
@@ -720,7 +759,7 @@ __global__ void __launch_bounds__(TRI_THREADS) k_update_batch(UpdBatchK b, tg_pa
         for (int i = threadIdx.x; i < nw; i += TRI_THREADS) dst[i] = src[i];
     }
     __syncthreads();
-    update_item(sl, fr, lcam, prm, (int64_t)blockIdx.x - fr.blk0, cand, cn);
+    update_item(sl, fr, lcam, prm, (int64_t)blockIdx.x - fr.blk0, cand, cn, covs);
 }
 
 tg_status check_gauss(const tg_gaussians* g, bool in) {
