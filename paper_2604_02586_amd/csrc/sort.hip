@@ -295,9 +295,14 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(uint32_t* __restrict
 // the thread totals, then writes back.  Replaces the three-kernel scan when
 // the segments are small (the radix histograms of per-view depth sorts).
 template <int ITEMS>
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_seg(uint32_t* __restrict__ data, int64_t L)
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_seg(uint32_t* __restrict__ data, int64_t L,
+                                                           const uint32_t* __restrict__ seginfo, int skip, int bit0,
+                                                           int top_shift)
 {
     static_assert(ITEMS % 4 == 0, "16-byte chunks");
+    // the last pass of a segment whose top digit is constant scatters
+    // nothing, so its histogram needs no scan either
+    if (skip && top_constant(seginfo, blockIdx.x, bit0, top_shift)) return;   // block-uniform
     __shared__ uint32_t tot;
     uint32_t* d = data + (int64_t)blockIdx.x * L;
     const int64_t i0 = (int64_t)threadIdx.x * ITEMS;
@@ -539,11 +544,14 @@ tg_status tg_radix_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, 
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_radix_hist<false, false>), dim3(nblk, nseg), dim3(SORT_THREADS), 0,
                                s, ck, seg_len, dev_count, shift, hist, nblk, seginfo, 0, bit0, top_shift);
         if (L <= (int64_t)SCAN_THREADS * 16) {
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<16>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<16>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L,
+                               seginfo, mode & MODE_SKIP, bit0, top_shift);
         } else if (L <= (int64_t)SCAN_THREADS * 32) {
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<32>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<32>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L,
+                               seginfo, mode & MODE_SKIP, bit0, top_shift);
         } else if (L <= (int64_t)SCAN_THREADS * 64) {
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<64>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_seg<64>), dim3(nseg), dim3(SCAN_THREADS), 0, s, hist, L,
+                               seginfo, mode & MODE_SKIP, bit0, top_shift);
         } else {
             hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk, nseg), dim3(SCAN_THREADS), 0, s, hist, L, sums, nchunk);
             hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(SCAN_THREADS), 0, s, sums, nchunk);
