@@ -248,7 +248,9 @@ tg_status tg_bin_sort_static(const tg_splats* s, int64_t N, const tg_camera* cam
  *
  * disp: device [V,H,W,2] float32 (x' - x in pixels).  vis: device [V,H,W]
  * uint8 or NULL (all visible).  All views must share one resolution.
- * acc: device [V,N,16] float32, zeroed by the caller (results are added).
+ * acc: device [V,N,16] float32, zeroed by the caller (results are added);
+ * no other stream may read or write it until the launch completes (an
+ * unsynchronised reader on another stream has cost additions here).
  * t_final: device [V,H,W] or NULL: final transmittance per pixel.  With
  * t_final NULL, a pixel whose track is hidden (vis 0) is not visited at all:
  * it adds to no sum, and only t_final would need its transmittance.
