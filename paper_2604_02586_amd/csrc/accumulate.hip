@@ -129,7 +129,10 @@ template <int FM, bool STATS>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FM == 1 ? 7 : 1, 8)))
 k_accumulate(BatchArgs a)
 {
-    // 5.7 KB of LDS per wave (7 waves per SIMD fit): queues of candidate
+    // 5.5 KB of LDS per wave, allocated as 6 KB (512-byte granules), so 26
+    // waves share a CU (the VGPRs would allow 28; a 5.5 KB variant that let
+    // them in ran no faster, the VALU issuing every cycle already): queues
+    // of candidate
     // and filtered list entries (ids), per-pixel records (transmittance, and for one frame the
     // track; a row of them is held in registers while the row is visited)
     // and the atomics' transpose buffer
