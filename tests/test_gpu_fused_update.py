@@ -37,6 +37,9 @@ def _same_bits(a, b):
 CASES = {
     "lite": dict(name="medium", seed=5, n=20000, views=5, width=420, height=300),
     "outliers": dict(name="large", seed=41, n=30000, views=6, width=640, height=360),
+    # more views than the update keeps Sigma' for in LDS (20): the views past
+    # those are solved a second time in the covariance loop
+    "many_views": dict(name="medium", seed=9, n=6000, views=28, width=256, height=192),
 }
 
 
@@ -56,6 +59,11 @@ def test_fused_equals_two_calls_and_oracle(case):
     fused = _host(go, st)
     same = _same_bits(fused, gpu)
     log(f"[fused {case}] bit-identical to the two-call path: {same.sum()} / {same.size}")
+    if len(wl.cams) > 20:
+        nsolved = (gpu["vflags"] == 1).sum(axis=0)
+        many = int(((nsolved > 20) & ((gpu["status"] & 1) != 0)).sum())
+        log(f"[fused {case}] updated Gaussians with more than 20 solved views: {many}")
+        assert many > 0
     ref = oracle_full(wl)
     sens = check_end_to_end(f"fused {case}", wl, ref, fused)
     # the two paths do the same FP64 arithmetic; they may differ only where
