@@ -273,7 +273,8 @@ tg_status tg_splat_accumulate(const tg_splats* s, const tg_bins* bins, int64_t N
  * into (Sec. 4.3.3, Eq. 4).  acc: device float32, 16-byte aligned (NULL
  * allowed when n_records is 0).  One 16-byte store per thread over as many
  * workgroups as it takes (the layout that reaches the highest HBM write rate
- * for a fill).  Errors: TG_ERR_INVALID_ARG for n_records < 0 or a null acc;
+ * for a fill).  Errors: TG_ERR_INVALID_ARG for n_records < 0 (or so large
+ * that its bytes overflow int64) or a null acc;
  * TG_ERR_ALIGNMENT; TG_ERR_DEVICE on a failed launch.
  */
 tg_status tg_acc_zero(float* acc, int64_t n_records, void* stream);

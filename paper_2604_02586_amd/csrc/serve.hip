@@ -680,7 +680,7 @@ struct tg_server {
 // ---------------------------------------------------------------- C ABI
 extern "C" tg_status tg_acc_zero(float* acc, int64_t n_records, void* stream)
 {
-    if (n_records < 0 || (n_records > 0 && !acc)) return TG_ERR_INVALID_ARG;
+    if (n_records < 0 || n_records > INT64_MAX / 64 || (n_records > 0 && !acc)) return TG_ERR_INVALID_ARG;
     if (n_records == 0) return TG_OK;
     if (!aligned16(acc)) return TG_ERR_ALIGNMENT;
     launch_zero16((float4*)acc, n_records * (TG_ACC_STRIDE / 4), (hipStream_t)stream);

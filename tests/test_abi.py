@@ -75,6 +75,7 @@ def test_host_side_validation(L):
     assert L.tg_acc_zero(None, 5, None) == 1
     assert L.tg_acc_zero(ctypes.c_void_p(0x10004), 5, None) == 2
     assert L.tg_acc_zero(None, 0, None) == 0
+    assert L.tg_acc_zero(fake, 2**62, None) == 1
     # too many views for binning
     big = _cams(33)
     b = _lib.Bins()
