@@ -179,13 +179,24 @@ __global__ void __launch_bounds__(256) k_reg_classify(RegArgs a) {
         // static: more than static_min_pix pixels, more than static_frac of
         // them static, in at least static_views views (decided in FP64 on the
         // exact integer counts)
+        // The pixel counts of each record (slots 12 and 13, one 8-byte load),
+        // eight views' loads issued together (views past V load the last
+        // view's record again, unused) before the tests, which take both
+        // comparisons without short-circuit so no load waits on another.
         int sv = 0;
-#pragma unroll 4
-        for (int v = 0; v < a.V; ++v) {
-            // the pixel counts of the record (slots 12 and 13), one 8-byte load
-            const float2 r = *(const float2*)(a.acc + ((int64_t)v * a.N + g) * TG_ACC_STRIDE + 12);
-            const double n = r.x, sn = r.y;
-            if (n > (double)a.static_min_pix && sn > a.static_frac * n) ++sv;
+        for (int v0 = 0; v0 < a.V; v0 += 8) {
+            float2 r[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int v = v0 + j < a.V ? v0 + j : a.V - 1;
+                r[j] = *(const float2*)(a.acc + ((int64_t)v * a.N + g) * TG_ACC_STRIDE + 12);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const double n = r[j].x, sn = r[j].y;
+                const bool is_static = (n > (double)a.static_min_pix) & (sn > a.static_frac * n);
+                sv += (v0 + j < a.V && is_static) ? 1 : 0;
+            }
         }
         const bool stat = sv >= a.static_views;
         const uint32_t st = a.status[g];
