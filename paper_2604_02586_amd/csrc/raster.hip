@@ -554,11 +554,23 @@ __global__ void __launch_bounds__(128) k_project_bwd(ProjArgs a, CamPack cams, t
     }
     for (int v = 0; v < a.V; ++v) {
         const int64_t o_ = (int64_t)v * a.N + g;
-        const ushort4 rc = a.rect[o_];
-        if (!(rc.z > rc.x && rc.w > rc.y)) continue;
+        // every load of the view issued before the culling test (a culled
+        // view reads its 40 unused bytes, but the view waits out one round
+        // trip instead of one per test)
+        const uint2 rr = *(const uint2*)(a.rect + o_);
         const float* gr = a.grad2d + o_ * 9;
-        const float gmx = gr[0], gmy = gr[1], gA = gr[2], gB = gr[3], gC = gr[4], gop = gr[5];
-        const float gcol[3] = {gr[6], gr[7], gr[8]};
+        float gv[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) gv[i] = gr[i];
+        uint8_t clp[3] = {0, 0, 0};
+        if (DEG >= 0 && a.clamped) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) clp[ch] = a.clamped[3 * o_ + ch];
+        }
+        const uint32_t rx0 = rr.x & 0xFFFFu, ry0 = rr.x >> 16, rx1 = rr.y & 0xFFFFu, ry1 = rr.y >> 16;
+        if (!((rx1 > rx0) & (ry1 > ry0))) continue;
+        const float gmx = gv[0], gmy = gv[1], gA = gv[2], gB = gv[3], gC = gv[4], gop = gv[5];
+        const float gcol[3] = {gv[6], gv[7], gv[8]};
         const tg_camera& c = cams.cam[v];
         const float* Rc = c.R;
         const float p0 = Rc[0] * m0 + Rc[1] * m1 + Rc[2] * m2 + c.t[0];
@@ -640,7 +652,7 @@ __global__ void __launch_bounds__(128) k_project_bwd(ProjArgs a, CamPack cams, t
             // clamped channels (colour = 0) pass no gradient
             float gc[3];
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) gc[ch] = (a.clamped && a.clamped[3 * o_ + ch]) ? 0.f : gcol[ch];
+            for (int ch = 0; ch < 3; ++ch) gc[ch] = clp[ch] ? 0.f : gcol[ch];
             float av[NB], Y[NB], gdir[3];
 #pragma unroll
             for (int k = 0; k < NB; ++k)
