@@ -644,35 +644,49 @@ __device__ __forceinline__ void tri_block(const Src& src, const GaussIO& a, cons
             }
         }
     }
+    // Candidates go to the LDS list; every other Gaussian is copied through
+    // (a Gaussian with a non-finite parameter is always copied, culled in
+    // every view).  All the copied items' loads come before the first
+    // store: the outputs may alias the inputs, so a store between loads
+    // would make each load wait for the one before.
+    float x[TRI_ITEMS][11];
+    uint32_t stc[TRI_ITEMS];
+    bool cp[TRI_ITEMS];
 #pragma unroll
     for (int it = 0; it < TRI_ITEMS; ++it) {
         const int64_t g = base + (int64_t)it * TRI_THREADS + t;
-        if (g >= a.N) break;
-        uint32_t st = light_status(nv[it], sw[it], nt[it], nonfinite[it], prm);
+        cp[it] = false;
+        stc[it] = 0;
+        if (g >= a.N) continue;
+        const uint32_t st = light_status(nv[it], sw[it], nt[it], nonfinite[it], prm);
         if ((st & ~256u) == 0) {
             cand[atomicAdd(&cn, 1u)] = (uint32_t)(g - base);
         } else {
-            // not updated: copied (a Gaussian with a non-finite parameter
-            // is always here, culled in every view)
-            bool fin = isfinite(a.opacity_in[g]);
-            for (int i = 0; i < 3; ++i) {
-                const float x = a.means_in[3 * g + i];
-                fin = fin && isfinite(x);
-                a.means_out[3 * g + i] = x;
-            }
-            for (int i = 0; i < 4; ++i) {
-                const float x = a.quats_in[4 * g + i];
-                fin = fin && isfinite(x);
-                a.quats_out[4 * g + i] = x;
-            }
-            for (int i = 0; i < 3; ++i) {
-                const float x = a.scales_in[3 * g + i];
-                fin = fin && isfinite(x);
-                a.scales_out[3 * g + i] = x;
-            }
-            if (!fin) st |= 256;
-            if (a.status) a.status[g] = st;
+            cp[it] = true;
+            stc[it] = st;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) x[it][k] = a.means_in[3 * g + k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[it][3 + k] = a.quats_in[4 * g + k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) x[it][7 + k] = a.scales_in[3 * g + k];
+            x[it][10] = a.opacity_in[g];
         }
+    }
+#pragma unroll
+    for (int it = 0; it < TRI_ITEMS; ++it) {
+        if (!cp[it]) continue;
+        const int64_t g = base + (int64_t)it * TRI_THREADS + t;
+        bool fin = true;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) fin &= isfinite(x[it][k]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.means_out[3 * g + k] = x[it][k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.quats_out[4 * g + k] = x[it][3 + k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.scales_out[3 * g + k] = x[it][7 + k];
+        if (a.status) a.status[g] = fin ? stc[it] : (stc[it] | 256u);
     }
     __syncthreads();
     const uint32_t n = cn;
