@@ -740,8 +740,18 @@ __global__ void __launch_bounds__(128) k_reg_filter(RegArgs a) {
 __global__ void __launch_bounds__(128) k_reg_apply(RegArgs a) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.N) return;
+    // Every load before the first store (the outputs may alias the inputs,
+    // so a store between loads would make each wait for the one before),
+    // and a target's neighbour ids all loaded before their changes.
     const uint8_t cl = a.cls[g];
     const int K = a.ncnt[g];
+    float m0v[3], q0v[4], s0v[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) m0v[i] = a.m0[3 * g + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q0v[i] = a.q0[4 * g + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s0v[i] = a.s0[3 * g + i];
     double d[9];
     uint32_t flag = 0;
     if (cl == CLS_STATIC) {
@@ -750,33 +760,48 @@ __global__ void __launch_bounds__(128) k_reg_apply(RegArgs a) {
         for (int c = 0; c < 9; ++c) d[c] = a.filt[g * 9 + c];
         flag = 2;
     } else if (cl == CLS_TARGET && K > 0) {
-        for (int c = 0; c < 9; ++c) d[c] = 0.0;
-        for (int k = 0; k < K; ++k) {
-            const int64_t nbk = a.nbr[g * KMAX + k];
-            for (int c = 0; c < 9; ++c) d[c] += a.filt[nbk * 9 + c];
+        // unused slots (k >= K) gather Gaussian 0's changes, never added:
+        // no load waits on a branch
+        uint32_t nb[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const uint32_t id = a.nbr[g * KMAX + k];
+            nb[k] = k < K ? id : 0u;
         }
+        float f[KMAX][9];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+            for (int c = 0; c < 9; ++c) f[k][c] = a.filt[(int64_t)nb[k] * 9 + c];
+        // the same summation order as one neighbour at a time
+        for (int c = 0; c < 9; ++c) d[c] = 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < K)
+#pragma unroll
+                for (int c = 0; c < 9; ++c) d[c] += f[k][c];
         for (int c = 0; c < 9; ++c) d[c] /= K;
         flag = 4;
     }
     a.reg[g] = flag;
     if (flag == 2 || flag == 4) {
-        for (int i = 0; i < 3; ++i) a.mo[3 * g + i] = (float)((double)a.m0[3 * g + i] + d[i]);
+        for (int i = 0; i < 3; ++i) a.mo[3 * g + i] = (float)((double)m0v[i] + d[i]);
         double Q[9], R0[9], R[9], q[4];
         rot_zyx(d[3], d[4], d[5], Q);
-        quat_rot64(a.q0 + 4 * g, R0);
+        quat_rot64(q0v, R0);
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j)
                 R[i * 3 + j] = Q[i * 3] * R0[j] + Q[i * 3 + 1] * R0[3 + j] + Q[i * 3 + 2] * R0[6 + j];
         rot_quat(R, q);
         for (int i = 0; i < 4; ++i) a.qo[4 * g + i] = (float)q[i];
         for (int i = 0; i < 3; ++i) {
-            const double s = (double)a.s0[3 * g + i] + d[6 + i];
-            a.so[3 * g + i] = s > 0 ? (float)s : a.s0[3 * g + i];
+            const double s = (double)s0v[i] + d[6 + i];
+            a.so[3 * g + i] = s > 0 ? (float)s : s0v[i];
         }
     } else {
-        for (int i = 0; i < 3; ++i) a.mo[3 * g + i] = a.m0[3 * g + i];
-        for (int i = 0; i < 4; ++i) a.qo[4 * g + i] = a.q0[4 * g + i];
-        for (int i = 0; i < 3; ++i) a.so[3 * g + i] = a.s0[3 * g + i];
+        for (int i = 0; i < 3; ++i) a.mo[3 * g + i] = m0v[i];
+        for (int i = 0; i < 4; ++i) a.qo[4 * g + i] = q0v[i];
+        for (int i = 0; i < 3; ++i) a.so[3 * g + i] = s0v[i];
     }
 }
 
