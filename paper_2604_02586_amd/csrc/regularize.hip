@@ -183,6 +183,7 @@ __global__ void __launch_bounds__(256) k_reg_classify(RegArgs a) {
         // eight views' loads issued together (views past V load the last
         // view's record again, unused) before the tests, which take both
         // comparisons without short-circuit so no load waits on another.
+        const uint32_t st = a.status[g];   // in flight with the counts
         int sv = 0;
         for (int v0 = 0; v0 < a.V; v0 += 8) {
             float2 r[8];
@@ -199,29 +200,43 @@ __global__ void __launch_bounds__(256) k_reg_classify(RegArgs a) {
             }
         }
         const bool stat = sv >= a.static_views;
-        const uint32_t st = a.status[g];
         const bool src = !stat && (st & 1u) && (st & 2u);
-        a.cls[g] = stat ? CLS_STATIC : (src ? CLS_SOURCE : CLS_TARGET);
         if (src) {
+            // every input loaded before the first store (the change array
+            // may alias them, and a store between loads would serialise them)
+            float q0v[4], q1v[4], m0v[3], m1v[3], s0v[3], s1v[3];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                q0v[i] = a.q0[4 * g + i];
+                q1v[i] = a.q1[4 * g + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                m0v[i] = a.m0[3 * g + i];
+                m1v[i] = a.m1[3 * g + i];
+                s0v[i] = a.s0[3 * g + i];
+                s1v[i] = a.s1[3 * g + i];
+            }
             double R0[9], R1[9], Q[9];
-            quat_rot64(a.q0 + 4 * g, R0);
-            quat_rot64(a.q1 + 4 * g, R1);
+            quat_rot64(q0v, R0);
+            quat_rot64(q1v, R1);
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j)
                     Q[i * 3 + j] = R1[i * 3] * R0[j * 3] + R1[i * 3 + 1] * R0[j * 3 + 1] + R1[i * 3 + 2] * R0[j * 3 + 2];
             float* d = a.delta + g * 9;
-            for (int i = 0; i < 3; ++i) d[i] = (float)((double)a.m1[3 * g + i] - (double)a.m0[3 * g + i]);
+            for (int i = 0; i < 3; ++i) d[i] = (float)((double)m1v[i] - (double)m0v[i]);
             d[3] = (float)atan2(Q[7], Q[8]);
             d[4] = (float)asin(fmin(1.0, fmax(-1.0, -Q[6])));
             d[5] = (float)atan2(Q[3], Q[0]);
-            for (int i = 0; i < 3; ++i) d[6 + i] = (float)((double)a.s1[3 * g + i] - (double)a.s0[3 * g + i]);
+            for (int i = 0; i < 3; ++i) d[6 + i] = (float)((double)s1v[i] - (double)s0v[i]);
             for (int i = 0; i < 3; ++i) {
-                const int32_t o = f2o(a.m0[3 * g + i]);
+                const int32_t o = f2o(m0v[i]);
                 atomicMin(&bmin[i], o);
                 atomicMax(&bmax[i], o);
             }
             atomicAdd(&bcnt, 1u);
         }
+        a.cls[g] = stat ? CLS_STATIC : (src ? CLS_SOURCE : CLS_TARGET);
     }
     __syncthreads();
     if (threadIdx.x == 0 && bcnt) {
