@@ -35,10 +35,10 @@ constexpr int DIRECT_BINS = 256;   // coarse bins per view for the direct placem
 constexpr int DIRECT_WIN = 2048;   // pairs per LDS window of the direct placement
 
 // Coarse-bin rectangle of Gaussian g's tile rectangle (empty when culled).
-__device__ __forceinline__ ushort4 coarse_rect(const ushort4* __restrict__ rect, int64_t vN, uint32_t g, int64_t N,
-                                               int cshift, uint32_t& cnt) {
-    const ushort4 r = g < (uint64_t)N ? rect[vN + g] : make_ushort4(0, 0, 0, 0);
-    if (!(r.z > r.x && r.w > r.y)) return make_ushort4(0, 0, 0, 0);
+// Coarse rectangle of a tile rectangle r (all zero when r is empty or the id
+// was invalid), counting its coarse bins into cnt.
+__device__ __forceinline__ ushort4 coarse_of(ushort4 r, bool valid, int cshift, uint32_t& cnt) {
+    if (!valid || !(r.z > r.x && r.w > r.y)) return make_ushort4(0, 0, 0, 0);
     const ushort4 c = make_ushort4((unsigned short)(r.x >> cshift), (unsigned short)(r.y >> cshift),
                                    (unsigned short)(((r.z - 1) >> cshift) + 1),
                                    (unsigned short)(((r.w - 1) >> cshift) + 1));
@@ -168,16 +168,25 @@ __global__ void __launch_bounds__(256) k_emit_count(const uint32_t* __restrict__
                     for (int x = c.x; x < c.z; ++x) atomicAdd(&hist[y * cw + x], 1u);
         }
     } else {
+        // every id, then every rectangle, in flight before the first store
+        // (a store between them would make each load wait for the one before)
+        uint32_t g[EMIT_ITEMS];
+        ushort4 c[EMIT_ITEMS];
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) g[i] = base + i * 256 < N ? order[vN + base + i * 256] : 0xFFFFFFFFu;
+        ushort4 r[EMIT_ITEMS];
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) r[i] = rect[vN + (g[i] < (uint64_t)N ? g[i] : 0u)];
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) c[i] = coarse_of(r[i], g[i] < (uint64_t)N, cshift, cnt);
 #pragma unroll
         for (int i = 0; i < EMIT_ITEMS; ++i) {
             const int64_t k = base + i * 256;
             if (k < N) {
-                const uint32_t g = order[vN + k];
-                const ushort4 c = coarse_rect(rect, vN, g, N, cshift, cnt);
-                crs[vN + k] = c;
+                crs[vN + k] = c[i];
                 if (HIST)
-                    for (int y = c.y; y < c.w; ++y)
-                        for (int x = c.x; x < c.z; ++x) atomicAdd(&hist[y * cw + x], 1u);
+                    for (int y = c[i].y; y < c[i].w; ++y)
+                        for (int x = c[i].x; x < c[i].z; ++x) atomicAdd(&hist[y * cw + x], 1u);
             }
         }
     }

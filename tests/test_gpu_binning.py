@@ -20,6 +20,9 @@ CASES = {
     "direct_1080p": dict(name="small", seed=21, n=6000, views=3, width=1920, height=1080),
     # 33 x 9 = 297 coarse bins per view: general path
     "general_wide": dict(name="small", seed=22, n=3000, views=2, width=4200, height=1100),
+    # 163 x 38 tiles -> 21 x 5 = 105 coarse bins per view: direct placement
+    # with 8-byte coarse rectangles (more than 16 bins across)
+    "direct_wide": dict(name="small", seed=24, n=4000, views=2, width=2600, height=600),
     # ragged tiles and bins, many Gaussians per bin
     "direct_dense": dict(name="medium", seed=23, n=40000, views=4, width=420, height=300),
 }
