@@ -228,8 +228,8 @@ __global__ void __launch_bounds__(64) k_raster_bwd(RasterArgs a, GridPack gp, co
     // transmittance, and dL/dC itself.  Every channel enters dL/dalpha only
     // through that dot product, so one sum scan per step replaces three.
     __shared__ float2 RT[256];   // g . remaining colour, T
-    // dL/dC per channel: three word arrays keep the wave's LDS at 8 KB (five
-    // waves per SIMD; a float4 array would hold a dead word per pixel)
+    // dL/dC per channel: three word arrays keep the wave's LDS at 6 KB (26
+    // waves per CU; a float4 array would hold a dead word per pixel)
     __shared__ float GFr[256], GFg[256], GFb[256];
     if (*a.overflow) return;
     const int64_t b = blockIdx.x;
