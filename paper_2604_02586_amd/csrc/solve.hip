@@ -312,7 +312,7 @@ struct RecordViews {
 
 // Solved views whose Sigma' the DLT loop keeps in LDS for the covariance
 // loop (views past these are solved again there): 20 x 3 floats x 256
-// threads = 60 KB per block, so the two blocks a CU holds (252 VGPRs) fit.
+// threads = 60 KB per block, so the two blocks a CU holds (256 VGPRs) fit.
 constexpr int TRI_COV_SLOTS = 20;
 
 // The full multi-view update of Gaussian g from the per-view results of
